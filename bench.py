@@ -1,0 +1,193 @@
+"""Benchmark: randomized CP solves per second on one MI355X.
+
+One step = one whole decomposition (rcp_decompose): the randomized range
+finder on every mode with in-kernel Gaussian test matrices, q power
+iterations, the chained mode products down to the core, CP-ALS on the core
+and the back-projection, from X resident in HBM to (lambda, A_n) in HBM.
+
+Default workload (rcp400): a dense 400 x 400 x 400 float32 tensor, rank 20
+with mode-0 column norms log-uniform in [1, 100], noise 0.05 rms; k = 20,
+p = 10, q = 2, 100 ALS sweeps.
+
+Prints one JSON line.  Besides the throughput it reports, for the kernel
+class that takes the most time, the achieved algorithmic rate against the
+MI355X peak (HIP events around that kernel's launches on the plan's stream),
+every kernel class's totals, and the CPU oracle timed on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+if HERE not in sys.path:
+    sys.path.insert(0, HERE)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP64_VALU_TFLOPS = 78.6
+
+STREAMING = ("sketch", "power", "contract_in", "contract_out")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rcp400")
+    ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="CPU oracle sample budget (0 disables the cpu_baseline leg)")
+    ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
+                    help="HBM traffic per launch measured with rocprofv3 counters")
+    return ap.parse_args()
+
+
+def cpu_baseline(X, cfg, budget_s):
+    """The float64 oracle, unmodified, on this host: whole solves of the same
+    workload until the budget is spent (at least one)."""
+    import numpy as np
+    from oracle import rcp
+    cores = len(os.sched_getaffinity(0))
+    X64 = X.astype(np.float64)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        rcp.rcp_als(X64, cfg["k"], cfg["p"], cfg["q"], cfg["iters"], 0.0, cfg["seed"])
+        n += 1
+        if time.perf_counter() - t0 >= budget_s or n >= 20:
+            break
+    dt = time.perf_counter() - t0
+    threads = os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS")
+    return {"value": n / dt, "unit": "solves/s",
+            "cores": int(threads) if threads and threads.isdigit() else cores,
+            "kind": "oracle",
+            "sample": f"{n} whole solve(s) of the same workload in float64 NumPy/SciPy ({dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1703_09074_amd as rcpgpu
+    from paper_1703_09074_amd import synth
+
+    cfg = dict(synth.WORKLOADS[args.workload])
+    w = synth.make(args.workload)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    X = torch.from_numpy(w.X).to(dev)
+    dims = list(w.X.shape)
+    plan = rcpgpu.Plan(dims, cfg["k"], cfg["p"], cfg["q"], cfg["iters"], 0.0, cfg["seed"],
+                       device=dev)
+    A = [torch.empty((d, cfg["k"]), dtype=torch.float32, device=dev) for d in dims]
+    lam = torch.empty((cfg["k"],), dtype=torch.float32, device=dev)
+    info = plan._info_buffer()
+
+    for _ in range(args.warmup):
+        plan.decompose_into(X, A, lam, info)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.decompose_into(X, A, lam, info)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ms_per_step = ms / args.steps
+    value = 1000.0 / ms_per_step
+    res = rcpgpu.Plan.read_info(info)
+
+    # per-kernel timing (separate pass with an event pair around every launch)
+    plan.profile(True)
+    for _ in range(args.profile_steps):
+        plan.decompose_into(X, A, lam, info)
+    torch.cuda.synchronize()
+    kern = plan.profile_read()
+    plan.profile(False)
+    for v in kern.values():
+        v["ms_per_launch"] = v["ms"] / v["launches"]
+        v["bytes_per_launch"] = v["bytes"] / v["launches"]
+        v["flops_per_launch"] = v["flops"] / v["launches"]
+        v["ms_per_step"] = v["ms"] / args.profile_steps
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    d = kern[dom]
+    if dom in STREAMING or dom == "reduce":
+        ach = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS}
+    else:
+        ach = d["flops"] / (d["ms"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VALU_TFLOPS}
+    roof["kernel"] = dom
+    roof["traffic"] = None
+    if os.path.exists(args.traffic_json):
+        try:
+            tj = json.load(open(args.traffic_json))
+            ent = tj.get(args.workload, {}).get(dom)
+            if ent and ent.get("source_hash") == _source_hash():
+                roof["traffic"] = ent["bytes_per_launch"]
+        except (ValueError, OSError):
+            pass
+    sb = sum(kern[k]["bytes"] for k in STREAMING if k in kern)
+    sf = sum(kern[k]["flops"] for k in STREAMING if k in kern)
+    sm = sum(kern[k]["ms"] for k in STREAMING if k in kern)
+    sketch_ttm = {"gbps": sb / (sm * 1e-3) / 1e9, "tflops": sf / (sm * 1e-3) / 1e12,
+                  "frac_hbm": sb / (sm * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                  "frac_fp32_mfma": sf / (sm * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS,
+                  "ms_per_step": sm / args.profile_steps} if sm > 0 else None
+
+    out = {
+        "metric": "rCP solves/sec + sketch/TTM TFLOP/s (% peak), mixed vs FP32 at equal rel. error",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dims": dims, "R": cfg["R"], "k": cfg["k"],
+                   "p": cfg["p"], "q": cfg["q"], "als_iters": cfg["iters"],
+                   "noise": cfg["noise"], "factors": cfg["kind"], "scheme": "sequential",
+                   "precision": "fp32"},
+        "rel_err": res["rel_err"],
+        "wall_s": wall,
+        "roofline": roof,
+        "sketch_ttm": sketch_ttm,
+        "kernels": kern,
+        "cpu_baseline": None,
+    }
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(w.X, cfg, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def _source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "paper_1703_09074_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

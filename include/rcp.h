@@ -1,0 +1,215 @@
+/*
+ * rcp.h -- C interface of librcp, randomized CP decomposition on AMD MI355X
+ * (gfx950).
+ *
+ * Method: Erichson, Manohar, Brunton, Kutz, "Randomized CP Tensor
+ * Decomposition".  Section 3.1 / Algorithm 1 (randomized tensor
+ * compression), Section 3.2.1 / Algorithm 2 (CP-ALS on the compressed
+ * tensor, back-projection eq. qbs), Section 3.3 (fit and stopping rule).
+ *
+ * Conventions shared by every entry point
+ *   - Tensors are dense, float32, C order (last index fastest).  Matrices are
+ *     row-major.  Mode indices are 0-based.
+ *   - Every tensor / matrix pointer is a DEVICE pointer unless stated.
+ *     Arrays of pointers (``float* const* A``) are HOST arrays of device
+ *     pointers, one per mode.
+ *   - l_n = min(k + p, I_n) is the sketch width of mode n; the core has
+ *     dims l_0 x ... x l_{N-1}; R = k is the CP rank.
+ *   - The library never allocates device memory.  The caller provides one
+ *     workspace buffer (size from rcp_workspace_size) and every input and
+ *     output buffer; the library owns only the host-side plan object.
+ *   - Calls only enqueue work on the HIP stream given to rcp_init and return
+ *     without synchronising.  The returned status covers argument checking
+ *     and launch errors only.  Numeric outcomes (Cholesky fallback taken, a
+ *     non-finite fit) are written to the device-side rcp_als_info.
+ *   - A plan is not thread-safe; distinct plans are independent.  Calls on
+ *     one plan must not overlap (they share the workspace), which holds
+ *     automatically when they are issued on the plan's stream.
+ *   - The library never aborts, throws across this interface or prints.
+ */
+#ifndef RCP_H_
+#define RCP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rcp_status {
+    RCP_OK = 0,
+    RCP_ERR_INVALID_ARG = 1,   /* bad size, null or misaligned pointer, aliasing */
+    RCP_ERR_WORKSPACE = 2,     /* workspace missing or too small */
+    RCP_ERR_HIP = 3,           /* a HIP runtime call or kernel launch failed */
+    RCP_ERR_NUMERIC = 4,       /* reserved for synchronous numeric failures */
+    RCP_ERR_UNSUPPORTED = 5    /* valid request this build does not implement */
+} rcp_status;
+
+/* rcp_problem.precision: operand precision of the streaming contractions. */
+enum { RCP_PREC_FP32 = 0, RCP_PREC_BF16 = 1, RCP_PREC_FP16 = 2 };
+
+/* rcp_problem.scheme (Section 3.1): SEQUENTIAL sketches mode n on the tensor
+ * already compressed in modes < n, as Algorithm 1 does (it replaces X by
+ * B_n after each mode); INDEPENDENT takes every basis from X itself and
+ * forms the core by chained mode products afterwards. */
+enum { RCP_SCHEME_SEQUENTIAL = 0, RCP_SCHEME_INDEPENDENT = 1 };
+
+/* Device-side status bits in rcp_als_info.status. */
+enum {
+    RCP_INFO_PINV_FALLBACK = 1,  /* a Gram matrix was singular: pseudo-inverse used */
+    RCP_INFO_NONFINITE = 2,      /* the fit became NaN/Inf */
+    RCP_INFO_EIG_NOT_CONVERGED = 4
+};
+
+#define RCP_MAX_NDIM 8     /* tensor order N in [2, 8] */
+#define RCP_MAX_L 64       /* k + p <= 64 */
+#define RCP_MAX_RANK 64    /* k <= 64 */
+
+/* The problem, as Algorithm 1 and 2 state it: an N-way tensor, target rank
+ * k (= CP rank R), oversampling p (Algorithm 1 step 3, l = k + p) and q
+ * normalised power iterations (Algorithm 1 steps 7-11). */
+typedef struct rcp_problem {
+    int32_t ndim;                    /* N, 2..RCP_MAX_NDIM */
+    int32_t k;                       /* target rank = CP rank R, >= 1 */
+    int32_t p;                       /* oversampling, >= 0, k + p <= RCP_MAX_L */
+    int32_t q;                       /* power iterations, >= 0 */
+    int64_t dims[RCP_MAX_NDIM];      /* I_0 .. I_{N-1}, each >= 1 */
+    int32_t max_iters;               /* ALS sweeps, >= 1 */
+    int32_t precision;               /* RCP_PREC_* */
+    int32_t scheme;                  /* RCP_SCHEME_* */
+    int32_t reserved;                /* must be 0 */
+    double tol;                      /* stop when |rho_j - rho_{j-1}| < tol (j >= 2); 0 = run max_iters */
+    uint64_t seed;                   /* seed of the Gaussian test matrices */
+} rcp_problem;
+
+/* Written on the device by rcp_als / rcp_decompose. */
+typedef struct rcp_als_info {
+    int32_t iters;                   /* sweeps run */
+    int32_t status;                  /* RCP_INFO_* bits */
+    double rho;                      /* fit of Section 3.3 after the last sweep */
+    double rel_err;                  /* sqrt(max(0, 1 - rho)) = ||X - Xhat|| / ||X|| */
+    double normX2;                   /* ||X||_F^2 used for the fit */
+} rcp_als_info;
+
+typedef struct rcp_plan_t* rcp_plan;
+
+/* Bytes of device workspace a plan for *prob needs (host only, no GPU call).
+ * Returns RCP_ERR_INVALID_ARG for an invalid problem (see rcp_init). */
+rcp_status rcp_workspace_size(const rcp_problem* prob, size_t* bytes);
+
+/* Validates *prob, binds the workspace (device pointer, 256-byte aligned,
+ * >= rcp_workspace_size bytes) and the HIP stream (hipStream_t passed as
+ * void*; NULL = the null stream) and returns a plan in *plan.
+ * RCP_ERR_INVALID_ARG: ndim outside [2, 8], a dim < 1, k < 1, p < 0, q < 0,
+ *   k + p > 64, k > l_n for some n, max_iters < 1, tol < 0, unknown
+ *   precision/scheme, reserved != 0, or a null plan / problem pointer.
+ * RCP_ERR_WORKSPACE: null or too small workspace.
+ * RCP_ERR_UNSUPPORTED: a precision other than FP32 in this build. */
+rcp_status rcp_init(rcp_plan* plan, const rcp_problem* prob, void* workspace,
+                    size_t workspace_bytes, void* hip_stream);
+
+/* Frees the host-side plan.  Does not touch the workspace. */
+rcp_status rcp_destroy(rcp_plan plan);
+
+/* Randomised range finder of one mode (Algorithm 1 steps 3-12).
+ * T: current tensor with dims cur_dims[0..N-1] (host array); mode n; the
+ * sketch width is l = min(k + p, cur_dims[n]).  Writes the orthonormal
+ * basis Q (cur_dims[n] x l, row-major, diag(R) > 0 convention) built from
+ * Y = T_(n) Omega_n and q normalised power iterations.  Omega_n is the
+ * counter-based Gaussian matrix of (seed, mode n, batch 0).
+ * cur_dims may differ from the plan's dims (the sequential scheme passes a
+ * partly compressed tensor) but no dim may exceed the plan's dims. */
+rcp_status rcp_sketch(rcp_plan plan, const float* T, const int64_t* cur_dims,
+                      int32_t mode, float* Q);
+
+/* Mode-n projection T_out = T x_n Q^T (Algorithm 1 step 13; the n-mode
+ * product of Definition 1).  Q is cur_dims[n] x l row-major, l = its
+ * width as rcp_sketch defines it; T_out has dims cur_dims with mode n
+ * replaced by l.  T and T_out must not overlap. */
+rcp_status rcp_compress(rcp_plan plan, const float* T, const int64_t* cur_dims,
+                        int32_t mode, const float* Q, float* T_out);
+
+/* ||X||_F^2 in float64 of count float32 values (written to *out, device). */
+rcp_status rcp_norm2(rcp_plan plan, const float* X, int64_t count, double* out);
+
+/* CP-ALS on the core (Algorithm 2 steps 2-11).  core: l_0 x ... x l_{N-1}
+ * (the plan's sketch widths).  At[n]: l_n x R outputs (row-major); lambda:
+ * R outputs; info: device rcp_als_info.  normX2: device pointer to ||X||^2
+ * of the uncompressed tensor for the fit (NULL: use ||core||^2).
+ * Initialisation: leading R eigenvectors of B_(n) B_(n)^T for modes
+ * 1..N-1 (Algorithm 2 step 2).  Sweeps: for n = 0..N-1, Ã_n = B_(n)
+ * KR(Ã_{m!=n}) (*_{m!=n} Ã_m^T Ã_m)^+, column-normalised, lambda from the
+ * last mode (steps 4-10).  Stops after max_iters sweeps, or earlier when
+ * tol > 0 and the fit changes by less than tol (step 11). */
+rcp_status rcp_als(rcp_plan plan, const float* core, float* const* At,
+                   float* lambda, const double* normX2, rcp_als_info* info);
+
+/* Back-projection A_n = Q_n Ã_n (eq. qbs, Algorithm 2 step 12) and the
+ * renormalisation of step 13: unit columns, norms folded into lambda,
+ * components sorted by lambda (descending), the largest-magnitude entry of
+ * each column of modes 0..N-2 made positive with the sign moved to mode
+ * N-1.  Q[n]: I_n x l_n, At[n]: l_n x R, lambda_in: R; outputs A[n]:
+ * I_n x R and lambda_out: R (may equal lambda_in). */
+rcp_status rcp_expand(rcp_plan plan, const float* const* Q, const float* const* At,
+                      const float* lambda_in, float* const* A, float* lambda_out);
+
+/* The whole path on X (dims = the plan's dims): ||X||^2, the compression of
+ * Algorithm 1 (scheme from the plan), CP-ALS on the core and the
+ * back-projection.  Outputs A[n] (I_n x R), lambda (R) and info (device).
+ * The bases and the core stay in the workspace (rcp_get_bases / rcp_get_core). */
+rcp_status rcp_decompose(rcp_plan plan, const float* X, float* const* A,
+                         float* lambda, rcp_als_info* info);
+
+/* Device pointers, inside the workspace, of the bases Q_n (I_n x l_n) and of
+ * the core (l_0 x ... x l_{N-1}) that the last rcp_decompose produced.
+ * Q: host array of N pointers to fill.  core_dims: host array of N (may be NULL). */
+rcp_status rcp_get_bases(rcp_plan plan, float** Q);
+rcp_status rcp_get_core(rcp_plan plan, float** core, int64_t* core_dims);
+
+/* Rows [row0, row0 + nrows) of the Gaussian test matrix Omega of a mode,
+ * width l <= 64 (nrows x l row-major, device).  Omega[j, c] is a pure
+ * function of (seed, mode, batch 0, j, c): Philox4x32-10 on the counter
+ * (j mod 2^32, j >> 32, c / 4, mode) with key (seed mod 2^32, seed >> 32),
+ * uniforms ((x >> 8) + 1) 2^-24, Box-Muller on the pairs (u0,u1), (u2,u3). */
+rcp_status rcp_debug_omega(rcp_plan plan, int32_t mode, int64_t row0, int64_t nrows,
+                           int32_t l, float* omega);
+
+/* Per-kernel timing of a plan's launches (for roofline reporting).
+ * rcp_profile(plan, 1) starts recording a HIP event pair around every kernel
+ * launch the plan makes (at most 4096 launches are recorded; later ones are
+ * counted but not timed), with the algorithmic bytes moved and flops done by
+ * each launch, computed on the host from its shapes: for the streaming
+ * kernels, every element of the current tensor read once (4 B), the outputs
+ * written once, and 2 flops per multiply-add of the contraction.
+ * rcp_profile(plan, 0) stops recording and clears the totals.
+ * rcp_profile_read waits for the recorded events (host blocking) and returns
+ * the totals of one kernel class (RCP_KERNEL_*): launches, milliseconds,
+ * bytes and flops.  Any pointer may be NULL. */
+enum {
+    RCP_KERNEL_SKETCH = 0,       /* Y = T_(n) Omega, Omega generated in-kernel */
+    RCP_KERNEL_POWER = 1,        /* Y = T_(n) (T_(n)^T Q), fused single pass */
+    RCP_KERNEL_CONTRACT_IN = 2,  /* T x_n Q^T (compression, or stored Z) */
+    RCP_KERNEL_CONTRACT_OUT = 3, /* Y = T_(n) Z with a stored Z */
+    RCP_KERNEL_REDUCE = 4,       /* partial-sum reduction */
+    RCP_KERNEL_QR = 5,           /* Householder QR of a sketch */
+    RCP_KERNEL_ALS = 6,          /* CP-ALS on the core */
+    RCP_KERNEL_EXPAND = 7,       /* back-projection and renormalisation */
+    RCP_KERNEL_OTHER = 8,
+    RCP_KERNEL_COUNT = 9
+};
+rcp_status rcp_profile(rcp_plan plan, int32_t enable);
+rcp_status rcp_profile_read(rcp_plan plan, int32_t kernel_class, int64_t* launches, double* ms,
+                            double* bytes, double* flops);
+
+/* Static description of a status code. */
+const char* rcp_status_string(rcp_status status);
+
+/* Library version string. */
+const char* rcp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RCP_H_ */

@@ -1,0 +1,234 @@
+"""Randomized CP decomposition on AMD MI355X (gfx950).
+
+Python front end of librcp (include/rcp.h).  PyTorch supplies device memory
+and the HIP stream; every step of the computation runs in the library's HIP
+kernels.  There is no CPU fallback: without the built library (or without a
+GPU) these functions raise.
+
+    lam, factors, info = decompose(X, k=20, p=10, q=2, iters=100)
+
+X is a C-order float32 CUDA tensor; factors[n] is I_n x k, lam has k
+entries sorted descending (Algorithm 2 of Erichson et al., "Randomized CP
+Tensor Decomposition": randomized compression, CP-ALS on the core,
+back-projection).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+from . import _lib
+
+__all__ = ["Plan", "decompose", "sketch_width", "library_path"]
+
+library_path = _lib.LIB_PATH
+
+
+def sketch_width(k: int, p: int, I: int) -> int:
+    return min(int(k) + int(p), int(I))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _f32(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 tensor")
+    return t
+
+
+class Plan:
+    """A plan: the problem, its device workspace and the stream it runs on.
+
+    All methods enqueue on the current HIP stream of ``device`` at plan
+    creation and return without synchronising.
+    """
+
+    def __init__(self, dims: Sequence[int], k: int, p: int = 10, q: int = 2,
+                 max_iters: int = 50, tol: float = 0.0, seed: int = 0,
+                 scheme: str = "sequential", precision: str = "fp32", device="cuda"):
+        torch = _torch()
+        self.lib = _lib.load()
+        self.dims = [int(d) for d in dims]
+        self.N = len(self.dims)
+        self.k = int(k)
+        self.R = int(k)
+        self.p = int(p)
+        self.q = int(q)
+        self.l = [sketch_width(k, p, d) for d in self.dims]
+        self.device = torch.device(device)
+        self.problem = _lib.make_problem(self.dims, k, p, q, max_iters, tol, seed, precision, scheme)
+        nbytes = ctypes.c_size_t(0)
+        _lib.check(self.lib.rcp_workspace_size(ctypes.byref(self.problem), ctypes.byref(nbytes)),
+                   "rcp_workspace_size")
+        self.workspace = torch.empty(max(256, nbytes.value), dtype=torch.uint8, device=self.device)
+        self.stream = _stream_handle(torch, self.device)
+        handle = ctypes.c_void_p(0)
+        _lib.check(self.lib.rcp_init(ctypes.byref(handle), ctypes.byref(self.problem),
+                                     ctypes.c_void_p(self.workspace.data_ptr()),
+                                     ctypes.c_size_t(self.workspace.numel()), self.stream),
+                   "rcp_init")
+        self.handle = handle
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.rcp_destroy(h)
+            self.handle = None
+
+    # -- helpers ---------------------------------------------------------------
+    def _empty(self, shape, dtype=None):
+        torch = _torch()
+        return torch.empty(shape, dtype=dtype or torch.float32, device=self.device)
+
+    def _info_buffer(self):
+        torch = _torch()
+        return torch.zeros(ctypes.sizeof(_lib.AlsInfo), dtype=torch.uint8, device=self.device)
+
+    @staticmethod
+    def read_info(buf) -> dict:
+        raw = bytes(buf.cpu().numpy().tobytes())
+        info = _lib.AlsInfo.from_buffer_copy(raw)
+        return dict(iters=info.iters, status=info.status, rho=info.rho, rel_err=info.rel_err,
+                    normX2=info.normX2)
+
+    # -- entry points ------------------------------------------------------------
+    def sketch(self, T, mode: int, cur_dims: Optional[Sequence[int]] = None):
+        """Orthonormal basis Q_n (I_n x l) of mode ``mode`` (Algorithm 1 steps 3-12)."""
+        _f32(T, "T")
+        cur = list(T.shape) if cur_dims is None else [int(d) for d in cur_dims]
+        l = sketch_width(self.k, self.p, cur[mode])
+        Q = self._empty((cur[mode], l))
+        _lib.check(self.lib.rcp_sketch(self.handle, ctypes.c_void_p(T.data_ptr()),
+                                       _lib.dims_array(cur), int(mode),
+                                       ctypes.c_void_p(Q.data_ptr())), "rcp_sketch")
+        return Q
+
+    def compress(self, T, mode: int, Q):
+        """T x_mode Q^T (Algorithm 1 step 13)."""
+        _f32(T, "T")
+        _f32(Q, "Q")
+        cur = list(T.shape)
+        out_shape = list(cur)
+        out_shape[mode] = Q.shape[1]
+        out = self._empty(out_shape)
+        _lib.check(self.lib.rcp_compress(self.handle, ctypes.c_void_p(T.data_ptr()),
+                                         _lib.dims_array(cur), int(mode),
+                                         ctypes.c_void_p(Q.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr())), "rcp_compress")
+        return out
+
+    def norm2(self, X):
+        torch = _torch()
+        _f32(X, "X")
+        out = torch.empty(1, dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.rcp_norm2(self.handle, ctypes.c_void_p(X.data_ptr()), X.numel(),
+                                      ctypes.c_void_p(out.data_ptr())), "rcp_norm2")
+        return out
+
+    def als(self, core, normX2=None):
+        """CP-ALS on the core (Algorithm 2 steps 2-11): (factors, lambda, info buffer)."""
+        _f32(core, "core")
+        At = [self._empty((self.l[n], self.R)) for n in range(self.N)]
+        lam = self._empty((self.R,))
+        info = self._info_buffer()
+        nptr = ctypes.c_void_p(normX2.data_ptr()) if normX2 is not None else ctypes.c_void_p(0)
+        _lib.check(self.lib.rcp_als(self.handle, ctypes.c_void_p(core.data_ptr()),
+                                    _lib.ptr_array([a.data_ptr() for a in At]),
+                                    ctypes.c_void_p(lam.data_ptr()), nptr,
+                                    ctypes.c_void_p(info.data_ptr())), "rcp_als")
+        return At, lam, info
+
+    def expand(self, Q: List, At: List, lam):
+        """A_n = Q_n Ã_n and the final renormalisation (eq. qbs, Algorithm 2 steps 12-13)."""
+        A = [self._empty((self.dims[n], self.R)) for n in range(self.N)]
+        lam_out = self._empty((self.R,))
+        _lib.check(self.lib.rcp_expand(self.handle, _lib.ptr_array([q.data_ptr() for q in Q]),
+                                       _lib.ptr_array([a.data_ptr() for a in At]),
+                                       ctypes.c_void_p(lam.data_ptr()),
+                                       _lib.ptr_array([a.data_ptr() for a in A]),
+                                       ctypes.c_void_p(lam_out.data_ptr())), "rcp_expand")
+        return A, lam_out
+
+    def decompose_into(self, X, A: List, lam, info) -> None:
+        """The whole path into preallocated outputs (no allocation)."""
+        _lib.check(self.lib.rcp_decompose(self.handle, ctypes.c_void_p(X.data_ptr()),
+                                          _lib.ptr_array([a.data_ptr() for a in A]),
+                                          ctypes.c_void_p(lam.data_ptr()),
+                                          ctypes.c_void_p(info.data_ptr())), "rcp_decompose")
+
+    def decompose(self, X):
+        """(lambda, [A_n], info buffer) for the float32 CUDA tensor X."""
+        _f32(X, "X")
+        if list(X.shape) != self.dims:
+            raise ValueError(f"X has shape {list(X.shape)}, plan expects {self.dims}")
+        A = [self._empty((self.dims[n], self.R)) for n in range(self.N)]
+        lam = self._empty((self.R,))
+        info = self._info_buffer()
+        self.decompose_into(X, A, lam, info)
+        return lam, A, info
+
+    def _workspace_view(self, ptr, shape):
+        """float32 view of a region of the plan's workspace."""
+        n = 1
+        for s in shape:
+            n *= int(s)
+        off = int(ptr) - self.workspace.data_ptr()
+        if off < 0 or off % 4 or off + 4 * n > self.workspace.numel():
+            raise RuntimeError("library returned a pointer outside the workspace")
+        return self.workspace[off:off + 4 * n].view(_torch().float32).view(*shape)
+
+    def bases(self):
+        """Views of the bases Q_n from the last decompose (valid until the next call)."""
+        arr = (ctypes.c_void_p * self.N)()
+        _lib.check(self.lib.rcp_get_bases(self.handle, arr), "rcp_get_bases")
+        return [self._workspace_view(arr[n], (self.dims[n], self.l[n])) for n in range(self.N)]
+
+    def core(self):
+        """View of the core from the last decompose (valid until the next call)."""
+        p = ctypes.c_void_p(0)
+        dims = (ctypes.c_int64 * _lib.RCP_MAX_NDIM)()
+        _lib.check(self.lib.rcp_get_core(self.handle, ctypes.byref(p), dims), "rcp_get_core")
+        return self._workspace_view(p.value, tuple(dims[n] for n in range(self.N)))
+
+    def profile(self, enable: bool) -> None:
+        """Start (and clear) or stop per-kernel event timing of this plan's launches."""
+        _lib.check(self.lib.rcp_profile(self.handle, 1 if enable else 0), "rcp_profile")
+
+    def profile_read(self) -> dict:
+        """{kernel class: dict(launches, ms, bytes, flops)} of the recorded launches."""
+        out = {}
+        for cls, name in enumerate(_lib.KERNEL_CLASSES):
+            n = ctypes.c_int64(0)
+            ms = ctypes.c_double(0)
+            b = ctypes.c_double(0)
+            f = ctypes.c_double(0)
+            _lib.check(self.lib.rcp_profile_read(self.handle, cls, ctypes.byref(n), ctypes.byref(ms),
+                                                 ctypes.byref(b), ctypes.byref(f)),
+                       "rcp_profile_read")
+            if n.value:
+                out[name] = dict(launches=n.value, ms=ms.value, bytes=b.value, flops=f.value)
+        return out
+
+    def omega(self, mode: int, row0: int, nrows: int, l: int):
+        out = self._empty((nrows, l))
+        _lib.check(self.lib.rcp_debug_omega(self.handle, int(mode), int(row0), int(nrows), int(l),
+                                            ctypes.c_void_p(out.data_ptr())), "rcp_debug_omega")
+        return out
+
+
+def decompose(X, k: int, p: int = 10, q: int = 2, iters: int = 50, tol: float = 0.0,
+              seed: int = 0, scheme: str = "sequential", precision: str = "fp32"):
+    """Randomized CP of X (Algorithm 2).  Returns (lambda, [A_n], info dict)."""
+    plan = Plan(list(X.shape), k, p, q, iters, tol, seed, scheme, precision, device=X.device)
+    lam, A, info = plan.decompose(X)
+    return lam, A, Plan.read_info(info)

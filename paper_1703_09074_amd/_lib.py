@@ -1,0 +1,147 @@
+"""ctypes declarations of librcp's C interface (include/rcp.h).
+
+Argument marshalling only.  Loading fails loudly when the HIP library has
+not been built: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librcp.so")
+
+RCP_MAX_NDIM = 8
+RCP_MAX_L = 64
+RCP_MAX_RANK = 64
+
+RCP_OK = 0
+RCP_ERR_INVALID_ARG = 1
+RCP_ERR_WORKSPACE = 2
+RCP_ERR_HIP = 3
+RCP_ERR_NUMERIC = 4
+RCP_ERR_UNSUPPORTED = 5
+
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
+KERNEL_CLASSES = ["sketch", "power", "contract_in", "contract_out", "reduce", "qr", "als",
+                  "expand", "other"]
+SCHEMES = {"sequential": 0, "independent": 1}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("k", ctypes.c_int32),
+        ("p", ctypes.c_int32),
+        ("q", ctypes.c_int32),
+        ("dims", ctypes.c_int64 * RCP_MAX_NDIM),
+        ("max_iters", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class AlsInfo(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("rho", ctypes.c_double),
+        ("rel_err", ctypes.c_double),
+        ("normX2", ctypes.c_double),
+    ]
+
+
+_vp = ctypes.c_void_p
+_st = ctypes.c_int
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "rcp_workspace_size": (_st, [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)]),
+    "rcp_init": (_st, [ctypes.POINTER(_vp), ctypes.POINTER(Problem), _vp, ctypes.c_size_t, _vp]),
+    "rcp_destroy": (_st, [_vp]),
+    "rcp_sketch": (_st, [_vp, _vp, _i64p, ctypes.c_int32, _vp]),
+    "rcp_compress": (_st, [_vp, _vp, _i64p, ctypes.c_int32, _vp, _vp]),
+    "rcp_norm2": (_st, [_vp, _vp, ctypes.c_int64, _vp]),
+    "rcp_als": (_st, [_vp, _vp, ctypes.POINTER(_vp), _vp, _vp, _vp]),
+    "rcp_expand": (_st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, ctypes.POINTER(_vp), _vp]),
+    "rcp_decompose": (_st, [_vp, _vp, ctypes.POINTER(_vp), _vp, _vp]),
+    "rcp_get_bases": (_st, [_vp, ctypes.POINTER(_vp)]),
+    "rcp_get_core": (_st, [_vp, ctypes.POINTER(_vp), _i64p]),
+    "rcp_debug_omega": (_st, [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _vp]),
+    "rcp_profile": (_st, [_vp, ctypes.c_int32]),
+    "rcp_profile_read": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_double)]),
+    "rcp_status_string": (ctypes.c_char_p, [_st]),
+    "rcp_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load librcp.so (once) and declare every entry point."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    try:  # share PyTorch's HIP runtime (same SONAME) when PyTorch is present
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"librcp is not built ({path} missing); run `python -m paper_1703_09074_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class RcpError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = load().rcp_status_string(status).decode()
+        super().__init__(f"{where}: {msg}")
+        self.status = status
+
+
+def check(status: int, where: str) -> None:
+    if status != RCP_OK:
+        raise RcpError(status, where)
+
+
+def ptr_array(ptrs):
+    arr = (_vp * len(ptrs))()
+    for i, p in enumerate(ptrs):
+        arr[i] = p
+    return arr
+
+
+def dims_array(dims):
+    arr = (ctypes.c_int64 * RCP_MAX_NDIM)()
+    for i, d in enumerate(dims):
+        arr[i] = int(d)
+    return arr
+
+
+def make_problem(dims, k, p, q, max_iters, tol, seed, precision="fp32", scheme="sequential"):
+    prob = Problem()
+    prob.ndim = len(dims)
+    prob.k = int(k)
+    prob.p = int(p)
+    prob.q = int(q)
+    for i, d in enumerate(dims):
+        prob.dims[i] = int(d)
+    prob.max_iters = int(max_iters)
+    prob.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    prob.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+    prob.reserved = 0
+    prob.tol = float(tol)
+    prob.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    return prob

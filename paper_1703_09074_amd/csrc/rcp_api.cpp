@@ -1,0 +1,586 @@
+// librcp host library: argument checking, workspace layout, launch
+// sequencing.  Every entry point only enqueues work on the plan's stream.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/rcp.h"
+#include "rcp_kernels.h"
+
+using namespace rcp;
+
+namespace {
+
+constexpr int kPmax = 512;            // max workgroups of a streaming pass (partial buffers)
+constexpr size_t kAlign = 256;
+constexpr size_t kLdsBytes = 160 * 1024;   // LDS per workgroup on gfx950
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int lp_of(int l) { return (l + 15) / 16 * 16; }
+
+struct Layout {
+    int N, R;
+    int64_t dims[RCP_MAX_NDIM];
+    int l[RCP_MAX_NDIM];
+    int LP[RCP_MAX_NDIM];
+    int64_t Imax;
+    int LPmax;
+    // offsets (bytes)
+    size_t part, y64, qt, sq, norm, qb[RCP_MAX_NDIM], tb[2], zbuf, als, at[RCP_MAX_NDIM], lam,
+        raw, total;
+    size_t part_elems, tb_elems[2], zbuf_elems, als_doubles;
+    int64_t core_dims[RCP_MAX_NDIM];
+};
+
+bool valid_problem(const rcp_problem* p) {
+    if (p == nullptr) return false;
+    if (p->ndim < 2 || p->ndim > RCP_MAX_NDIM) return false;
+    if (p->k < 1 || p->p < 0 || p->q < 0) return false;
+    if (p->k > RCP_MAX_RANK || p->k + p->p > RCP_MAX_L) return false;
+    if (p->max_iters < 1 || !(p->tol >= 0.0)) return false;
+    if (p->scheme != RCP_SCHEME_SEQUENTIAL && p->scheme != RCP_SCHEME_INDEPENDENT) return false;
+    if (p->precision != RCP_PREC_FP32 && p->precision != RCP_PREC_BF16 &&
+        p->precision != RCP_PREC_FP16)
+        return false;
+    if (p->reserved != 0) return false;
+    for (int n = 0; n < p->ndim; ++n) {
+        if (p->dims[n] < 1 || p->dims[n] > (int64_t)1 << 40) return false;
+        const int64_t l = std::min<int64_t>(p->k + p->p, p->dims[n]);
+        if (p->k > l) return false;
+    }
+    // total element count must stay well inside int64
+    double S = 1.0;
+    for (int n = 0; n < p->ndim; ++n) S *= (double)p->dims[n];
+    if (S > 4.0e12) return false;
+    return true;
+}
+
+// Workspace layout; identical for rcp_workspace_size and rcp_init.
+Layout make_layout(const rcp_problem* p) {
+    Layout L{};
+    L.N = p->ndim;
+    L.R = p->k;
+    L.Imax = 1;
+    L.LPmax = 16;
+    for (int n = 0; n < L.N; ++n) {
+        L.dims[n] = p->dims[n];
+        L.l[n] = (int)std::min<int64_t>(p->k + p->p, p->dims[n]);
+        L.LP[n] = lp_of(L.l[n]);
+        L.Imax = std::max(L.Imax, p->dims[n]);
+        L.LPmax = std::max(L.LPmax, L.LP[n]);
+    }
+    // partials: any sketch on a tensor with dims <= the plan's dims
+    size_t part = 0;
+    for (int n = 0; n < L.N; ++n)
+        part = std::max(part, (size_t)kPmax * (size_t)L.dims[n] * (size_t)L.LP[n]);
+    L.part_elems = part;
+    // compressed tensors: output of mode n goes to buffer n % 2
+    int64_t cur[RCP_MAX_NDIM];
+    for (int n = 0; n < L.N; ++n) cur[n] = L.dims[n];
+    L.tb_elems[0] = L.tb_elems[1] = 0;
+    for (int n = 0; n < L.N; ++n) {
+        cur[n] = L.l[n];
+        int64_t s = 1;
+        for (int m = 0; m < L.N; ++m) s *= cur[m];
+        L.tb_elems[n % 2] = std::max(L.tb_elems[n % 2], (size_t)s);
+    }
+    for (int n = 0; n < L.N; ++n) L.core_dims[n] = L.l[n];
+    // stored Z for modes whose tile does not fit the fused power kernel
+    L.zbuf_elems = 0;
+    if (p->q > 0) {
+        int64_t S = 1;
+        for (int n = 0; n < L.N; ++n) S *= L.dims[n];
+        for (int n = 0; n < L.N; ++n) {
+            if (!power_fused_fits(L.dims[n], L.l[n], kLdsBytes))
+                L.zbuf_elems = std::max(L.zbuf_elems, (size_t)(S / L.dims[n]) * (size_t)L.LP[n]);
+        }
+    }
+    L.als_doubles = als_workspace_doubles(L.N, L.l, L.R);
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
+    L.part = take(L.part_elems * sizeof(float));
+    L.y64 = take((size_t)L.Imax * L.LPmax * sizeof(double));
+    L.qt = take((size_t)L.Imax * L.LPmax * sizeof(float));
+    int nib = 1;
+    for (int n = 0; n < L.N; ++n) nib = std::max(nib, contract_out_row_blocks(L.dims[n]));
+    L.sq = take((size_t)kPmax * nib * sizeof(double));
+    L.norm = take(64 * sizeof(double));
+    for (int n = 0; n < L.N; ++n) L.qb[n] = take((size_t)L.dims[n] * L.l[n] * sizeof(float));
+    L.tb[0] = take(L.tb_elems[0] * sizeof(float));
+    L.tb[1] = take(L.tb_elems[1] * sizeof(float));
+    L.zbuf = take(L.zbuf_elems * sizeof(float));
+    L.als = take(L.als_doubles * sizeof(double));
+    for (int n = 0; n < L.N; ++n) L.at[n] = take((size_t)L.l[n] * L.R * sizeof(float));
+    L.lam = take((size_t)L.R * sizeof(float));
+    size_t raw = 0;
+    for (int n = 0; n < L.N; ++n) raw += (size_t)L.dims[n] * L.R;
+    L.raw = take(raw * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+namespace {
+
+constexpr int kMaxProfiled = 4096;
+
+struct ProfRecord {
+    int cls;
+    double bytes, flops;
+};
+
+// Event pairs around every launch while profiling is on.
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> ev;            // 2 * kMaxProfiled
+    std::vector<ProfRecord> rec;
+    int64_t untimed[RCP_KERNEL_COUNT] = {};
+    void clear() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        rec.clear();
+        for (auto& u : untimed) u = 0;
+        on = false;
+    }
+};
+
+}  // namespace
+
+struct rcp_plan_t {
+    rcp_problem prob;
+    Layout L;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    int P;                 // workgroups per streaming pass
+    size_t smem_limit;
+    Profiler prof;
+    template <class T>
+    T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+rcp_status hip_status(hipError_t e) { return e == hipSuccess ? RCP_OK : RCP_ERR_HIP; }
+
+#define RCP_TRY(expr)                                       \
+    do {                                                    \
+        const hipError_t rcp_e_ = (expr);                   \
+        if (rcp_e_ != hipSuccess) return RCP_ERR_HIP;       \
+    } while (0)
+
+// Runs `launch` (which enqueues one kernel) between two recorded events when
+// profiling is on, with the launch's algorithmic bytes and flops.
+template <class F>
+hipError_t timed(rcp_plan_t* pl, int cls, double bytes, double flops, F&& launch) {
+    Profiler& pr = pl->prof;
+    if (!pr.on) return launch();
+    const size_t idx = pr.rec.size();
+    if (idx >= (size_t)kMaxProfiled) {
+        ++pr.untimed[cls];
+        return launch();
+    }
+    hipError_t e = hipEventRecord(pr.ev[2 * idx], pl->stream);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(pr.ev[2 * idx + 1], pl->stream);
+    if (e != hipSuccess) return e;
+    pr.rec.push_back(ProfRecord{cls, bytes, flops});
+    return hipSuccess;
+}
+
+bool valid_cur_dims(const rcp_plan_t* pl, const int64_t* cur) {
+    if (cur == nullptr) return false;
+    for (int n = 0; n < pl->L.N; ++n)
+        if (cur[n] < 1 || cur[n] > pl->L.dims[n]) return false;
+    return true;
+}
+
+int64_t count_of(const int64_t* d, int N) {
+    int64_t s = 1;
+    for (int n = 0; n < N; ++n) s *= d[n];
+    return s;
+}
+
+// Y (I x LP float64, in the workspace) <- partials
+rcp_status reduce_y(rcp_plan_t* pl, int P, int64_t I, int LP, const double* sq, int nsq,
+                    double* sq_out) {
+    const double bytes = (double)P * I * LP * 4.0 + (double)I * LP * 8.0;
+    RCP_TRY(timed(pl, RCP_KERNEL_REDUCE, bytes, (double)P * I * LP, [&] {
+        return launch_reduce_partials(pl->at<float>(pl->L.part), P, I * LP,
+                                      pl->at<double>(pl->L.y64), sq, nsq, sq_out, pl->stream);
+    }));
+    return RCP_OK;
+}
+
+// Algorithm 1 steps 3-12 for one mode.  On return the padded basis is in
+// Qt (I x LP) and, if Q != null, the basis (I x l) is in Q.
+rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int mode, float* Q,
+                       double* norm_out) {
+    const int N = pl->L.N;
+    const int64_t I = cur[mode];
+    const int l = (int)std::min<int64_t>(pl->prob.k + pl->prob.p, I);
+    const int LP = lp_of(l);
+    const StreamGeom g = make_geom(T, cur, N, mode);
+    const int P = (int)std::max<int64_t>(1, std::min<int64_t>(pl->P, g.ntiles));
+    float* part = pl->at<float>(pl->L.part);
+    double* Y = pl->at<double>(pl->L.y64);
+    float* Qt = pl->at<float>(pl->L.qt);
+    double* sq = pl->at<double>(pl->L.sq);
+    const uint32_t tag = omega_stream_tag(0, (uint32_t)mode);
+    const int nIB = contract_out_row_blocks(I);
+
+    const double S = (double)count_of(cur, N);
+    const double J = S / (double)I;
+    const double qr_bytes = (double)I * l * 8.0 + (double)I * LP * 4.0;
+    const double qr_flops = 4.0 * (double)I * l * l;
+    RCP_TRY(timed(pl, RCP_KERNEL_SKETCH, 4.0 * S + 4.0 * I * l, 2.0 * S * l, [&] {
+        return launch_contract_out(g, l, nullptr, pl->prob.seed, tag, part, P,
+                                   norm_out ? sq : nullptr, pl->stream);
+    }));
+    rcp_status st = reduce_y(pl, P, I, LP, norm_out ? sq : nullptr, P * nIB, norm_out);
+    if (st != RCP_OK) return st;
+    const bool fused = power_fused_fits(I, l, pl->smem_limit);
+    for (int it = 0; it < pl->prob.q; ++it) {
+        RCP_TRY(timed(pl, RCP_KERNEL_QR, qr_bytes, qr_flops,
+                      [&] { return launch_qr(Y, I, l, LP, Qt, LP, nullptr, pl->stream); }));
+        if (fused) {
+            RCP_TRY(timed(pl, RCP_KERNEL_POWER, 4.0 * S + 4.0 * I * l, 4.0 * S * l,
+                          [&] { return launch_power_fused(g, l, Qt, part, P, pl->stream); }));
+        } else {
+            float* Z = pl->at<float>(pl->L.zbuf);
+            RCP_TRY(timed(pl, RCP_KERNEL_CONTRACT_IN, 4.0 * S + 4.0 * J * LP, 2.0 * S * l,
+                          [&] { return launch_contract_in(g, l, Qt, LP, Z, P, pl->stream); }));
+            RCP_TRY(timed(pl, RCP_KERNEL_CONTRACT_OUT, 4.0 * S + 4.0 * J * LP, 2.0 * S * l, [&] {
+                return launch_contract_out(g, l, Z, 0, 0, part, P, nullptr, pl->stream);
+            }));
+        }
+        st = reduce_y(pl, P, I, LP, nullptr, 0, nullptr);
+        if (st != RCP_OK) return st;
+    }
+    RCP_TRY(timed(pl, RCP_KERNEL_QR, qr_bytes, qr_flops,
+                  [&] { return launch_qr(Y, I, l, LP, Qt, LP, Q, pl->stream); }));
+    return RCP_OK;
+}
+
+// T_out = T x_mode Q^T with the padded basis already in Qt.
+rcp_status compress_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int mode,
+                         float* T_out) {
+    const int64_t I = cur[mode];
+    const int l = (int)std::min<int64_t>(pl->prob.k + pl->prob.p, I);
+    const StreamGeom g = make_geom(T, cur, pl->L.N, mode);
+    const int P = (int)std::max<int64_t>(1, std::min<int64_t>(pl->P, g.ntiles));
+    const double S = (double)count_of(cur, pl->L.N);
+    RCP_TRY(timed(pl, RCP_KERNEL_CONTRACT_IN, 4.0 * S + 4.0 * (S / (double)I) * l,
+                  2.0 * S * l, [&] {
+                      return launch_contract_in(g, l, pl->at<float>(pl->L.qt), l, T_out, P,
+                                                pl->stream);
+                  }));
+    return RCP_OK;
+}
+
+rcp_status als_impl(rcp_plan_t* pl, const float* core, float* const* At, float* lambda,
+                    const double* normX2, rcp_als_info* info) {
+    const Layout& L = pl->L;
+    AlsArgs a{};
+    a.B = core;
+    a.N = L.N;
+    for (int n = 0; n < L.N; ++n) { a.l[n] = L.l[n]; a.At[n] = At[n]; }
+    a.R = L.R;
+    a.max_iters = pl->prob.max_iters;
+    a.tol = pl->prob.tol;
+    a.normX2 = normX2;
+    a.lambda = lambda;
+    a.info = info;
+    double* w = pl->at<double>(L.als);
+    int64_t S = 1;
+    for (int n = 0; n < L.N; ++n) S *= L.l[n];
+    const int64_t Lh = S / L.l[L.N - 1];
+    const int R = L.R;
+    a.W = w; w += Lh * R;
+    a.KR = w; w += Lh * R;
+    a.G = w; w += (int64_t)L.N * R * R;
+    a.Mbuf = w; w += 2 * 64 * RCP_MAX_RANK;
+    a.Vbuf = w; w += (int64_t)R * R;
+    w += (int64_t)R * R;
+    a.Ebuf = w; w += 2 * 64 * 64;
+    a.misc = w;
+    // nominal algorithmic work: two contractions of the core with R columns per sweep
+    const double sweeps = (double)pl->prob.max_iters;
+    RCP_TRY(timed(pl, RCP_KERNEL_ALS, sweeps * 2.0 * 4.0 * (double)S, sweeps * 4.0 * (double)S * R,
+                  [&] { return launch_als(a, pl->stream); }));
+    return RCP_OK;
+}
+
+rcp_status expand_impl(rcp_plan_t* pl, const float* const* Q, const float* const* At,
+                       const float* lam_in, float* const* A, float* lam_out) {
+    const Layout& L = pl->L;
+    ExpandArgs e{};
+    e.N = L.N;
+    e.R = L.R;
+    for (int n = 0; n < L.N; ++n) {
+        e.I[n] = L.dims[n];
+        e.l[n] = L.l[n];
+        e.Q[n] = Q[n];
+        e.At[n] = At[n];
+        e.A[n] = A[n];
+    }
+    e.lambda_in = lam_in;
+    e.lambda_out = lam_out;
+    e.raw = pl->at<double>(L.raw);
+    double flops = 0.0, bytes = 0.0;
+    for (int n = 0; n < L.N; ++n) {
+        flops += 2.0 * (double)L.dims[n] * L.l[n] * L.R;
+        bytes += 4.0 * ((double)L.dims[n] * L.l[n] + (double)L.dims[n] * L.R);
+    }
+    RCP_TRY(timed(pl, RCP_KERNEL_EXPAND, bytes, flops, [&] { return launch_expand(e, pl->stream); }));
+    return RCP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rcp_status_string(rcp_status s) {
+    switch (s) {
+        case RCP_OK: return "RCP_OK: success";
+        case RCP_ERR_INVALID_ARG: return "RCP_ERR_INVALID_ARG: invalid argument";
+        case RCP_ERR_WORKSPACE: return "RCP_ERR_WORKSPACE: workspace missing or too small";
+        case RCP_ERR_HIP: return "RCP_ERR_HIP: HIP runtime or launch failure";
+        case RCP_ERR_NUMERIC: return "RCP_ERR_NUMERIC: numeric failure";
+        case RCP_ERR_UNSUPPORTED: return "RCP_ERR_UNSUPPORTED: not supported by this build";
+    }
+    return "unknown rcp_status";
+}
+
+const char* rcp_version(void) { return "librcp 0.1 (gfx950)"; }
+
+rcp_status rcp_workspace_size(const rcp_problem* prob, size_t* bytes) {
+    if (bytes == nullptr || !valid_problem(prob)) return RCP_ERR_INVALID_ARG;
+    *bytes = make_layout(prob).total;
+    return RCP_OK;
+}
+
+rcp_status rcp_init(rcp_plan* plan, const rcp_problem* prob, void* workspace,
+                    size_t workspace_bytes, void* hip_stream) {
+    if (plan == nullptr) return RCP_ERR_INVALID_ARG;
+    *plan = nullptr;
+    if (!valid_problem(prob)) return RCP_ERR_INVALID_ARG;
+    if (prob->precision != RCP_PREC_FP32) return RCP_ERR_UNSUPPORTED;
+    const Layout L = make_layout(prob);
+    if (workspace == nullptr || workspace_bytes < L.total || !aligned(workspace, kAlign))
+        return RCP_ERR_WORKSPACE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RCP_ERR_HIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return RCP_ERR_HIP;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return RCP_ERR_UNSUPPORTED;
+    const int cus = prop.multiProcessorCount;
+    rcp_plan_t* pl = new (std::nothrow) rcp_plan_t;
+    if (pl == nullptr) return RCP_ERR_HIP;
+    pl->prob = *prob;
+    pl->L = L;
+    pl->stream = (hipStream_t)hip_stream;
+    pl->ws = (char*)workspace;
+    pl->ws_bytes = workspace_bytes;
+    pl->P = std::max(1, std::min(kPmax, cus));
+    pl->smem_limit = kLdsBytes;
+    *plan = pl;
+    return RCP_OK;
+}
+
+rcp_status rcp_destroy(rcp_plan plan) {
+    if (plan == nullptr) return RCP_ERR_INVALID_ARG;
+    plan->prof.clear();
+    delete plan;
+    return RCP_OK;
+}
+
+rcp_status rcp_profile(rcp_plan plan, int32_t enable) {
+    if (plan == nullptr) return RCP_ERR_INVALID_ARG;
+    Profiler& pr = plan->prof;
+    pr.clear();
+    if (!enable) return RCP_OK;
+    pr.ev.resize(2 * kMaxProfiled);
+    for (size_t i = 0; i < pr.ev.size(); ++i) {
+        if (hipEventCreate(&pr.ev[i]) != hipSuccess) {
+            pr.ev.resize(i);
+            pr.clear();
+            return RCP_ERR_HIP;
+        }
+    }
+    pr.rec.reserve(kMaxProfiled);
+    pr.on = true;
+    return RCP_OK;
+}
+
+rcp_status rcp_profile_read(rcp_plan plan, int32_t kernel_class, int64_t* launches, double* ms,
+                            double* bytes, double* flops) {
+    if (plan == nullptr || kernel_class < 0 || kernel_class >= RCP_KERNEL_COUNT)
+        return RCP_ERR_INVALID_ARG;
+    const Profiler& pr = plan->prof;
+    int64_t n = pr.untimed[kernel_class];
+    double t = 0.0, b = 0.0, f = 0.0;
+    for (size_t i = 0; i < pr.rec.size(); ++i) {
+        if (pr.rec[i].cls != kernel_class) continue;
+        if (hipEventSynchronize(pr.ev[2 * i + 1]) != hipSuccess) return RCP_ERR_HIP;
+        float e = 0.0f;
+        if (hipEventElapsedTime(&e, pr.ev[2 * i], pr.ev[2 * i + 1]) != hipSuccess) return RCP_ERR_HIP;
+        t += e;
+        b += pr.rec[i].bytes;
+        f += pr.rec[i].flops;
+        ++n;
+    }
+    if (launches) *launches = n;
+    if (ms) *ms = t;
+    if (bytes) *bytes = b;
+    if (flops) *flops = f;
+    return RCP_OK;
+}
+
+rcp_status rcp_sketch(rcp_plan plan, const float* T, const int64_t* cur_dims, int32_t mode,
+                      float* Q) {
+    if (plan == nullptr || T == nullptr || Q == nullptr) return RCP_ERR_INVALID_ARG;
+    if (mode < 0 || mode >= plan->L.N || !valid_cur_dims(plan, cur_dims)) return RCP_ERR_INVALID_ARG;
+    if (!aligned(T, 4) || !aligned(Q, 4)) return RCP_ERR_INVALID_ARG;
+    return sketch_impl(plan, T, cur_dims, mode, Q, nullptr);
+}
+
+rcp_status rcp_compress(rcp_plan plan, const float* T, const int64_t* cur_dims, int32_t mode,
+                        const float* Q, float* T_out) {
+    if (plan == nullptr || T == nullptr || Q == nullptr || T_out == nullptr)
+        return RCP_ERR_INVALID_ARG;
+    if (mode < 0 || mode >= plan->L.N || !valid_cur_dims(plan, cur_dims)) return RCP_ERR_INVALID_ARG;
+    if (!aligned(T, 4) || !aligned(Q, 4) || !aligned(T_out, 4)) return RCP_ERR_INVALID_ARG;
+    const int N = plan->L.N;
+    const int64_t I = cur_dims[mode];
+    const int l = (int)std::min<int64_t>(plan->prob.k + plan->prob.p, I);
+    const int64_t nin = count_of(cur_dims, N);
+    const int64_t nout = nin / I * l;
+    if (overlap(T, (size_t)nin * 4, T_out, (size_t)nout * 4)) return RCP_ERR_INVALID_ARG;
+    RCP_TRY(launch_pad_q(Q, I, l, plan->at<float>(plan->L.qt), lp_of(l), plan->stream));
+    return compress_impl(plan, T, cur_dims, mode, T_out);
+}
+
+rcp_status rcp_norm2(rcp_plan plan, const float* X, int64_t count, double* out) {
+    if (plan == nullptr || X == nullptr || out == nullptr || count < 0) return RCP_ERR_INVALID_ARG;
+    if (!aligned(X, 4) || !aligned(out, 8)) return RCP_ERR_INVALID_ARG;
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kPmax, (count + 255) / 256));
+    RCP_TRY(launch_sumsq(X, count, plan->at<double>(plan->L.sq), nb, out, plan->stream));
+    return RCP_OK;
+}
+
+rcp_status rcp_als(rcp_plan plan, const float* core, float* const* At, float* lambda,
+                   const double* normX2, rcp_als_info* info) {
+    if (plan == nullptr || core == nullptr || At == nullptr || lambda == nullptr || info == nullptr)
+        return RCP_ERR_INVALID_ARG;
+    for (int n = 0; n < plan->L.N; ++n)
+        if (At[n] == nullptr || !aligned(At[n], 4)) return RCP_ERR_INVALID_ARG;
+    if (!aligned(core, 4) || !aligned(info, 8) || (normX2 && !aligned(normX2, 8)))
+        return RCP_ERR_INVALID_ARG;
+    return als_impl(plan, core, At, lambda, normX2, info);
+}
+
+rcp_status rcp_expand(rcp_plan plan, const float* const* Q, const float* const* At,
+                      const float* lambda_in, float* const* A, float* lambda_out) {
+    if (plan == nullptr || Q == nullptr || At == nullptr || A == nullptr || lambda_in == nullptr ||
+        lambda_out == nullptr)
+        return RCP_ERR_INVALID_ARG;
+    for (int n = 0; n < plan->L.N; ++n)
+        if (Q[n] == nullptr || At[n] == nullptr || A[n] == nullptr) return RCP_ERR_INVALID_ARG;
+    return expand_impl(plan, Q, At, lambda_in, A, lambda_out);
+}
+
+rcp_status rcp_decompose(rcp_plan plan, const float* X, float* const* A, float* lambda,
+                         rcp_als_info* info) {
+    if (plan == nullptr || X == nullptr || A == nullptr || lambda == nullptr || info == nullptr)
+        return RCP_ERR_INVALID_ARG;
+    for (int n = 0; n < plan->L.N; ++n)
+        if (A[n] == nullptr || !aligned(A[n], 4)) return RCP_ERR_INVALID_ARG;
+    if (!aligned(X, 4) || !aligned(info, 8)) return RCP_ERR_INVALID_ARG;
+    const Layout& L = plan->L;
+    const int N = L.N;
+    double* normX2 = plan->at<double>(L.norm);
+    float* Qb[RCP_MAX_NDIM];
+    for (int n = 0; n < N; ++n) Qb[n] = plan->at<float>(L.qb[n]);
+    int64_t cur[RCP_MAX_NDIM];
+    for (int n = 0; n < N; ++n) cur[n] = L.dims[n];
+    const float* T = X;
+    rcp_status st;
+    if (plan->prob.scheme == RCP_SCHEME_SEQUENTIAL) {
+        for (int n = 0; n < N; ++n) {
+            st = sketch_impl(plan, T, cur, n, Qb[n], n == 0 ? normX2 : nullptr);
+            if (st != RCP_OK) return st;
+            float* out = plan->at<float>(L.tb[n % 2]);
+            st = compress_impl(plan, T, cur, n, out);
+            if (st != RCP_OK) return st;
+            cur[n] = L.l[n];
+            T = out;
+        }
+    } else {
+        for (int n = 0; n < N; ++n) {
+            st = sketch_impl(plan, X, cur, n, Qb[n], n == 0 ? normX2 : nullptr);
+            if (st != RCP_OK) return st;
+        }
+        for (int n = 0; n < N; ++n) {
+            RCP_TRY(launch_pad_q(Qb[n], L.dims[n], L.l[n], plan->at<float>(L.qt), L.LP[n],
+                                 plan->stream));
+            float* out = plan->at<float>(L.tb[n % 2]);
+            st = compress_impl(plan, T, cur, n, out);
+            if (st != RCP_OK) return st;
+            cur[n] = L.l[n];
+            T = out;
+        }
+    }
+    float* At[RCP_MAX_NDIM];
+    for (int n = 0; n < N; ++n) At[n] = plan->at<float>(L.at[n]);
+    float* lam = plan->at<float>(L.lam);
+    st = als_impl(plan, T, At, lam, normX2, info);
+    if (st != RCP_OK) return st;
+    const float* Qc[RCP_MAX_NDIM];
+    const float* Atc[RCP_MAX_NDIM];
+    for (int n = 0; n < N; ++n) { Qc[n] = Qb[n]; Atc[n] = At[n]; }
+    return expand_impl(plan, Qc, Atc, lam, A, lambda);
+}
+
+rcp_status rcp_get_bases(rcp_plan plan, float** Q) {
+    if (plan == nullptr || Q == nullptr) return RCP_ERR_INVALID_ARG;
+    for (int n = 0; n < plan->L.N; ++n) Q[n] = plan->at<float>(plan->L.qb[n]);
+    return RCP_OK;
+}
+
+rcp_status rcp_get_core(rcp_plan plan, float** core, int64_t* core_dims) {
+    if (plan == nullptr || core == nullptr) return RCP_ERR_INVALID_ARG;
+    *core = plan->at<float>(plan->L.tb[(plan->L.N - 1) % 2]);
+    if (core_dims != nullptr)
+        for (int n = 0; n < plan->L.N; ++n) core_dims[n] = plan->L.core_dims[n];
+    return RCP_OK;
+}
+
+rcp_status rcp_debug_omega(rcp_plan plan, int32_t mode, int64_t row0, int64_t nrows, int32_t l,
+                           float* omega) {
+    if (plan == nullptr || omega == nullptr || mode < 0 || mode >= 256 || row0 < 0 || nrows < 0 ||
+        l < 1 || l > RCP_MAX_L)
+        return RCP_ERR_INVALID_ARG;
+    if (!aligned(omega, 4)) return RCP_ERR_INVALID_ARG;
+    RCP_TRY(launch_omega(plan->prob.seed, omega_stream_tag(0, (uint32_t)mode), row0, nrows, l, omega,
+                         plan->stream));
+    return RCP_OK;
+}
+
+}  // extern "C"

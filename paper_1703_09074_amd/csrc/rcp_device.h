@@ -1,0 +1,123 @@
+// Device-side building blocks shared by the librcp kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rcp {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Counter-based Gaussian test matrix (Section 3.1: Gaussian random vectors
+// omega_1..omega_l; Algorithm 1 step 5).  Philox4x32-10 from Salmon, Moraes,
+// Dror, Shaw (SC'11): ten rounds of two 32x32->64 multiplies with the
+// constants below, key bumped by the Weyl increments between rounds.
+
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * c.x;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        U4 n;
+        n.x = hi1 ^ c.y ^ k0;
+        n.y = lo1;
+        n.z = hi0 ^ c.w ^ k1;
+        n.w = lo0;
+        c = n;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    return c;
+}
+
+// u = ((x >> 8) + 1) * 2^-24 in (0, 1], exact in float32.
+__device__ __forceinline__ float uniform24(uint32_t x) {
+    return (float)((x >> 8) + 1u) * 5.9604644775390625e-08f;
+}
+
+// Four N(0,1) values of row j, columns 4g..4g+3 of Omega (Box-Muller on the
+// pairs (u0,u1) and (u2,u3); cos/sin of 2*pi*u through sinpi/cospi of 2u,
+// which is exact in the argument).
+__device__ __forceinline__ void omega4(uint64_t seed, uint32_t tag, uint64_t j, uint32_t g,
+                                       float out[4]) {
+    U4 c;
+    c.x = (uint32_t)j;
+    c.y = (uint32_t)(j >> 32);
+    c.z = g;
+    c.w = tag;
+    const U4 x = philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const float u0 = uniform24(x.x), u1 = uniform24(x.y);
+    const float u2 = uniform24(x.z), u3 = uniform24(x.w);
+    const float ra = sqrtf(-2.0f * logf(u0));
+    const float rb = sqrtf(-2.0f * logf(u2));
+    float sa, ca, sb, cb;
+    sincospif(2.0f * u1, &sa, &ca);
+    sincospif(2.0f * u3, &sb, &cb);
+    out[0] = ra * ca;
+    out[1] = ra * sa;
+    out[2] = rb * cb;
+    out[3] = rb * sb;
+}
+
+__device__ __forceinline__ uint32_t omega_tag(uint32_t batch, uint32_t mode) {
+    return (batch << 8) | (mode & 0xFFu);
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core FP32 product: D(16x16) += A(16x4) B(4x16) on one wavefront.
+// Lane layout (v_mfma_f32_16x16x4_f32): lane holds A[lane%16][lane/16],
+// B[lane/16][lane%16] and D[4*(lane/16)+v][lane%16], v = 0..3.
+
+__device__ __forceinline__ f32x4 mfma16x16x4(float a, float b, f32x4 acc) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions.
+
+__device__ __forceinline__ double warp_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ float warp_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-wide sum of one double; `red` holds >= blockDim.x/64 doubles.
+// Every thread receives the total.  Contains two __syncthreads.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = warp_sum(v);
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += red[i];
+    return t;
+}
+
+// Exact-ish integer quotient of small non-negative values (< 2^22) by a
+// positive divisor, using a float reciprocal plus one correction step.
+__device__ __forceinline__ int small_div(int a, int d, float inv_d) {
+    int q = (int)((float)a * inv_d);
+    int r = a - q * d;
+    if (r < 0) { --q; r += d; }
+    if (r >= d) { ++q; }
+    return q;
+}
+
+}  // namespace rcp

@@ -1,0 +1,90 @@
+// Internal launch interface between the host library and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/rcp.h"
+
+namespace rcp {
+
+// Mode-n view (L, I, Rr) of a C-order tensor and its column tiling.
+struct StreamGeom {
+    const float* T;
+    int64_t L, I, Rr;
+    int32_t caseB;         // 0: tiles are b-runs inside one a; 1: tiles are TA whole a-slabs
+    int32_t TA;
+    int64_t tiles_per_a;   // case A
+    int64_t ntiles;
+};
+
+StreamGeom make_geom(const float* T, const int64_t* dims, int ndim, int mode);
+
+// streaming contractions (stream_kernels.hip)
+hipError_t launch_contract_out(const StreamGeom& g, int l, const float* Z, uint64_t seed,
+                               uint32_t tag, float* part, int P, double* sq_part,
+                               hipStream_t s);
+int contract_out_row_blocks(int64_t I);
+bool power_fused_fits(int64_t I, int l, size_t smem_limit);
+hipError_t launch_power_fused(const StreamGeom& g, int l, const float* Qt, float* part, int P,
+                              hipStream_t s);
+hipError_t launch_contract_in(const StreamGeom& g, int l, const float* Qpadded, int lout,
+                              float* out, int P, hipStream_t s);
+hipError_t launch_reduce_partials(const float* part, int P, int64_t count, double* Y,
+                                  const double* sq_part, int nsq, double* sq_out,
+                                  hipStream_t s);
+hipError_t launch_sumsq(const float* x, int64_t count, double* part, int nblocks, double* out,
+                        hipStream_t s);
+hipError_t launch_omega(uint64_t seed, uint32_t tag, int64_t row0, int64_t nrows, int l,
+                        float* out, hipStream_t s);
+hipError_t launch_pad_q(const float* Q, int64_t I, int l, float* Qpad, int ldq, hipStream_t s);
+constexpr uint32_t omega_stream_tag(uint32_t batch, uint32_t mode) { return (batch << 8) | (mode & 0xFFu); }
+
+// small dense kernels (qr_kernel.hip)
+// Householder QR of the m x n float64 matrix Y (row stride ldy, overwritten);
+// writes Q (diag(R) > 0) as float32 into Qpad (m x ldq, columns >= n zeroed)
+// and, if non-null, into Qout (m x n).
+hipError_t launch_qr(double* Y, int64_t m, int n, int ldy, float* Qpad, int ldq, float* Qout,
+                     hipStream_t s);
+
+// CP-ALS on the core (als_kernel.hip)
+struct AlsArgs {
+    const float* B;            // core, dims l[0..N-1]
+    int N;
+    int l[RCP_MAX_NDIM];
+    int R;
+    int max_iters;
+    double tol;
+    const double* normX2;      // may be null
+    float* At[RCP_MAX_NDIM];   // l_n x R outputs
+    float* lambda;             // R
+    rcp_als_info* info;
+    // workspace
+    double* W;                 // Lh x R (Lh = S / l_{N-1})
+    double* KR;                // Lh x R
+    double* G;                 // N x R x R Grams
+    double* Mbuf;              // lmax x R
+    double* Vbuf;              // R x R
+    double* Ebuf;              // 2 x 64 x 64 Jacobi scratch
+    double* misc;              // 64 doubles
+};
+hipError_t launch_als(const AlsArgs& a, hipStream_t s);
+size_t als_workspace_doubles(int N, const int* l, int R);
+
+// back-projection (expand_kernel.hip)
+struct ExpandArgs {
+    int N;
+    int64_t I[RCP_MAX_NDIM];
+    int l[RCP_MAX_NDIM];
+    int R;
+    const float* Q[RCP_MAX_NDIM];
+    const float* At[RCP_MAX_NDIM];
+    const float* lambda_in;
+    float* A[RCP_MAX_NDIM];
+    float* lambda_out;
+    double* raw;               // scratch: sum_n I_n x R
+};
+hipError_t launch_expand(const ExpandArgs& a, hipStream_t s);
+
+}  // namespace rcp

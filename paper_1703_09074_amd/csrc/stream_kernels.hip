@@ -1,0 +1,597 @@
+// Streaming contractions over the current tensor T (Algorithm 1 steps 6,
+// 9, 10 and 13), hand-written for gfx950.
+//
+// T is C-order with dims (I_0..I_{N-1}); around mode n it is viewed as a
+// 3-D array (L, I, Rr): L = prod of dims before n, Rr = prod after n.  The
+// mode-n unfolding T_(n) is I x J with column j = a*Rr + b and is never
+// materialised.  Its columns are cut into tiles of JT consecutive j that
+// stay contiguous in memory:
+//   case A (Rr >= JT): a tile is (fixed a, b in [b0, b0+JT)), one run of
+//     JT floats per row i;
+//   case B (Rr <  JT): a tile is TA whole a-slabs (all b), i.e. one
+//     contiguous block of TA*I*Rr floats.
+// A workgroup loads a tile (all rows of its row block) into LDS with
+// coalesced loads and feeds the matrix cores (v_mfma_f32_16x16x4_f32) from
+// there.  The sketch width l is padded to LP (a multiple of 16) with zero
+// columns.
+
+#include "rcp_device.h"
+#include "rcp_kernels.h"
+
+namespace rcp {
+
+constexpr int JT = 32;            // tile width along the unfolding's columns
+constexpr int TS = JT + 1;        // LDS row stride of a tile
+constexpr int NT = 256;           // threads per workgroup (4 wavefronts)
+
+struct TileInfo {
+    int64_t j0;      // first unfolding column of the tile
+    int64_t a0;      // first a (case A: the a of the tile)
+    int64_t b0;      // first b (case A), 0 in case B
+    int width;       // number of valid columns (<= JT)
+    int na;          // case B: number of a-slabs in the tile
+};
+
+__device__ __forceinline__ TileInfo tile_info(const StreamGeom& g, int64_t t) {
+    TileInfo ti;
+    if (!g.caseB) {
+        const int64_t a = t / g.tiles_per_a;
+        const int64_t b0 = (t - a * g.tiles_per_a) * JT;
+        ti.a0 = a;
+        ti.b0 = b0;
+        ti.j0 = a * g.Rr + b0;
+        const int64_t w = g.Rr - b0;
+        ti.width = (int)(w < JT ? w : JT);
+        ti.na = 1;
+    } else {
+        const int64_t a0 = t * g.TA;
+        const int64_t left = g.L - a0;
+        ti.na = (int)(left < g.TA ? left : g.TA);
+        ti.a0 = a0;
+        ti.b0 = 0;
+        ti.j0 = a0 * g.Rr;
+        ti.width = ti.na * (int)g.Rr;
+    }
+    return ti;
+}
+
+// Loads rows [i_lo, i_lo + nrows) of tile `ti` into Ts[r][jj] (row stride TS)
+// for r < rows_alloc: rows >= nrows and columns >= width are zero-filled.
+// Returns this thread's sum of squares of the loaded values (float64).
+__device__ __forceinline__ double load_tile(const StreamGeom& g, const TileInfo& ti,
+                                            int64_t i_lo, int nrows, int rows_alloc,
+                                            float* Ts, bool want_sq) {
+    double sq = 0.0;
+    const int tid = threadIdx.x;
+    // zero the padding first (columns >= width of valid rows, rows >= nrows)
+    if (ti.width < JT || nrows < rows_alloc) {
+        for (int e = tid; e < rows_alloc * JT; e += NT) {
+            const int r = e / JT, jj = e % JT;
+            if (r >= nrows || jj >= ti.width) Ts[r * TS + jj] = 0.0f;
+        }
+    }
+    if (!g.caseB) {
+        const float* base = g.T + ((ti.a0 * g.I + i_lo) * g.Rr + ti.b0);
+        const int total = nrows * JT;
+        for (int e = tid; e < total; e += NT) {
+            const int r = e / JT, jj = e % JT;
+            if (jj < ti.width) {
+                const float v = base[(int64_t)r * g.Rr + jj];
+                Ts[r * TS + jj] = v;
+                if (want_sq) sq += (double)v * (double)v;
+            }
+        }
+    } else {
+        const int rr = (int)g.Rr;
+        const int slab = nrows * rr;                 // floats per a-slab in this row block
+        const float inv_slab = 1.0f / (float)slab, inv_rr = 1.0f / (float)rr;
+        const int total = ti.na * slab;
+        for (int e = tid; e < total; e += NT) {
+            const int arel = small_div(e, slab, inv_slab);
+            const int rem = e - arel * slab;
+            const int r = small_div(rem, rr, inv_rr);
+            const int b = rem - r * rr;
+            const float v = g.T[((ti.a0 + arel) * g.I + i_lo) * g.Rr + rem];
+            Ts[r * TS + arel * rr + b] = v;
+            if (want_sq) sq += (double)v * (double)v;
+        }
+    }
+    return sq;
+}
+
+// Y[rows, 0:16*NB] += Ts[rows, 0:JT] * W[0:JT, 0:16*NB] for the MB row
+// blocks this wavefront owns (row block rb = wave + 4*m).
+template <int NB, int MB>
+__device__ __forceinline__ void tile_times_w(const float* Ts, const float* W, int ldw,
+                                             f32x4 (&acc)[MB][NB]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int k0 = 0; k0 < JT; k0 += 4) {
+        float b[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) b[nb] = W[(k0 + lk) * ldw + nb * 16 + lr];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            const float a = Ts[((wave + 4 * m) * 16 + lr) * TS + k0 + lk];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[m][nb] = mfma16x16x4(a, b[nb], acc[m][nb]);
+        }
+    }
+}
+
+// z[0:JT, 0:16*NB] (partial over rows [r_lo, r_hi) of the LDS tile) =
+// Ts[r, :]^T Qs[r, :].  The rows are split across the 4 wavefronts.
+template <int NB>
+__device__ __forceinline__ void tile_t_times_q(const float* Ts, const float* Qs, int ldq,
+                                               int rows, f32x4 (&zacc)[2][NB]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int per = rows / 4;                    // rows is a multiple of 16
+    const int r_lo = wave * per, r_hi = r_lo + per;
+    for (int k0 = r_lo; k0 < r_hi; k0 += 4) {
+        float b[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) b[nb] = Qs[(k0 + lk) * ldq + nb * 16 + lr];
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) {
+            const float a = Ts[(k0 + lk) * TS + jb * 16 + lr];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) zacc[jb][nb] = mfma16x16x4(a, b[nb], zacc[jb][nb]);
+        }
+    }
+}
+
+// Store the wavefronts' partial z into zp[wave][jj][c] and sum into zs.
+template <int NB>
+__device__ __forceinline__ void reduce_z(const f32x4 (&zacc)[2][NB], float* zp, float* zs) {
+    constexpr int LPc = NB * 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    float* my = zp + wave * JT * LPc;
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                my[(jb * 16 + 4 * lk + v) * LPc + nb * 16 + lr] = zacc[jb][nb][v];
+    __syncthreads();
+    for (int e = threadIdx.x; e < JT * LPc; e += NT)
+        zs[e] = zp[e] + zp[JT * LPc + e] + zp[2 * JT * LPc + e] + zp[3 * JT * LPc + e];
+    __syncthreads();
+}
+
+template <int NB, int MB>
+__device__ __forceinline__ void store_partial(const f32x4 (&acc)[MB][NB], float* part,
+                                              int64_t I, int64_t row0) {
+    constexpr int LPc = NB * 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = row0 + (wave + 4 * m) * 16 + 4 * lk + v;
+            if (row < I) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) part[row * LPc + nb * 16 + lr] = acc[m][nb][v];
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// contract_out: partial Y = T_(n) W over the tiles of this workgroup, for
+// the row block blockIdx.y (64*MB rows).  W is the Gaussian test matrix
+// generated in registers (GEN) or a stored J x LP matrix in the layout
+// (L, LP, Rr) (power iteration with a stored Z).  Optional float64 partial
+// sum of squares of T (used for ||X||^2 in the first pass).
+
+template <int NB, int MB, bool GEN>
+__global__ __launch_bounds__(NT) void k_contract_out(StreamGeom g, int l, const float* Z,
+                                                     uint64_t seed, uint32_t tag, float* part,
+                                                     double* sq_part) {
+    constexpr int LPc = NB * 16;
+    constexpr int IB = 64 * MB;
+    extern __shared__ float smem[];
+    float* Ts = smem;                       // IB x TS
+    float* Ws = Ts + IB * TS;               // JT x LPc
+    __shared__ double red[NT / 64];
+
+    const int64_t row0 = (int64_t)blockIdx.y * IB;
+    const int64_t rows_left = g.I - row0;
+    const int nrows = (int)(rows_left < IB ? rows_left : IB);
+
+    f32x4 acc[MB][NB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    double sq = 0.0;
+    const bool want_sq = sq_part != nullptr;
+    for (int64_t t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
+        const TileInfo ti = tile_info(g, t);
+        __syncthreads();
+        sq += load_tile(g, ti, row0, nrows, IB, Ts, want_sq);
+        if (GEN) {
+            constexpr int NG = LPc / 4;
+            for (int e = threadIdx.x; e < JT * NG; e += NT) {
+                const int jj = e / NG, gi = e % NG;
+                float z[4] = {0.f, 0.f, 0.f, 0.f};
+                if (jj < ti.width) omega4(seed, tag, (uint64_t)(ti.j0 + jj), (uint32_t)gi, z);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = 4 * gi + v;
+                    Ws[jj * LPc + c] = (c < l) ? z[v] : 0.0f;
+                }
+            }
+        } else {
+            for (int e = threadIdx.x; e < JT * LPc; e += NT) {
+                const int jj = e % JT, c = e / JT;
+                float v = 0.0f;
+                if (jj < ti.width) {
+                    int64_t a, b;
+                    if (!g.caseB) { a = ti.a0; b = ti.b0 + jj; }
+                    else { a = ti.a0 + jj / g.Rr; b = jj % g.Rr; }
+                    v = Z[(a * LPc + c) * g.Rr + b];
+                }
+                Ws[jj * LPc + c] = v;
+            }
+        }
+        __syncthreads();
+        tile_times_w<NB, MB>(Ts, Ws, LPc, acc);
+    }
+    store_partial<NB, MB>(acc, part + (int64_t)blockIdx.x * g.I * LPc, g.I, row0);
+    if (want_sq) {
+        const double s = block_sum(sq, red);
+        if (threadIdx.x == 0) sq_part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// power_fused: partial Y = T_(n) (T_(n)^T Qt) in one pass over T.  Each tile
+// (all I rows, I <= 64*MB) is held in LDS: first z = tile^T Qt (JT x LP),
+// then Y += tile z.  The normalisation of Z in Algorithm 1 step 9 is an
+// invertible upper-triangular right factor, which the QR of the next sketch
+// absorbs, so it is not applied.
+
+template <int NB, int MB>
+__global__ __launch_bounds__(NT) void k_power_fused(StreamGeom g, const float* Qt, float* part) {
+    constexpr int LPc = NB * 16;
+    constexpr int IB = 64 * MB;
+    extern __shared__ float smem[];
+    float* Ts = smem;                       // IB x TS
+    float* Qs = Ts + IB * TS;               // IB x LPc
+    float* zp = Qs + IB * LPc;              // 4 x JT x LPc
+    float* zs = zp + 4 * JT * LPc;          // JT x LPc
+
+    const int I = (int)g.I;
+    for (int e = threadIdx.x; e < IB * LPc; e += NT) {
+        const int r = e / LPc;
+        Qs[e] = (r < I) ? Qt[e] : 0.0f;
+    }
+
+    f32x4 acc[MB][NB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int64_t t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
+        const TileInfo ti = tile_info(g, t);
+        __syncthreads();
+        load_tile(g, ti, 0, I, IB, Ts, false);
+        __syncthreads();
+        f32x4 zacc[2][NB];
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) zacc[jb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        tile_t_times_q<NB>(Ts, Qs, LPc, IB, zacc);
+        reduce_z<NB>(zacc, zp, zs);
+        tile_times_w<NB, MB>(Ts, zs, LPc, acc);
+    }
+    store_partial<NB, MB>(acc, part + (int64_t)blockIdx.x * g.I * LPc, g.I, 0);
+}
+
+// ---------------------------------------------------------------------------
+// contract_in: out[a, c, b] = sum_i Q[i, c] T[a, i, b] for c < lout
+// (Algorithm 1 step 13, T x_n Q^T; also Z = T_(n)^T Qt for the two-pass
+// power iteration).  Rows are streamed in chunks of IC through LDS.
+
+constexpr int IC = 128;
+
+template <int NB>
+__global__ __launch_bounds__(NT) void k_contract_in(StreamGeom g, const float* Q, int lout,
+                                                    float* out) {
+    constexpr int LPc = NB * 16;
+    extern __shared__ float smem[];
+    float* Ts = smem;                       // IC x TS
+    float* Qs = Ts + IC * TS;               // IC x LPc
+    float* zp = Qs + IC * LPc;              // 4 x JT x LPc
+    float* zs = zp + 4 * JT * LPc;          // JT x LPc
+
+    for (int64_t t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
+        const TileInfo ti = tile_info(g, t);
+        f32x4 zacc[2][NB];
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) zacc[jb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int64_t i_lo = 0; i_lo < g.I; i_lo += IC) {
+            const int64_t left = g.I - i_lo;
+            const int nrows = (int)(left < IC ? left : IC);
+            __syncthreads();
+            load_tile(g, ti, i_lo, nrows, IC, Ts, false);
+            for (int e = threadIdx.x; e < IC * LPc; e += NT) {
+                const int r = e / LPc;
+                Qs[e] = (r < nrows) ? Q[(i_lo + r) * LPc + (e - r * LPc)] : 0.0f;
+            }
+            __syncthreads();
+            tile_t_times_q<NB>(Ts, Qs, LPc, IC, zacc);
+        }
+        reduce_z<NB>(zacc, zp, zs);
+        // write z^T into the (L, lout, Rr) output
+        for (int e = threadIdx.x; e < lout * JT; e += NT) {
+            const int c = e / JT, jj = e % JT;
+            if (jj < ti.width) {
+                int64_t a, b;
+                if (!g.caseB) { a = ti.a0; b = ti.b0 + jj; }
+                else { a = ti.a0 + jj / g.Rr; b = jj % g.Rr; }
+                out[(a * lout + c) * g.Rr + b] = zs[jj * LPc + c];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic reduction of the per-workgroup partials:
+// Y[i, c] = sum_p part[p, i, c] in float64, fixed order.  Block 0 also sums
+// the optional sum-of-squares partials into *sq_out.
+
+__global__ __launch_bounds__(NT) void k_reduce_partials(const float* part, int P, int64_t count,
+                                                        double* Y, const double* sq_part,
+                                                        int nsq, double* sq_out) {
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e < count) {
+        double s = 0.0;
+        for (int p = 0; p < P; ++p) s += (double)part[(int64_t)p * count + e];
+        Y[e] = s;
+    }
+    if (sq_part != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
+        double s = 0.0;
+        for (int p = 0; p < nsq; ++p) s += sq_part[p];
+        *sq_out = s;
+    }
+}
+
+// Sum of squares of count floats: per-block float64 partials.
+__global__ __launch_bounds__(NT) void k_sumsq(const float* x, int64_t count, double* part) {
+    __shared__ double red[NT / 64];
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * NT) {
+        const double v = x[e];
+        s += v * v;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_sum_doubles(const double* part, int n, double* out) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += part[i];
+        *out = s;
+    }
+}
+
+// Rows [row0, row0+nrows) of Omega (nrows x l).
+__global__ __launch_bounds__(NT) void k_omega(uint64_t seed, uint32_t tag, int64_t row0,
+                                              int64_t nrows, int l, float* out) {
+    const int ng = (l + 3) / 4;
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= nrows * ng) return;
+    const int64_t r = e / ng;
+    const int gi = (int)(e - r * ng);
+    float z[4];
+    omega4(seed, tag, (uint64_t)(row0 + r), (uint32_t)gi, z);
+    for (int v = 0; v < 4; ++v) {
+        const int c = 4 * gi + v;
+        if (c < l) out[r * l + c] = z[v];
+    }
+}
+
+// Q (I x l) -> Qpad (I x ldq), zero columns >= l.
+__global__ __launch_bounds__(NT) void k_pad_q(const float* Q, int64_t I, int l, float* Qpad,
+                                              int ldq) {
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= I * ldq) return;
+    const int64_t i = e / ldq;
+    const int c = (int)(e - i * ldq);
+    Qpad[e] = (c < l) ? Q[i * l + c] : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+
+StreamGeom make_geom(const float* T, const int64_t* dims, int ndim, int mode) {
+    StreamGeom g;
+    g.T = T;
+    g.L = 1;
+    g.Rr = 1;
+    for (int m = 0; m < mode; ++m) g.L *= dims[m];
+    for (int m = mode + 1; m < ndim; ++m) g.Rr *= dims[m];
+    g.I = dims[mode];
+    if (g.Rr >= JT) {
+        g.caseB = 0;
+        g.TA = 1;
+        g.tiles_per_a = (g.Rr + JT - 1) / JT;
+        g.ntiles = g.L * g.tiles_per_a;
+    } else {
+        g.caseB = 1;
+        g.TA = (int32_t)(JT / g.Rr);
+        g.tiles_per_a = 0;
+        g.ntiles = (g.L + g.TA - 1) / g.TA;
+    }
+    return g;
+}
+
+hipError_t launch_pad_q(const float* Q, int64_t I, int l, float* Qpad, int ldq, hipStream_t s) {
+    const int64_t n = I * ldq;
+    const unsigned blocks = (unsigned)((n + NT - 1) / NT);
+    hipLaunchKernelGGL(k_pad_q, dim3(blocks), dim3(NT), 0, s, Q, I, l, Qpad, ldq);
+    return hipGetLastError();
+}
+
+static int lp_blocks(int l) { return (l + 15) / 16; }
+
+size_t contract_out_smem(int NB, int MB) {
+    return (size_t)(64 * MB * TS + JT * NB * 16) * sizeof(float);
+}
+
+size_t power_fused_smem(int NB, int MB) {
+    const int IB = 64 * MB, LPc = NB * 16;
+    return (size_t)(IB * TS + IB * LPc + 4 * JT * LPc + JT * LPc) * sizeof(float);
+}
+
+size_t contract_in_smem(int NB) {
+    const int LPc = NB * 16;
+    return (size_t)(IC * TS + IC * LPc + 4 * JT * LPc + JT * LPc) * sizeof(float);
+}
+
+template <int NB, int MB, bool GEN>
+static hipError_t launch_co(dim3 grid, size_t smem, hipStream_t s, const StreamGeom& g, int l,
+                            const float* Z, uint64_t seed, uint32_t tag, float* part,
+                            double* sq) {
+    auto k = k_contract_out<NB, MB, GEN>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, grid, dim3(NT), smem, s, g, l, Z, seed, tag, part, sq);
+    return hipGetLastError();
+}
+
+#define RCP_MB_SWITCH(MBV, ...)                                   \
+    switch (MBV) {                                                \
+        case 1: { constexpr int MB = 1; __VA_ARGS__; } break;     \
+        case 2: { constexpr int MB = 2; __VA_ARGS__; } break;     \
+        case 3: { constexpr int MB = 3; __VA_ARGS__; } break;     \
+        case 4: { constexpr int MB = 4; __VA_ARGS__; } break;     \
+        case 5: { constexpr int MB = 5; __VA_ARGS__; } break;     \
+        case 6: { constexpr int MB = 6; __VA_ARGS__; } break;     \
+        case 7: { constexpr int MB = 7; __VA_ARGS__; } break;     \
+        default: { constexpr int MB = 8; __VA_ARGS__; } break;    \
+    }
+
+#define RCP_NB_SWITCH(NBV, ...)                                   \
+    switch (NBV) {                                                \
+        case 1: { constexpr int NB = 1; __VA_ARGS__; } break;     \
+        case 2: { constexpr int NB = 2; __VA_ARGS__; } break;     \
+        case 3: { constexpr int NB = 3; __VA_ARGS__; } break;     \
+        default: { constexpr int NB = 4; __VA_ARGS__; } break;    \
+    }
+
+hipError_t launch_contract_out(const StreamGeom& g, int l, const float* Z, uint64_t seed,
+                               uint32_t tag, float* part, int P, double* sq_part,
+                               hipStream_t s) {
+    const int NBv = lp_blocks(l);
+    int MBv = (int)((g.I + 63) / 64);
+    if (MBv > 8) MBv = 8;
+    const int IB = 64 * MBv;
+    const unsigned nIB = (unsigned)((g.I + IB - 1) / IB);
+    const size_t smem = contract_out_smem(NBv, MBv);
+    const dim3 grid((unsigned)P, nIB);
+    hipError_t e = hipSuccess;
+    if (Z == nullptr) {
+        RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_co<NB, MB, true>(grid, smem, s, g, l, Z, seed, tag, part, sq_part))));
+    } else {
+        RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_co<NB, MB, false>(grid, smem, s, g, l, Z, seed, tag, part, sq_part))));
+    }
+    return e;
+}
+
+int contract_out_row_blocks(int64_t I) {
+    int MBv = (int)((I + 63) / 64);
+    if (MBv > 8) MBv = 8;
+    const int IB = 64 * MBv;
+    return (int)((I + IB - 1) / IB);
+}
+
+bool power_fused_fits(int64_t I, int l, size_t smem_limit) {
+    if (I > 512) return false;
+    const int MBv = (int)((I + 63) / 64);
+    return power_fused_smem(lp_blocks(l), MBv) <= smem_limit;
+}
+
+template <int NB, int MB>
+static hipError_t launch_pf(int P, size_t smem, hipStream_t s, const StreamGeom& g,
+                            const float* Qt, float* part) {
+    auto k = k_power_fused<NB, MB>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)P), dim3(NT), smem, s, g, Qt, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_fused(const StreamGeom& g, int l, const float* Qt, float* part, int P,
+                              hipStream_t s) {
+    const int NBv = lp_blocks(l);
+    const int MBv = (int)((g.I + 63) / 64);
+    const size_t smem = power_fused_smem(NBv, MBv);
+    hipError_t e = hipSuccess;
+    RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_pf<NB, MB>(P, smem, s, g, Qt, part))));
+    return e;
+}
+
+template <int NB>
+static hipError_t launch_ci(int P, size_t smem, hipStream_t s, const StreamGeom& g,
+                            const float* Q, int lout, float* out) {
+    auto k = k_contract_in<NB>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)P), dim3(NT), smem, s, g, Q, lout, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_contract_in(const StreamGeom& g, int l, const float* Qpadded, int lout,
+                              float* out, int P, hipStream_t s) {
+    const int NBv = lp_blocks(l);
+    const size_t smem = contract_in_smem(NBv);
+    hipError_t e = hipSuccess;
+    RCP_NB_SWITCH(NBv, e = (launch_ci<NB>(P, smem, s, g, Qpadded, lout, out)));
+    return e;
+}
+
+hipError_t launch_reduce_partials(const float* part, int P, int64_t count, double* Y,
+                                  const double* sq_part, int nsq, double* sq_out,
+                                  hipStream_t s) {
+    const unsigned blocks = (unsigned)((count + NT - 1) / NT);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks > 0 ? blocks : 1), dim3(NT), 0, s, part, P,
+                       count, Y, sq_part, nsq, sq_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const float* x, int64_t count, double* part, int nblocks, double* out,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_sumsq, dim3((unsigned)nblocks), dim3(NT), 0, s, x, count, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_doubles, dim3(1), dim3(64), 0, s, part, nblocks, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_omega(uint64_t seed, uint32_t tag, int64_t row0, int64_t nrows, int l,
+                        float* out, hipStream_t s) {
+    const int ng = (l + 3) / 4;
+    const int64_t n = nrows * ng;
+    const unsigned blocks = (unsigned)((n + NT - 1) / NT);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_omega, dim3(blocks), dim3(NT), 0, s, seed, tag, row0, nrows, l, out);
+    return hipGetLastError();
+}
+
+}  // namespace rcp

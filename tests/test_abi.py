@@ -1,0 +1,163 @@
+"""The C interface without a GPU: the library loads, exports every entry
+point the header declares, the binding's structs match the header's
+layout, and host-side argument checking behaves as documented."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rcp.h")
+
+from paper_1703_09074_amd import _lib  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:rcp_status|const char\*)\s+(rcp_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("rcp_init", "rcp_sketch", "rcp_compress", "rcp_als", "rcp_expand",
+                     "rcp_decompose", "rcp_workspace_size", "rcp_destroy"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    for name in names:
+        assert hasattr(lib, name), name
+    nm = shutil.which("nm")
+    if nm:
+        out = subprocess.run([nm, "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                             text=True, check=True).stdout
+        exported = set(re.findall(r"\bT\s+(rcp_\w+)", out))
+        assert set(names) <= exported
+    # the binding declares exactly the header's functions
+    assert set(_lib.SIGNATURES) == set(names)
+
+
+def test_struct_layout_matches_header():
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "rcp.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(rcp_problem), offsetof(rcp_problem, dims),
+         offsetof(rcp_problem, max_iters), offsetof(rcp_problem, tol), offsetof(rcp_problem, seed),
+         sizeof(rcp_als_info), offsetof(rcp_als_info, rho));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "t")
+        subprocess.run([gcc, "-std=c99", "-I" + os.path.dirname(HEADER), c, "-o", exe], check=True)
+        vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True,
+                                               check=True).stdout.split()]
+    P, A = _lib.Problem, _lib.AlsInfo
+    assert vals == [ctypes.sizeof(P), P.dims.offset, P.max_iters.offset, P.tol.offset,
+                    P.seed.offset, ctypes.sizeof(A), A.rho.offset]
+
+
+def _ws(lib, prob):
+    n = ctypes.c_size_t(0)
+    st = lib.rcp_workspace_size(ctypes.byref(prob), ctypes.byref(n))
+    return st, n.value
+
+
+def test_workspace_size_valid_and_monotone(lib):
+    sizes = []
+    for d in (50, 100, 200, 400):
+        st, n = _ws(lib, _lib.make_problem((d, d, d), 20, 10, 2, 100, 0.0, 1))
+        assert st == _lib.RCP_OK and n > 0 and n % 256 == 0
+        sizes.append(n)
+    assert sizes == sorted(sizes) and len(set(sizes)) == len(sizes)
+    # 4-way and matrix problems are accepted
+    assert _ws(lib, _lib.make_problem((256, 256, 256, 64), 30, 15, 3, 200, 0.0, 1))[0] == _lib.RCP_OK
+    assert _ws(lib, _lib.make_problem((300, 40), 5, 5, 1, 10, 0.0, 1))[0] == _lib.RCP_OK
+
+
+@pytest.mark.parametrize("field,value", [
+    ("ndim", 1), ("ndim", 9), ("k", 0), ("p", -1), ("q", -1), ("k", 65), ("p", 60),
+    ("max_iters", 0), ("tol", -1.0), ("precision", 7), ("scheme", 3), ("reserved", 1),
+])
+def test_invalid_problems_rejected(lib, field, value):
+    prob = _lib.make_problem((40, 30, 20), 5, 5, 1, 10, 0.0, 1)
+    setattr(prob, field, value)
+    assert _ws(lib, prob)[0] == _lib.RCP_ERR_INVALID_ARG
+
+
+def test_invalid_dims_rejected(lib):
+    prob = _lib.make_problem((40, 30, 20), 5, 5, 1, 10, 0.0, 1)
+    prob.dims[1] = 0
+    assert _ws(lib, prob)[0] == _lib.RCP_ERR_INVALID_ARG
+    # k larger than a mode size: l_n = min(k+p, I_n) < k
+    prob = _lib.make_problem((40, 4, 20), 5, 5, 1, 10, 0.0, 1)
+    assert _ws(lib, prob)[0] == _lib.RCP_ERR_INVALID_ARG
+    # null arguments
+    assert lib.rcp_workspace_size(None, None) == _lib.RCP_ERR_INVALID_ARG
+
+
+def test_init_checks_before_touching_the_gpu(lib):
+    prob = _lib.make_problem((40, 30, 20), 5, 5, 1, 10, 0.0, 1)
+    h = ctypes.c_void_p(0)
+    st = lib.rcp_init(ctypes.byref(h), ctypes.byref(prob), None, 0, None)
+    assert st == _lib.RCP_ERR_WORKSPACE and not h.value
+    _, need = _ws(lib, prob)
+    st = lib.rcp_init(ctypes.byref(h), ctypes.byref(prob), ctypes.c_void_p(256), need - 1, None)
+    assert st == _lib.RCP_ERR_WORKSPACE
+    st = lib.rcp_init(ctypes.byref(h), ctypes.byref(prob), ctypes.c_void_p(4096 + 8), need, None)
+    assert st == _lib.RCP_ERR_WORKSPACE                  # misaligned
+    assert lib.rcp_init(None, ctypes.byref(prob), None, 0, None) == _lib.RCP_ERR_INVALID_ARG
+    bad = _lib.make_problem((40, 30, 20), 0, 5, 1, 10, 0.0, 1)
+    assert lib.rcp_init(ctypes.byref(h), ctypes.byref(bad), None, 0, None) == _lib.RCP_ERR_INVALID_ARG
+
+
+def test_null_plan_rejected_everywhere(lib):
+    dims = _lib.dims_array((4, 4, 4))
+    assert lib.rcp_sketch(None, None, dims, 0, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_compress(None, None, dims, 0, None, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_als(None, None, None, None, None, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_expand(None, None, None, None, None, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_decompose(None, None, None, None, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_norm2(None, None, 0, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_debug_omega(None, 0, 0, 1, 4, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_get_bases(None, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_get_core(None, None, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_destroy(None) == _lib.RCP_ERR_INVALID_ARG
+
+
+def test_status_strings(lib):
+    seen = set()
+    for code in range(6):
+        s = lib.rcp_status_string(code).decode()
+        assert s.startswith("RCP_")
+        seen.add(s)
+    assert len(seen) == 6
+    assert "unknown" in lib.rcp_status_string(99).decode()
+    assert b"gfx950" in lib.rcp_version()
+
+
+def test_product_path_fails_loudly_without_library(tmp_path):
+    with pytest.raises(RuntimeError, match="not built"):
+        saved = _lib._lib
+        _lib._lib = None
+        try:
+            _lib.load(str(tmp_path / "missing.so"))
+        finally:
+            _lib._lib = saved
