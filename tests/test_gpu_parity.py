@@ -93,7 +93,8 @@ def test_compress_matches_oracle(shape, mode):
     I = shape[mode]
     l = min(8, I)
     Qn = np.linalg.qr(np.random.default_rng(mode).standard_normal((I, l)))[0].astype(np.float32)
-    plan = rcpgpu.Plan(shape, min(4, l), l - min(4, l), 0, 1, 0.0, 1)
+    k = min(2, min(shape))
+    plan = rcpgpu.Plan(shape, k, 8 - k, 0, 1, 0.0, 1)
     out = _np(plan.compress(_dev(T), mode, _dev(Qn)))
     want = rcp.mode_product(T.astype(np.float64), Qn.astype(np.float64).T, mode)
     assert out.shape == want.shape
