@@ -31,7 +31,7 @@ struct Layout {
     int64_t Imax;
     int LPmax;
     // offsets (bytes)
-    size_t part, y64, qt, sq, norm, qb[RCP_MAX_NDIM], tb[2], zbuf, als, at[RCP_MAX_NDIM], lam,
+    size_t part, red1, y64, qt, sq, norm, qb[RCP_MAX_NDIM], tb[2], zbuf, als, at[RCP_MAX_NDIM], lam,
         raw, total;
     size_t part_elems, tb_elems[2], zbuf_elems, als_doubles;
     int64_t core_dims[RCP_MAX_NDIM];
@@ -105,6 +105,7 @@ Layout make_layout(const rcp_problem* p) {
     size_t off = 0;
     auto take = [&](size_t bytes) { const size_t o = off; off = align_up(off + bytes); return o; };
     L.part = take(L.part_elems * sizeof(float));
+    L.red1 = take((size_t)16 * L.Imax * L.LPmax * sizeof(double));
     L.y64 = take((size_t)L.Imax * L.LPmax * sizeof(double));
     L.qt = take((size_t)L.Imax * L.LPmax * sizeof(float));
     int nib = 1;
@@ -223,7 +224,8 @@ rcp_status reduce_y(rcp_plan_t* pl, int P, int64_t I, int LP, const double* sq, 
     const double bytes = (double)P * I * LP * 4.0 + (double)I * LP * 8.0;
     RCP_TRY(timed(pl, RCP_KERNEL_REDUCE, bytes, (double)P * I * LP, [&] {
         return launch_reduce_partials(pl->at<float>(pl->L.part), P, I * LP,
-                                      pl->at<double>(pl->L.y64), sq, nsq, sq_out, pl->stream);
+                                      pl->at<double>(pl->L.red1), pl->at<double>(pl->L.y64), sq,
+                                      nsq, sq_out, pl->stream);
     }));
     return RCP_OK;
 }
@@ -307,22 +309,15 @@ rcp_status als_impl(rcp_plan_t* pl, const float* core, float* const* At, float* 
     a.normX2 = normX2;
     a.lambda = lambda;
     a.info = info;
-    double* w = pl->at<double>(L.als);
     int64_t S = 1;
     for (int n = 0; n < L.N; ++n) S *= L.l[n];
-    const int64_t Lh = S / L.l[L.N - 1];
     const int R = L.R;
-    a.W = w; w += Lh * R;
-    a.KR = w; w += Lh * R;
-    a.G = w; w += (int64_t)L.N * R * R;
-    a.Mbuf = w; w += 2 * 64 * RCP_MAX_RANK;
-    a.Vbuf = w; w += (int64_t)R * R;
-    w += (int64_t)R * R;
-    a.Ebuf = w; w += 2 * 64 * 64;
-    a.misc = w;
-    // nominal algorithmic work: two contractions of the core with R columns per sweep
+    a.Mpart = pl->at<float>(L.als);
+    a.Ebuf = pl->at<double>(L.als) + (als_workspace_floats(L.N, L.l, R) + 1) / 2;
+    // nominal algorithmic work: N mode products of the core with R columns per sweep
     const double sweeps = (double)pl->prob.max_iters;
-    RCP_TRY(timed(pl, RCP_KERNEL_ALS, sweeps * 2.0 * 4.0 * (double)S, sweeps * 4.0 * (double)S * R,
+    RCP_TRY(timed(pl, RCP_KERNEL_ALS, sweeps * L.N * 4.0 * (double)S,
+                  sweeps * L.N * 2.0 * (double)S * R,
                   [&] { return launch_als(a, pl->stream); }));
     return RCP_OK;
 }
@@ -383,6 +378,7 @@ rcp_status rcp_init(rcp_plan* plan, const rcp_problem* prob, void* workspace,
     if (!valid_problem(prob)) return RCP_ERR_INVALID_ARG;
     if (prob->precision != RCP_PREC_FP32) return RCP_ERR_UNSUPPORTED;
     const Layout L = make_layout(prob);
+    if (!als_supported(L.N, L.l, L.R)) return RCP_ERR_UNSUPPORTED;
     if (workspace == nullptr || workspace_bytes < L.total || !aligned(workspace, kAlign))
         return RCP_ERR_WORKSPACE;
     int dev = 0;

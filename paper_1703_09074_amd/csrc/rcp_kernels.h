@@ -15,6 +15,8 @@ struct StreamGeom {
     int64_t L, I, Rr;
     int32_t caseB;         // 0: tiles are b-runs inside one a; 1: tiles are TA whole a-slabs
     int32_t TA;
+    int32_t vec4;          // case A rows can be read as aligned float4
+    int32_t pad_;
     int64_t tiles_per_a;   // case A
     int64_t ntiles;
 };
@@ -31,8 +33,9 @@ hipError_t launch_power_fused(const StreamGeom& g, int l, const float* Qt, float
                               hipStream_t s);
 hipError_t launch_contract_in(const StreamGeom& g, int l, const float* Qpadded, int lout,
                               float* out, int P, hipStream_t s);
-hipError_t launch_reduce_partials(const float* part, int P, int64_t count, double* Y,
-                                  const double* sq_part, int nsq, double* sq_out,
+int reduce_split(int P);
+hipError_t launch_reduce_partials(const float* part, int P, int64_t count, double* red1,
+                                  double* Y, const double* sq_part, int nsq, double* sq_out,
                                   hipStream_t s);
 hipError_t launch_sumsq(const float* x, int64_t count, double* part, int nblocks, double* out,
                         hipStream_t s);
@@ -61,16 +64,13 @@ struct AlsArgs {
     float* lambda;             // R
     rcp_als_info* info;
     // workspace
-    double* W;                 // Lh x R (Lh = S / l_{N-1})
-    double* KR;                // Lh x R
-    double* G;                 // N x R x R Grams
-    double* Mbuf;              // lmax x R
-    double* Vbuf;              // R x R
-    double* Ebuf;              // 2 x 64 x 64 Jacobi scratch
-    double* misc;              // 64 doubles
+    float* Mpart;              // 8 x 64 x 64 per-wavefront partial products
+    double* Ebuf;              // Jacobi (2 x 64 x 64) and Gauss-Jordan (64 x 128) scratch
 };
 hipError_t launch_als(const AlsArgs& a, hipStream_t s);
+size_t als_workspace_floats(int N, const int* l, int R);
 size_t als_workspace_doubles(int N, const int* l, int R);
+bool als_supported(int N, const int* l, int R);
 
 // back-projection (expand_kernel.hip)
 struct ExpandArgs {

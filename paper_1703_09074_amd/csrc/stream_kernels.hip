@@ -21,8 +21,10 @@
 namespace rcp {
 
 constexpr int JT = 32;            // tile width along the unfolding's columns
-constexpr int TS = JT + 1;        // LDS row stride of a tile
-constexpr int NT = 256;           // threads per workgroup (4 wavefronts)
+constexpr int TS = JT + 4;        // LDS row stride of a tile (16-byte aligned rows)
+constexpr int NT = 256;           // threads per workgroup of the small kernels
+constexpr int NTS = 512;          // threads per workgroup of the streaming kernels (8 wavefronts)
+constexpr int NWS = NTS / 64;
 
 struct TileInfo {
     int64_t j0;      // first unfolding column of the tile
@@ -55,17 +57,70 @@ __device__ __forceinline__ TileInfo tile_info(const StreamGeom& g, int64_t t) {
     return ti;
 }
 
-// Loads rows [i_lo, i_lo + nrows) of tile `ti` into Ts[r][jj] (row stride TS)
-// for r < rows_alloc: rows >= nrows and columns >= width are zero-filled.
-// Returns this thread's sum of squares of the loaded values (float64).
-__device__ __forceinline__ double load_tile(const StreamGeom& g, const TileInfo& ti,
-                                            int64_t i_lo, int nrows, int rows_alloc,
-                                            float* Ts, bool want_sq) {
-    double sq = 0.0;
+// Register staging of one tile (rows [i_lo, i_lo + nrows) of a row block of
+// 64*MB rows): MB float4 slots per thread.  Case A slot f = tid + s*NTS
+// covers row f / 8, columns 4*(f % 8) .. +3 (one 16-byte load when aligned);
+// case B slot covers 4 consecutive floats of the contiguous slab data.
+template <int MB>
+struct TileRegs {
+    float4 v[MB];
+};
+
+// Case A (Rr >= JT) staging: row f / 8, columns 4*(f % 8) .. +3 of slot
+// f = tid + s*NTS.  Case B tiles (small trailing modes) use load_tile.
+template <int MB>
+__device__ __forceinline__ void tile_issue(const StreamGeom& g, const TileInfo& ti, int64_t i_lo,
+                                           int nrows, TileRegs<MB>& pf) {
     const int tid = threadIdx.x;
-    // zero the padding first (columns >= width of valid rows, rows >= nrows)
+    const float* base = g.T + ((ti.a0 * g.I + i_lo) * g.Rr + ti.b0);
+#pragma unroll
+    for (int s = 0; s < MB; ++s) {
+        const int f = tid + s * NTS;
+        const int r = f >> 3, c0 = (f & 7) * 4;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r < nrows && c0 < ti.width) {
+            const float* p = base + (int64_t)r * g.Rr + c0;
+            if (g.vec4 && c0 + 4 <= ti.width) {
+                v = *reinterpret_cast<const float4*>(p);
+            } else {
+                v.x = p[0];
+                if (c0 + 1 < ti.width) v.y = p[1];
+                if (c0 + 2 < ti.width) v.z = p[2];
+                if (c0 + 3 < ti.width) v.w = p[3];
+            }
+        }
+        pf.v[s] = v;
+    }
+}
+
+// Writes the staged tile into Ts (64*MB rows x JT, stride TS); every cell is
+// written (zeros outside the valid rows / columns).  Returns the float64
+// sum of squares of the staged values.
+template <int MB>
+__device__ __forceinline__ double tile_commit(const TileRegs<MB>& pf, float* Ts, bool want_sq) {
+    const int tid = threadIdx.x;
+    double sq = 0.0;
+#pragma unroll
+    for (int s = 0; s < MB; ++s) {
+        const int f = tid + s * NTS;
+        const int r = f >> 3, c0 = (f & 7) * 4;
+        *reinterpret_cast<float4*>(Ts + r * TS + c0) = pf.v[s];
+        if (want_sq) {
+            const float4 v = pf.v[s];
+            sq += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+        }
+    }
+    return sq;
+}
+
+// Unstaged load of rows [i_lo, i_lo + nrows) into Ts (rows_alloc x JT),
+// zero-filled outside the valid cells; returns the float64 sum of squares.
+__device__ __forceinline__ double load_tile(const StreamGeom& g, const TileInfo& ti, int64_t i_lo,
+                                            int nrows, int rows_alloc, float* Ts, bool want_sq) {
+    const int tid = threadIdx.x;
+    double sq = 0.0;
     if (ti.width < JT || nrows < rows_alloc) {
-        for (int e = tid; e < rows_alloc * JT; e += NT) {
+        for (int e = tid; e < rows_alloc * JT; e += NTS) {
             const int r = e / JT, jj = e % JT;
             if (r >= nrows || jj >= ti.width) Ts[r * TS + jj] = 0.0f;
         }
@@ -73,37 +128,42 @@ __device__ __forceinline__ double load_tile(const StreamGeom& g, const TileInfo&
     if (!g.caseB) {
         const float* base = g.T + ((ti.a0 * g.I + i_lo) * g.Rr + ti.b0);
         const int total = nrows * JT;
-        for (int e = tid; e < total; e += NT) {
+        for (int e = tid; e < total; e += NTS) {
             const int r = e / JT, jj = e % JT;
             if (jj < ti.width) {
                 const float v = base[(int64_t)r * g.Rr + jj];
                 Ts[r * TS + jj] = v;
-                if (want_sq) sq += (double)v * (double)v;
+                if (want_sq) sq += (double)v * v;
             }
         }
     } else {
         const int rr = (int)g.Rr;
-        const int slab = nrows * rr;                 // floats per a-slab in this row block
+        const int slab = nrows * rr;
         const float inv_slab = 1.0f / (float)slab, inv_rr = 1.0f / (float)rr;
         const int total = ti.na * slab;
-        for (int e = tid; e < total; e += NT) {
+        for (int e = tid; e < total; e += NTS) {
             const int arel = small_div(e, slab, inv_slab);
             const int rem = e - arel * slab;
             const int r = small_div(rem, rr, inv_rr);
             const int b = rem - r * rr;
             const float v = g.T[((ti.a0 + arel) * g.I + i_lo) * g.Rr + rem];
             Ts[r * TS + arel * rr + b] = v;
-            if (want_sq) sq += (double)v * (double)v;
+            if (want_sq) sq += (double)v * v;
         }
     }
     return sq;
 }
 
-// Y[rows, 0:16*NB] += Ts[rows, 0:JT] * W[0:JT, 0:16*NB] for the MB row
-// blocks this wavefront owns (row block rb = wave + 4*m).
+// Y[rows, 0:16*NB] += Ts[rows, 0:JT] * W[0:JT, 0:16*NB] for the row blocks
+// this wavefront owns: rb = wave + 8*m, m < MH = ceil(MB/2) (4*MB row blocks
+// of 16 rows in all; blocks past the end are skipped).
+template <int MB>
+struct MHalf { static constexpr int v = (MB + 1) / 2; };
+
 template <int NB, int MB>
 __device__ __forceinline__ void tile_times_w(const float* Ts, const float* W, int ldw,
-                                             f32x4 (&acc)[MB][NB]) {
+                                             f32x4 (&acc)[MHalf<MB>::v][NB]) {
+    constexpr int MH = MHalf<MB>::v;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
@@ -112,72 +172,77 @@ __device__ __forceinline__ void tile_times_w(const float* Ts, const float* W, in
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) b[nb] = W[(k0 + lk) * ldw + nb * 16 + lr];
 #pragma unroll
-        for (int m = 0; m < MB; ++m) {
-            const float a = Ts[((wave + 4 * m) * 16 + lr) * TS + k0 + lk];
+        for (int m = 0; m < MH; ++m) {
+            const int rb = wave + NWS * m;
+            if (rb < 4 * MB) {
+                const float a = Ts[(rb * 16 + lr) * TS + k0 + lk];
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) acc[m][nb] = mfma16x16x4(a, b[nb], acc[m][nb]);
+                for (int nb = 0; nb < NB; ++nb) acc[m][nb] = mfma16x16x4(a, b[nb], acc[m][nb]);
+            }
         }
     }
 }
 
-// z[0:JT, 0:16*NB] (partial over rows [r_lo, r_hi) of the LDS tile) =
-// Ts[r, :]^T Qs[r, :].  The rows are split across the 4 wavefronts.
+// Partial z[jb*16 .. +16, 0:16*NB] = Ts[r, jb-block]^T Qs[r, :] over one
+// quarter of the rows: wavefront w takes column block jb = w / 4 and row
+// quarter w % 4 (rows is a multiple of 16).
 template <int NB>
 __device__ __forceinline__ void tile_t_times_q(const float* Ts, const float* Qs, int ldq,
-                                               int rows, f32x4 (&zacc)[2][NB]) {
+                                               int rows, f32x4 (&zacc)[NB]) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int per = rows / 4;                    // rows is a multiple of 16
-    const int r_lo = wave * per, r_hi = r_lo + per;
+    const int jb = wave >> 2, quarter = wave & 3;
+    const int per = rows / 4;
+    const int r_lo = quarter * per, r_hi = r_lo + per;
+#pragma unroll 2
     for (int k0 = r_lo; k0 < r_hi; k0 += 4) {
-        float b[NB];
+        const float a = Ts[(k0 + lk) * TS + jb * 16 + lr];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) b[nb] = Qs[(k0 + lk) * ldq + nb * 16 + lr];
-#pragma unroll
-        for (int jb = 0; jb < 2; ++jb) {
-            const float a = Ts[(k0 + lk) * TS + jb * 16 + lr];
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) zacc[jb][nb] = mfma16x16x4(a, b[nb], zacc[jb][nb]);
-        }
+        for (int nb = 0; nb < NB; ++nb)
+            zacc[nb] = mfma16x16x4(a, Qs[(k0 + lk) * ldq + nb * 16 + lr], zacc[nb]);
     }
 }
 
-// Store the wavefronts' partial z into zp[wave][jj][c] and sum into zs.
+// Store the wavefronts' partial z into zp[quarter][jj][c] and sum into zs.
 template <int NB>
-__device__ __forceinline__ void reduce_z(const f32x4 (&zacc)[2][NB], float* zp, float* zs) {
+__device__ __forceinline__ void reduce_z(const f32x4 (&zacc)[NB], float* zp, float* zs) {
     constexpr int LPc = NB * 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    float* my = zp + wave * JT * LPc;
+    const int jb = wave >> 2, quarter = wave & 3;
+    float* my = zp + quarter * JT * LPc;
 #pragma unroll
-    for (int jb = 0; jb < 2; ++jb)
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                my[(jb * 16 + 4 * lk + v) * LPc + nb * 16 + lr] = zacc[jb][nb][v];
+        for (int v = 0; v < 4; ++v)
+            my[(jb * 16 + 4 * lk + v) * LPc + nb * 16 + lr] = zacc[nb][v];
     __syncthreads();
-    for (int e = threadIdx.x; e < JT * LPc; e += NT)
+    for (int e = threadIdx.x; e < JT * LPc; e += NTS)
         zs[e] = zp[e] + zp[JT * LPc + e] + zp[2 * JT * LPc + e] + zp[3 * JT * LPc + e];
     __syncthreads();
 }
 
 template <int NB, int MB>
-__device__ __forceinline__ void store_partial(const f32x4 (&acc)[MB][NB], float* part,
+__device__ __forceinline__ void store_partial(const f32x4 (&acc)[MHalf<MB>::v][NB], float* part,
                                               int64_t I, int64_t row0) {
     constexpr int LPc = NB * 16;
+    constexpr int MH = MHalf<MB>::v;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
-    for (int m = 0; m < MB; ++m)
+    for (int m = 0; m < MH; ++m) {
+        const int rb = wave + NWS * m;
+        if (rb < 4 * MB) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t row = row0 + (wave + 4 * m) * 16 + 4 * lk + v;
-            if (row < I) {
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = row0 + rb * 16 + 4 * lk + v;
+                if (row < I) {
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) part[row * LPc + nb * 16 + lr] = acc[m][nb][v];
+                    for (int nb = 0; nb < NB; ++nb) part[row * LPc + nb * 16 + lr] = acc[m][nb][v];
+                }
             }
         }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -187,36 +252,40 @@ __device__ __forceinline__ void store_partial(const f32x4 (&acc)[MB][NB], float*
 // (L, LP, Rr) (power iteration with a stored Z).  Optional float64 partial
 // sum of squares of T (used for ||X||^2 in the first pass).
 
-template <int NB, int MB, bool GEN>
-__global__ __launch_bounds__(NT) void k_contract_out(StreamGeom g, int l, const float* Z,
+template <int NB, int MB, bool GEN, bool CB>
+__global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const float* Z,
                                                      uint64_t seed, uint32_t tag, float* part,
                                                      double* sq_part) {
     constexpr int LPc = NB * 16;
     constexpr int IB = 64 * MB;
-    extern __shared__ float smem[];
+    extern __shared__ __align__(16) float smem[];
     float* Ts = smem;                       // IB x TS
     float* Ws = Ts + IB * TS;               // JT x LPc
-    __shared__ double red[NT / 64];
+    __shared__ double red[NWS];
 
     const int64_t row0 = (int64_t)blockIdx.y * IB;
     const int64_t rows_left = g.I - row0;
     const int nrows = (int)(rows_left < IB ? rows_left : IB);
 
-    f32x4 acc[MB][NB];
+    f32x4 acc[MHalf<MB>::v][NB];
 #pragma unroll
-    for (int m = 0; m < MB; ++m)
+    for (int m = 0; m < MHalf<MB>::v; ++m)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     double sq = 0.0;
     const bool want_sq = sq_part != nullptr;
-    for (int64_t t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
+    TileRegs<MB> pf;
+    int64_t t = blockIdx.x;
+    if (!CB && t < g.ntiles) tile_issue<MB>(g, tile_info(g, t), row0, nrows, pf);
+    for (; t < g.ntiles; t += gridDim.x) {
         const TileInfo ti = tile_info(g, t);
         __syncthreads();
-        sq += load_tile(g, ti, row0, nrows, IB, Ts, want_sq);
+        if (CB) sq += load_tile(g, ti, row0, nrows, IB, Ts, want_sq);
+        else sq += tile_commit<MB>(pf, Ts, want_sq);
         if (GEN) {
             constexpr int NG = LPc / 4;
-            for (int e = threadIdx.x; e < JT * NG; e += NT) {
+            for (int e = threadIdx.x; e < JT * NG; e += NTS) {
                 const int jj = e / NG, gi = e % NG;
                 float z[4] = {0.f, 0.f, 0.f, 0.f};
                 if (jj < ti.width) omega4(seed, tag, (uint64_t)(ti.j0 + jj), (uint32_t)gi, z);
@@ -227,7 +296,7 @@ __global__ __launch_bounds__(NT) void k_contract_out(StreamGeom g, int l, const 
                 }
             }
         } else {
-            for (int e = threadIdx.x; e < JT * LPc; e += NT) {
+            for (int e = threadIdx.x; e < JT * LPc; e += NTS) {
                 const int jj = e % JT, c = e / JT;
                 float v = 0.0f;
                 if (jj < ti.width) {
@@ -239,6 +308,8 @@ __global__ __launch_bounds__(NT) void k_contract_out(StreamGeom g, int l, const 
                 Ws[jj * LPc + c] = v;
             }
         }
+        const int64_t tn = t + gridDim.x;
+        if (!CB && tn < g.ntiles) tile_issue<MB>(g, tile_info(g, tn), row0, nrows, pf);
         __syncthreads();
         tile_times_w<NB, MB>(Ts, Ws, LPc, acc);
     }
@@ -256,43 +327,61 @@ __global__ __launch_bounds__(NT) void k_contract_out(StreamGeom g, int l, const 
 // invertible upper-triangular right factor, which the QR of the next sketch
 // absorbs, so it is not applied.
 
-template <int NB, int MB>
-__global__ __launch_bounds__(NT) void k_power_fused(StreamGeom g, const float* Qt, float* part) {
+template <int NB, int MB, bool FUSED, bool CB>
+__global__ __launch_bounds__(NTS) void k_power_fused(StreamGeom g, const float* Qt, float* part,
+                                                    int lout, float* out) {
     constexpr int LPc = NB * 16;
     constexpr int IB = 64 * MB;
-    extern __shared__ float smem[];
+    extern __shared__ __align__(16) float smem[];
     float* Ts = smem;                       // IB x TS
     float* Qs = Ts + IB * TS;               // IB x LPc
     float* zp = Qs + IB * LPc;              // 4 x JT x LPc
     float* zs = zp + 4 * JT * LPc;          // JT x LPc
 
     const int I = (int)g.I;
-    for (int e = threadIdx.x; e < IB * LPc; e += NT) {
+    for (int e = threadIdx.x; e < IB * LPc; e += NTS) {
         const int r = e / LPc;
         Qs[e] = (r < I) ? Qt[e] : 0.0f;
     }
 
-    f32x4 acc[MB][NB];
+    f32x4 acc[MHalf<MB>::v][NB];
 #pragma unroll
-    for (int m = 0; m < MB; ++m)
+    for (int m = 0; m < MHalf<MB>::v; ++m)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int64_t t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
+    TileRegs<MB> pf;
+    int64_t t = blockIdx.x;
+    if (!CB && t < g.ntiles) tile_issue<MB>(g, tile_info(g, t), 0, I, pf);
+    for (; t < g.ntiles; t += gridDim.x) {
         const TileInfo ti = tile_info(g, t);
         __syncthreads();
-        load_tile(g, ti, 0, I, IB, Ts, false);
+        if (CB) load_tile(g, ti, 0, I, IB, Ts, false);
+        else tile_commit<MB>(pf, Ts, false);
+        const int64_t tn = t + gridDim.x;
+        if (!CB && tn < g.ntiles) tile_issue<MB>(g, tile_info(g, tn), 0, I, pf);
         __syncthreads();
-        f32x4 zacc[2][NB];
+        f32x4 zacc[NB];
 #pragma unroll
-        for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) zacc[jb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int nb = 0; nb < NB; ++nb) zacc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
         tile_t_times_q<NB>(Ts, Qs, LPc, IB, zacc);
         reduce_z<NB>(zacc, zp, zs);
-        tile_times_w<NB, MB>(Ts, zs, LPc, acc);
+        if (FUSED) {
+            tile_times_w<NB, MB>(Ts, zs, LPc, acc);
+        } else {
+            // mode product: write z^T into the (L, lout, Rr) output
+            for (int e = threadIdx.x; e < lout * JT; e += NTS) {
+                const int c = e / JT, jj = e % JT;
+                if (jj < ti.width) {
+                    int64_t a, b;
+                    if (!g.caseB) { a = ti.a0; b = ti.b0 + jj; }
+                    else { a = ti.a0 + jj / g.Rr; b = jj % g.Rr; }
+                    out[(a * lout + c) * g.Rr + b] = zs[jj * LPc + c];
+                }
+            }
+        }
     }
-    store_partial<NB, MB>(acc, part + (int64_t)blockIdx.x * g.I * LPc, g.I, 0);
+    if (FUSED) store_partial<NB, MB>(acc, part + (int64_t)blockIdx.x * g.I * LPc, g.I, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -303,7 +392,7 @@ __global__ __launch_bounds__(NT) void k_power_fused(StreamGeom g, const float* Q
 constexpr int IC = 128;
 
 template <int NB>
-__global__ __launch_bounds__(NT) void k_contract_in(StreamGeom g, const float* Q, int lout,
+__global__ __launch_bounds__(NTS) void k_contract_in(StreamGeom g, const float* Q, int lout,
                                                     float* out) {
     constexpr int LPc = NB * 16;
     extern __shared__ float smem[];
@@ -314,17 +403,15 @@ __global__ __launch_bounds__(NT) void k_contract_in(StreamGeom g, const float* Q
 
     for (int64_t t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
         const TileInfo ti = tile_info(g, t);
-        f32x4 zacc[2][NB];
+        f32x4 zacc[NB];
 #pragma unroll
-        for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) zacc[jb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int nb = 0; nb < NB; ++nb) zacc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
         for (int64_t i_lo = 0; i_lo < g.I; i_lo += IC) {
             const int64_t left = g.I - i_lo;
             const int nrows = (int)(left < IC ? left : IC);
             __syncthreads();
             load_tile(g, ti, i_lo, nrows, IC, Ts, false);
-            for (int e = threadIdx.x; e < IC * LPc; e += NT) {
+            for (int e = threadIdx.x; e < IC * LPc; e += NTS) {
                 const int r = e / LPc;
                 Qs[e] = (r < nrows) ? Q[(i_lo + r) * LPc + (e - r * LPc)] : 0.0f;
             }
@@ -333,7 +420,7 @@ __global__ __launch_bounds__(NT) void k_contract_in(StreamGeom g, const float* Q
         }
         reduce_z<NB>(zacc, zp, zs);
         // write z^T into the (L, lout, Rr) output
-        for (int e = threadIdx.x; e < lout * JT; e += NT) {
+        for (int e = threadIdx.x; e < lout * JT; e += NTS) {
             const int c = e / JT, jj = e % JT;
             if (jj < ti.width) {
                 int64_t a, b;
@@ -346,17 +433,32 @@ __global__ __launch_bounds__(NT) void k_contract_in(StreamGeom g, const float* Q
 }
 
 // ---------------------------------------------------------------------------
-// Deterministic reduction of the per-workgroup partials:
-// Y[i, c] = sum_p part[p, i, c] in float64, fixed order.  Block 0 also sums
-// the optional sum-of-squares partials into *sq_out.
+// Deterministic reduction of the per-workgroup partials, in two stages so
+// that enough workgroups stream the partial buffer:
+//   stage 1: red1[y, e] = sum_{p in split y} part[p, e]        (float64)
+//   stage 2: Y[e] = sum_y red1[y, e]
+// Block 0 of stage 2 also sums the optional sum-of-squares partials.
 
-__global__ __launch_bounds__(NT) void k_reduce_partials(const float* part, int P, int64_t count,
-                                                        double* Y, const double* sq_part,
-                                                        int nsq, double* sq_out) {
+constexpr int kRedSplit = 16;
+
+__global__ __launch_bounds__(NT) void k_reduce_stage1(const float* part, int P, int64_t count,
+                                                      double* red1) {
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= count) return;
+    const int y = blockIdx.y, ny = gridDim.y;
+    const int p0 = (int)((int64_t)P * y / ny), p1 = (int)((int64_t)P * (y + 1) / ny);
+    double s = 0.0;
+    for (int p = p0; p < p1; ++p) s += (double)part[(int64_t)p * count + e];
+    red1[(int64_t)y * count + e] = s;
+}
+
+__global__ __launch_bounds__(NT) void k_reduce_stage2(const double* red1, int ny, int64_t count,
+                                                      double* Y, const double* sq_part, int nsq,
+                                                      double* sq_out) {
     const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (e < count) {
         double s = 0.0;
-        for (int p = 0; p < P; ++p) s += (double)part[(int64_t)p * count + e];
+        for (int y = 0; y < ny; ++y) s += red1[(int64_t)y * count + e];
         Y[e] = s;
     }
     if (sq_part != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -424,6 +526,7 @@ StreamGeom make_geom(const float* T, const int64_t* dims, int ndim, int mode) {
     for (int m = 0; m < mode; ++m) g.L *= dims[m];
     for (int m = mode + 1; m < ndim; ++m) g.Rr *= dims[m];
     g.I = dims[mode];
+    g.vec4 = ((g.Rr % 4) == 0 && ((uintptr_t)T % 16) == 0) ? 1 : 0;
     if (g.Rr >= JT) {
         g.caseB = 0;
         g.TA = 1;
@@ -465,11 +568,11 @@ template <int NB, int MB, bool GEN>
 static hipError_t launch_co(dim3 grid, size_t smem, hipStream_t s, const StreamGeom& g, int l,
                             const float* Z, uint64_t seed, uint32_t tag, float* part,
                             double* sq) {
-    auto k = k_contract_out<NB, MB, GEN>;
+    auto k = g.caseB ? k_contract_out<NB, MB, GEN, true> : k_contract_out<NB, MB, GEN, false>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)smem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, grid, dim3(NT), smem, s, g, l, Z, seed, tag, part, sq);
+    hipLaunchKernelGGL(k, grid, dim3(NTS), smem, s, g, l, Z, seed, tag, part, sq);
     return hipGetLastError();
 }
 
@@ -525,14 +628,14 @@ bool power_fused_fits(int64_t I, int l, size_t smem_limit) {
     return power_fused_smem(lp_blocks(l), MBv) <= smem_limit;
 }
 
-template <int NB, int MB>
+template <int NB, int MB, bool FUSED>
 static hipError_t launch_pf(int P, size_t smem, hipStream_t s, const StreamGeom& g,
-                            const float* Qt, float* part) {
-    auto k = k_power_fused<NB, MB>;
+                            const float* Qt, float* part, int lout, float* out) {
+    auto k = g.caseB ? k_power_fused<NB, MB, FUSED, true> : k_power_fused<NB, MB, FUSED, false>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)smem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((unsigned)P), dim3(NT), smem, s, g, Qt, part);
+    hipLaunchKernelGGL(k, dim3((unsigned)P), dim3(NTS), smem, s, g, Qt, part, lout, out);
     return hipGetLastError();
 }
 
@@ -542,7 +645,7 @@ hipError_t launch_power_fused(const StreamGeom& g, int l, const float* Qt, float
     const int MBv = (int)((g.I + 63) / 64);
     const size_t smem = power_fused_smem(NBv, MBv);
     hipError_t e = hipSuccess;
-    RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_pf<NB, MB>(P, smem, s, g, Qt, part))));
+    RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_pf<NB, MB, true>(P, smem, s, g, Qt, part, 0, nullptr))));
     return e;
 }
 
@@ -553,24 +656,39 @@ static hipError_t launch_ci(int P, size_t smem, hipStream_t s, const StreamGeom&
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)smem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((unsigned)P), dim3(NT), smem, s, g, Q, lout, out);
+    hipLaunchKernelGGL(k, dim3((unsigned)P), dim3(NTS), smem, s, g, Q, lout, out);
     return hipGetLastError();
 }
 
+// T x_n Q^T (or Z = T_(n)^T Q): the whole basis resident in LDS when the
+// mode is short enough, else streamed in row chunks.
 hipError_t launch_contract_in(const StreamGeom& g, int l, const float* Qpadded, int lout,
                               float* out, int P, hipStream_t s) {
     const int NBv = lp_blocks(l);
-    const size_t smem = contract_in_smem(NBv);
     hipError_t e = hipSuccess;
+    if (power_fused_fits(g.I, l, 160 * 1024)) {
+        const int MBv = (int)((g.I + 63) / 64);
+        const size_t smem = power_fused_smem(NBv, MBv);
+        RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_pf<NB, MB, false>(P, smem, s, g, Qpadded, nullptr, lout, out))));
+        return e;
+    }
+    const size_t smem = contract_in_smem(NBv);
     RCP_NB_SWITCH(NBv, e = (launch_ci<NB>(P, smem, s, g, Qpadded, lout, out)));
     return e;
 }
 
-hipError_t launch_reduce_partials(const float* part, int P, int64_t count, double* Y,
-                                  const double* sq_part, int nsq, double* sq_out,
+int reduce_split(int P) { return P < kRedSplit ? P : kRedSplit; }
+
+hipError_t launch_reduce_partials(const float* part, int P, int64_t count, double* red1,
+                                  double* Y, const double* sq_part, int nsq, double* sq_out,
                                   hipStream_t s) {
     const unsigned blocks = (unsigned)((count + NT - 1) / NT);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks > 0 ? blocks : 1), dim3(NT), 0, s, part, P,
+    const int ny = reduce_split(P);
+    hipLaunchKernelGGL(k_reduce_stage1, dim3(blocks > 0 ? blocks : 1, (unsigned)ny), dim3(NT), 0, s,
+                       part, P, count, red1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_stage2, dim3(blocks > 0 ? blocks : 1), dim3(NT), 0, s, red1, ny,
                        count, Y, sq_part, nsq, sq_out);
     return hipGetLastError();
 }
