@@ -3,16 +3,18 @@
 // sequence of dependent least-squares updates, so the whole sweep loop runs
 // in one persistent workgroup, with the stopping rule on the device.
 //
-// Per sweep the mode products B_(n) KR(Ã_{m != n}) use one split of the
-// modes, H1 = {0..N-2} and the last mode, so that only two contractions of
-// the full core are needed per sweep (instead of N):
-//   W[rho, r]     = sum_k B[rho, k] Ã_{N-1}[k, r]                (rho over H1)
-//   M_n[i, r]     = sum_{rho: i_n(rho)=i} W[rho, r] prod_{m in H1, m!=n} Ã_m[i_m(rho), r]
-//   M_{N-1}[i, r] = sum_rho B[rho, i] prod_{m in H1} Ã_m[i_m(rho), r]
-// Each M_n is exactly the mode-n product of the definition, computed with
-// the factors Algorithm 2 uses at that point (earlier modes already updated).
-// The two core contractions run on the matrix cores (FP32 operands, FP32
-// accumulation); Grams, solves, norms and the fit are float64.
+// Per mode n of a sweep:
+//   M_n = B_(n) KR(Ã_{m != n})   on the matrix cores (float32 operands and
+//                                accumulation), the Khatri-Rao operand formed
+//                                on the fly from the factors in LDS;
+//   V   = *_{m != n} G_m         (Hadamard product of the Gram matrices);
+//   Ã_n = M_n V^{-1}             by Gauss-Jordan elimination on [V | M_n^T]
+//                                (V is symmetric positive definite, so no
+//                                pivoting), the Moore-Penrose pseudo-inverse
+//                                when a pivot falls below 1e-13 of diag(V);
+//   columns of Ã_n scaled to unit norm (the norms are lambda), G_n updated.
+// Grams, solves, norms and the fit are float64; the factors feeding the
+// matrix cores are float32.
 
 #include "rcp_device.h"
 #include "rcp_kernels.h"
@@ -26,8 +28,16 @@ __device__ unsigned long long g_als_stamps[64];
         __syncthreads();                                                                   \
         if (threadIdx.x == 0 && it_dbg < 3) g_als_stamps[it_dbg * 16 + (slot)] = wall_clock64(); \
     } while (0)
+__device__ unsigned long long g_als_ns[64];
+#define ALS_SUB(slot)                                                                      \
+    do {                                                                                   \
+        __syncthreads();                                                                   \
+        if (threadIdx.x == 0 && n == 0 && dbg_it < 3)                                      \
+            g_als_stamps[dbg_it * 16 + (slot)] = wall_clock64();                           \
+    } while (0)
 #else
 #define ALS_STAMP(slot) do {} while (0)
+#define ALS_SUB(slot) do {} while (0)
 #endif
 
 constexpr int ANT = 512;
@@ -36,6 +46,7 @@ constexpr double kPivotRtol = 1e-13;
 constexpr int kJacobiMaxSweeps = 40;
 constexpr int kEigLd = 64;
 constexpr size_t kAlsLds = 160 * 1024 - 4096;   // dynamic LDS budget
+constexpr int kAlsPartFloats = (ANW - 1) * 256;  // partial 16 x 16 blocks of the mode products
 
 struct AlsCtx {
     int N, R;
@@ -180,380 +191,378 @@ __device__ __forceinline__ bool eig_init(const AlsCtx& c, const float* Bg, int n
     return ok;
 }
 
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// G_n = Ã_n^T Ã_n in float64 from the float32 factor.
-__device__ __forceinline__ void gram_of(const AlsCtx& c, int n, double* G) {
-    const int R = c.R, ln = c.l[n];
-    const float* A = c.fac(n);
-    for (int e = threadIdx.x; e < R * R; e += ANT) {
-        const int r = e / R, s = e - r * R;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        int i = 0;
-        for (; i + 4 <= ln; i += 4) {
-            a0 += (double)A[i * R + r] * (double)A[i * R + s];
-            a1 += (double)A[(i + 1) * R + r] * (double)A[(i + 1) * R + s];
-            a2 += (double)A[(i + 2) * R + r] * (double)A[(i + 2) * R + s];
-            a3 += (double)A[(i + 3) * R + r] * (double)A[(i + 3) * R + s];
-        }
-        for (; i < ln; ++i) a0 += (double)A[i * R + r] * (double)A[i * R + s];
-        G[e] = (a0 + a1) + (a2 + a3);
-    }
-}
-
-// Wavefront 0 solves V X^T = M^T (V symmetric positive definite, R x R) by
-// Gauss-Jordan elimination on the augmented matrix [V | M^T] held in LDS
-// (row stride 128): lane c owns columns c and c + 64, rows are processed
-// four at a time so their LDS accesses overlap.  The loop form keeps the
-// code small (this kernel is one workgroup walking long sequences, so
-// instruction-cache misses matter more than unrolling).  On return X
-// (ln x R, row-major) is in Xo.  Returns 0 when a pivot falls below
-// kPivotRtol times the largest diagonal entry of V (the caller then takes
-// the pseudo-inverse).
-__device__ __forceinline__ int wave_gj_solve(double* V, const double* M, double* Aug, double* Xo,
-                                             int R, int ln) {
-    const int lane = threadIdx.x;
-    const int W = R + ln;
-    for (int i = 0; i < R; ++i)
-        for (int cc = lane; cc < W; cc += 64)
-            Aug[i * 128 + cc] = (cc < R) ? V[i * R + cc] : M[(cc - R) * R + i];
-    double maxd = (lane < R) ? V[lane * R + lane] : 0.0;
-    for (int o = 32; o > 0; o >>= 1) maxd = fmax(maxd, __shfl_xor(maxd, o, 64));
-    const double thr = kPivotRtol * maxd;
-    wave_lds_sync();
-    int ok = 1;
-    for (int j = 0; j < R; ++j) {
-        const double piv = Aug[j * 128 + j];
-        ok &= (piv > thr) ? 1 : 0;
-        const double ip = 1.0 / fmax(piv, thr);
-        for (int cc = lane; cc < W; cc += 64) {
-            if (cc <= j) continue;
-            const double pr = Aug[j * 128 + cc] * ip;
-            int i = 0;
-            for (; i + 4 <= R; i += 4) {
-                const double f0 = Aug[i * 128 + j], f1 = Aug[(i + 1) * 128 + j];
-                const double f2 = Aug[(i + 2) * 128 + j], f3 = Aug[(i + 3) * 128 + j];
-                const double a0 = Aug[i * 128 + cc], a1 = Aug[(i + 1) * 128 + cc];
-                const double a2 = Aug[(i + 2) * 128 + cc], a3 = Aug[(i + 3) * 128 + cc];
-                Aug[i * 128 + cc] = (i == j) ? pr : a0 - f0 * pr;
-                Aug[(i + 1) * 128 + cc] = (i + 1 == j) ? pr : a1 - f1 * pr;
-                Aug[(i + 2) * 128 + cc] = (i + 2 == j) ? pr : a2 - f2 * pr;
-                Aug[(i + 3) * 128 + cc] = (i + 3 == j) ? pr : a3 - f3 * pr;
-            }
-            for (; i < R; ++i) {
-                const double f = Aug[i * 128 + j], av = Aug[i * 128 + cc];
-                Aug[i * 128 + cc] = (i == j) ? pr : av - f * pr;
-            }
-        }
-        wave_lds_sync();
-    }
-    if (!ok) return 0;
-    for (int cc = 0; cc < R; ++cc)
-        for (int i = lane; i < ln; i += 64) Xo[i * R + cc] = Aug[cc * 128 + R + i];
-    return 1;
-}
-
-// Exact quotient of a non-negative int below 2^31 by a positive divisor,
-// from a float64 reciprocal and one correction step.
-__device__ __forceinline__ int div_exact(int a, int d, double inv_d) {
-    int q = (int)((double)a * inv_d);
-    const int r = a - q * d;
-    if (r < 0) --q;
-    else if (r >= d) ++q;
-    return q;
-}
-
-// C = A (R x R) * Bm (R x R), float64, all threads; row-major, LDS.
-__device__ __forceinline__ void small_gemm(const double* A, const double* Bm, double* C, int R) {
-    for (int e = threadIdx.x; e < R * R; e += ANT) {
-        const int i = e / R, j = e - (e / R) * R;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int k = 0;
-        for (; k + 4 <= R; k += 4) {
-            s0 += A[i * R + k] * Bm[k * R + j];
-            s1 += A[i * R + k + 1] * Bm[(k + 1) * R + j];
-            s2 += A[i * R + k + 2] * Bm[(k + 2) * R + j];
-            s3 += A[i * R + k + 3] * Bm[(k + 3) * R + j];
-        }
-        for (; k < R; ++k) s0 += A[i * R + k] * Bm[k * R + j];
-        C[e] = (s0 + s1) + (s2 + s3);
-    }
-}
-
-__device__ __forceinline__ double block_max(double v, double* red) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+// ---------------------------------------------------------------------------
+// M_n = B_(n) KR(Ã_{m != n}) on the matrix cores.
+//
+// The core is row-major over (i_0, ..., i_{N-1}); for mode n the contraction
+// index k runs over the other modes in increasing order (the row order of the
+// Khatri-Rao product with the first factor slowest, Section 2.3), so
+// B_(n)[i, k] sits at  i * st_n + sum_m d_m(k) st_m  with st_m the stride of
+// mode m and d_m(k) the mixed-radix digits of k.  k splits into an outer part
+// (all other modes but the last) and the inner digit of the last other mode:
+// per outer index the Khatri-Rao row is the product of the outer factor rows
+// (formed once) and the inner factor row, and the inner loop is a plain
+// strided walk.  The output (l_n x R) is tiled in 16 x 16 blocks; a work unit
+// is one block over one slice of the outer index, the units are spread over
+// the eight wavefronts and slices of one block are summed through LDS.  Lane
+// (lr, lk) of a v_mfma_f32_16x16x4_f32 feeds row lr of the B_(n) tile and
+// column lr of the Khatri-Rao tile at inner index k0 + lk.
+//
+// NN - 1 digit slots, N - 1 of them real; the NN - N leading slots are
+// padding of size 1 and stride 0 whose factor reads hit a row of ones, so one
+// instantiation serves every order up to NN.  Writes M (l_n x R) and its
+// transpose into the right part of the augmented system.
+template <int NN>
+__device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, const int* st,
+                                       const float* ones, float* P, double* M, double* Xt,
+                                       int ldx) {
+    constexpr int D = NN - 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int N = c.N, R = c.R, ln = c.l[n];
+    const int stn = st[n];
+    int lo[D], so[D], fo[D];
+    int Ko = 1;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    __syncthreads();
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    double t = red[0];
-    for (int i = 1; i < ANW; ++i) t = fmax(t, red[i]);
-    return t;
-}
-
-constexpr int kNsMaxIters = 60;
-constexpr double kNsTol = 1e-11;
-
-// V^{-1} for the symmetric positive definite V (R x R, LDS) by Newton-Schulz
-// iteration X <- X (2I - V X) (Schulz 1933), started from Xi when `warm`
-// (the previous sweep's inverse for the same mode) and otherwise from
-// V / ||V||_inf^2, which converges for every non-singular V.  Stops once
-// max |V X - I| <= kNsTol, after one more step.  Returns 1 and the inverse in
-// Xi on convergence, 0 otherwise.  All threads; T, X2 are R x R scratch.
-__device__ __forceinline__ int ns_inverse(const double* V, double* Xi, double* T, double* X2, int R,
-                                          bool warm, double* red) {
-    const int tid = threadIdx.x;
-    double rs = 0.0;
-    for (int i = tid; i < R; i += ANT) {
-        double s = 0.0;
-        for (int k = 0; k < R; ++k) s += fabs(V[i * R + k]);
-        rs = fmax(rs, s);
-    }
-    const double ninf = block_max(rs, red);
-    if (!(ninf > 0.0) || !isfinite(ninf)) return 0;
-    const double scale = 1.0 / (ninf * ninf);
-    if (!warm)
-        for (int e = tid; e < R * R; e += ANT) Xi[e] = V[e] * scale;
-    __syncthreads();
-    bool restarted = !warm;
-    for (int k = 0; k < kNsMaxIters; ++k) {
-        small_gemm(V, Xi, T, R);
-        __syncthreads();
-        double dev = 0.0;
-        for (int e = tid; e < R * R; e += ANT) {
-            const int i = e / R, j = e - (e / R) * R;
-            dev = fmax(dev, fabs(T[e] - (i == j ? 1.0 : 0.0)));
+    for (int s = 0; s < D; ++s) {
+        const int j = s - (NN - N);             // index among the real other modes
+        if (j < 0) {
+            lo[s] = 1; so[s] = 0; fo[s] = (int)(ones - c.fbase);
+        } else {
+            const int m = (j < n) ? j : j + 1;
+            lo[s] = c.l[m]; so[s] = st[m]; fo[s] = c.foff[m];
+            if (s < D - 1) Ko *= lo[s];
         }
-        const double r = block_max(dev, red);
-        if (!isfinite(r)) return 0;
-        if (!restarted && r > 0.5) {
-            // warm start too far from the new inverse: restart from the scaled V
-            for (int e = tid; e < R * R; e += ANT) Xi[e] = V[e] * scale;
-            restarted = true;
-            __syncthreads();
-            continue;
-        }
-        // X2 = 2 X - X T
-        small_gemm(Xi, T, X2, R);
-        __syncthreads();
-        for (int e = tid; e < R * R; e += ANT) Xi[e] = 2.0 * Xi[e] - X2[e];
-        __syncthreads();
-        if (r <= kNsTol) return 1;
     }
-    return 0;
-}
-
-// Ã_n = M V^+ with V = *_{m != n} G_m, then column normalisation; the factor
-// lands in c.fac(n) and its Gram in G_n.  Returns RCP_INFO_* bits.
-__device__ __forceinline__ int solve_update(const AlsCtx& c, int n, double* G, const double* M,
-                                            double* X, double* V, double* Xi, double* T,
-                                            double* X2, int* ns_valid, double* Aug, double* E,
-                                            double* Ev, double* lam, int* flag) {
-    const int tid = threadIdx.x, R = c.R, ln = c.l[n];
-    int status = 0;
-    for (int e = tid; e < R * R; e += ANT) {
-        double v = 1.0;
-        for (int m = 0; m < c.N; ++m)
-            if (m != n) v *= G[m * R * R + e];
-        V[e] = v;
-    }
-    __syncthreads();
-    double* Xin = Xi + n * R * R;
-    int ok = ns_inverse(V, Xin, T, X2, R, ns_valid[n] != 0, c.red);
-    __syncthreads();
-    if (ok) {
-        if (tid == 0) ns_valid[n] = 1;
-        // X = M V^{-1}
-        for (int e = tid; e < ln * R; e += ANT) {
-            const int i = e / R, s = e - (e / R) * R;
-            double a0 = 0.0, a1 = 0.0;
-            int r = 0;
-            for (; r + 2 <= R; r += 2) {
-                a0 += M[i * R + r] * Xin[r * R + s];
-                a1 += M[i * R + r + 1] * Xin[(r + 1) * R + s];
+    const int Kl = lo[D - 1], sl = so[D - 1];
+    const float* fin = c.fbase + fo[D - 1];
+    const int nib = (ln + 15) >> 4, ncb = (R + 15) >> 4;
+    const int blocks = nib * ncb;
+    const int kp = (blocks >= ANW) ? 1 : min(ANW / blocks, Ko);
+    const int units = blocks * kp;
+    const int per = (Ko + kp - 1) / kp;
+    f32x4 keep = {0.f, 0.f, 0.f, 0.f};
+    int keep_blk = -1;
+    for (int u = wave; u < units; u += ANW) {
+        const int blk = u % blocks, part = u / blocks;
+        const int ib = blk / ncb, cb = blk - (blk / ncb) * ncb;
+        const int o_lo = part * per;
+        const int o_hi = min(Ko, o_lo + per);
+        const int i = ib * 16 + lr, col = cb * 16 + lr;
+        const bool rv = i < ln, cv = col < R;
+        const int ioff = (rv ? i : 0) * stn;   // rows past l_n only feed discarded outputs
+        const int ccol = cv ? col : 0;
+        // outer digits of o_lo
+        int d[D];
+        {
+            int rem = o_lo;
+#pragma unroll
+            for (int s = D - 2; s >= 0; --s) {
+                const int q = rem / lo[s];
+                d[s] = rem - q * lo[s];
+                rem = q;
             }
-            if (r < R) a0 += M[i * R + r] * Xin[r * R + s];
-            X[e] = a0 + a1;
         }
-    } else {
-        if (tid == 0) ns_valid[n] = 0;
-        if (tid < 64) {
-            const int okg = wave_gj_solve(V, M, Aug, X, R, ln);
-            if (tid == 0) *flag = okg;
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        for (int o = o_lo; o < o_hi; ++o) {
+            int boff = ioff;
+            float ob = cv ? 1.0f : 0.0f;
+#pragma unroll
+            for (int s = 0; s < D - 1; ++s) {
+                boff += d[s] * so[s];
+                ob *= c.fbase[fo[s] + d[s] * R + ccol];
+            }
+            const float* bp = B + boff;
+            // wave-uniform trip counts: the matrix-core instructions run with all lanes
+            int k0 = 0;
+            for (; k0 + 8 <= Kl; k0 += 8) {
+                const int kl = k0 + lk;
+                const float a0 = bp[kl * sl];
+                const float b0 = fin[kl * R + ccol];
+                const float a1 = bp[(kl + 4) * sl];
+                const float b1 = fin[(kl + 4) * R + ccol];
+                acc0 = mfma16x16x4(a0, ob * b0, acc0);
+                acc1 = mfma16x16x4(a1, ob * b1, acc1);
+            }
+            for (; k0 < Kl; k0 += 4) {
+                const int kl = k0 + lk;
+                float a0 = 0.0f, b0 = 0.0f;
+                if (kl < Kl) { a0 = bp[kl * sl]; b0 = fin[kl * R + ccol]; }
+                acc0 = mfma16x16x4(a0, ob * b0, acc0);
+            }
+            // next outer index
+#pragma unroll
+            for (int s = D - 2; s >= 0; --s) {
+                d[s] += 1;
+                if (d[s] < lo[s]) break;
+                d[s] = 0;
+            }
         }
-        __syncthreads();
-        if (!*flag) {
-            // Moore-Penrose pseudo-inverse through the eigen-decomposition
-            status |= RCP_INFO_PINV_FALLBACK;
-            for (int e = tid; e < R * R; e += ANT) E[(e / R) * kEigLd + (e % R)] = V[e];
-            __syncthreads();
-            jacobi_eig(E, Ev, R, c.red, c.sh);
-            double wmax = 0.0;
-            for (int f = 0; f < R; ++f) wmax = fmax(wmax, fabs(E[f * kEigLd + f]));
-            const double cut = kPivotRtol * wmax;
-            for (int e = tid; e < R * R; e += ANT) {
-                const int r = e / R, s = e % R;
-                double acc = 0.0;
-                for (int f = 0; f < R; ++f) {
-                    const double w = E[f * kEigLd + f];
-                    if (w > cut) acc += Ev[r * kEigLd + f] * Ev[s * kEigLd + f] / w;
+        f32x4 acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = acc0[v] + acc1[v];
+        if (kp == 1) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = ib * 16 + 4 * lk + v;
+                if (row < ln && cv) {
+                    M[row * R + col] = (double)acc[v];
+                    Xt[col * ldx + row] = (double)acc[v];
                 }
-                V[e] = acc;                                     // V <- V^+
             }
-            __syncthreads();
-            for (int e = tid; e < ln * R; e += ANT) {
-                const int i = e / R, s = e % R;
-                double acc = 0.0;
-                for (int r = 0; r < R; ++r) acc += M[i * R + r] * V[r * R + s];
-                X[e] = acc;
-            }
+        } else if (part > 0) {
+            float* dst = P + ((part - 1) * blocks + blk) * 256;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dst[(4 * lk + v) * 16 + lr] = acc[v];
+        } else {
+            keep = acc;
+            keep_blk = blk;
         }
     }
     __syncthreads();
-    // unit columns; wavefront w takes columns r = w, w + 8, ...
+    if (keep_blk >= 0) {
+        const int ib = keep_blk / ncb, cb = keep_blk - (keep_blk / ncb) * ncb;
+        const int col = cb * 16 + lr;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float sum = keep[v];
+            for (int part = 1; part < kp; ++part)
+                sum += P[((part - 1) * blocks + keep_blk) * 256 + (4 * lk + v) * 16 + lr];
+            const int row = ib * 16 + 4 * lk + v;
+            if (row < ln && col < R) {
+                M[row * R + col] = (double)sum;
+                Xt[col * ldx + row] = (double)sum;
+            }
+        }
+    }
+}
+
+// Blocked Gauss-Jordan elimination without pivoting on the augmented system
+// Aug = [V | Xt] (Rp x (Rp + ln), row stride ldx), V symmetric positive
+// definite (padded with identity up to Rp, a multiple of GB): on return the
+// right part holds V^{-1} Xt.  GB pivots per step: every thread inverts the
+// GB x GB pivot block in registers (plain Gauss-Jordan, whose pivots are the
+// successive Schur complements, i.e. the pivots of unblocked elimination)
+// and updates its elements with the GB pivot rows and columns.  The pivot
+// rows and columns of the next step are written to a second buffer while the
+// current ones are read, so a step needs a single barrier; columns left of
+// the pivot block are never read again and are not updated.  pb holds
+// 2 GB (ldx + Rp) doubles.  Returns 0 when a pivot of the first R is not
+// above thr.
+constexpr int GB = 4;
+
+__device__ __forceinline__ int block_gj(double* Aug, int ldx, int R, int Rp, int ln, double* pb,
+                                        double thr) {
+    const int tid = threadIdx.x;
+    const int W = Rp + ln;
+    double* prow0 = pb;                       // [2][GB][ldx]
+    double* pcol0 = pb + 2 * GB * ldx;        // [2][GB][Rp]
+    for (int e = tid; e < GB * W; e += ANT) {
+        const int t = e / W, cc = e - (e / W) * W;
+        prow0[t * ldx + cc] = Aug[t * ldx + cc];
+    }
+    for (int e = tid; e < GB * Rp; e += ANT) {
+        const int t = e / Rp, i = e - (e / Rp) * Rp;
+        pcol0[t * Rp + i] = Aug[i * ldx + t];
+    }
+    __syncthreads();
+    int ok = 1;
+    for (int j = 0; j < Rp; j += GB) {
+        const int cur = (j / GB) & 1, nxt = cur ^ 1;
+        const double* pr = prow0 + cur * GB * ldx;
+        const double* pc = pcol0 + cur * GB * Rp;
+        double* nr = prow0 + nxt * GB * ldx;
+        double* nc = pcol0 + nxt * GB * Rp;
+        // inverse of the pivot block
+        double m[GB][GB], inv[GB][GB];
+#pragma unroll
+        for (int t = 0; t < GB; ++t)
+#pragma unroll
+            for (int s2 = 0; s2 < GB; ++s2) {
+                m[t][s2] = pr[t * ldx + j + s2];
+                inv[t][s2] = (t == s2) ? 1.0 : 0.0;
+            }
+#pragma unroll
+        for (int t = 0; t < GB; ++t) {
+            const double piv = m[t][t];
+            const bool real = j + t < R;
+            if (real && !(piv > thr)) ok = 0;
+            const double ip = 1.0 / (piv > thr ? piv : (real ? thr : 1.0));
+#pragma unroll
+            for (int s2 = 0; s2 < GB; ++s2) { m[t][s2] *= ip; inv[t][s2] *= ip; }
+#pragma unroll
+            for (int r = 0; r < GB; ++r) {
+                if (r == t) continue;
+                const double f = m[r][t];
+#pragma unroll
+                for (int s2 = 0; s2 < GB; ++s2) {
+                    m[r][s2] -= f * m[t][s2];
+                    inv[r][s2] -= f * inv[t][s2];
+                }
+            }
+        }
+        const int wc = W - j - GB;
+        const int cnt = Rp * wc;
+        const float inv_wc = __builtin_amdgcn_rcpf((float)wc);
+        for (int e = tid; e < cnt; e += ANT) {
+            const int i = small_div(e, wc, inv_wc);
+            const int cc = j + GB + (e - i * wc);
+            double p[GB], u[GB];
+#pragma unroll
+            for (int t = 0; t < GB; ++t) p[t] = pr[t * ldx + cc];
+#pragma unroll
+            for (int t = 0; t < GB; ++t) {
+                double acc = 0.0;
+#pragma unroll
+                for (int s2 = 0; s2 < GB; ++s2) acc += inv[t][s2] * p[s2];
+                u[t] = acc;
+            }
+            const int ti = i - j;
+            double na;
+            if (ti >= 0 && ti < GB) {
+                na = u[0];
+#pragma unroll
+                for (int t = 1; t < GB; ++t) if (ti == t) na = u[t];
+            } else {
+                na = Aug[i * ldx + cc];
+#pragma unroll
+                for (int t = 0; t < GB; ++t) na -= pc[t * Rp + i] * u[t];
+            }
+            Aug[i * ldx + cc] = na;
+            const int tn = i - (j + GB);
+            if (tn >= 0 && tn < GB) nr[tn * ldx + cc] = na;
+            const int cn = cc - (j + GB);
+            if (cn >= 0 && cn < GB) nc[cn * Rp + i] = na;
+        }
+        __syncthreads();
+    }
+    return ok;
+}
+
+// Left block of the augmented system: V = *_{m != n} G_m, identity padding up
+// to Rp, and zero padding rows in the right block.
+__device__ __forceinline__ void hadamard_grams(const AlsCtx& c, int n, const double* G, double* Aug,
+                                               int ldx, int Rp, int ln) {
+    const int R = c.R;
+    for (int e = threadIdx.x; e < Rp * Rp; e += ANT) {
+        const int r = e / Rp, s = e - (e / Rp) * Rp;
+        double v;
+        if (r < R && s < R) {
+            v = 1.0;
+            for (int m = 0; m < c.N; ++m)
+                if (m != n) v *= G[m * R * R + r * R + s];
+        } else {
+            v = (r == s) ? 1.0 : 0.0;
+        }
+        Aug[r * ldx + s] = v;
+    }
+    for (int e = threadIdx.x; e < (Rp - R) * ln; e += ANT) {
+        const int r = R + e / ln, i = e - (e / ln) * ln;
+        Aug[r * ldx + Rp + i] = 0.0;
+    }
+}
+
+// Ã_n = M V^+ (V and M^T already in the augmented system), then unit
+// columns: lambda_r = ||column r||, the float32 factor in c.fac(n) and
+// G_n = Ã_n^T Ã_n of exactly that float32 factor.  Returns RCP_INFO_* bits.
+__device__ __forceinline__ int solve_update(const AlsCtx& c, int n, double* G, const double* M,
+                                            double* Aug, int ldx, int Rp, double* pb, double* E,
+                                            double* Ev, double* lam, double* inv_norm, int dbg_it) {
+    (void)dbg_it;
+    const int tid = threadIdx.x, R = c.R, ln = c.l[n];
+    double* Xt = Aug + Rp;
+    int status = 0;
+    double dmax = 0.0;
+    for (int r = 0; r < R; ++r) dmax = fmax(dmax, Aug[r * ldx + r]);
+    const double thr = kPivotRtol * dmax;
+    ALS_SUB(8);
+    const int ok = block_gj(Aug, ldx, R, Rp, ln, pb, thr);
+    ALS_SUB(9);
+    if (!ok) {
+        // Moore-Penrose pseudo-inverse through the eigen-decomposition
+        status |= RCP_INFO_PINV_FALLBACK;
+        for (int e = tid; e < R * R; e += ANT) {
+            double v = 1.0;
+            for (int m = 0; m < c.N; ++m)
+                if (m != n) v *= G[m * R * R + e];
+            E[(e / R) * kEigLd + (e % R)] = v;
+        }
+        __syncthreads();
+        jacobi_eig(E, Ev, R, c.red, c.sh);
+        double wmax = 0.0;
+        for (int f = 0; f < R; ++f) wmax = fmax(wmax, fabs(E[f * kEigLd + f]));
+        const double cut = kPivotRtol * wmax;
+        for (int e = tid; e < R * R; e += ANT) {
+            const int r = e / R, s = e % R;
+            double acc = 0.0;
+            for (int f = 0; f < R; ++f) {
+                const double w = E[f * kEigLd + f];
+                if (w > cut) acc += Ev[r * kEigLd + f] * Ev[s * kEigLd + f] / w;
+            }
+            Aug[r * ldx + s] = acc;                             // V^+ into the left block
+        }
+        __syncthreads();
+        for (int e = tid; e < ln * R; e += ANT) {
+            const int r = e / ln, i = e - (e / ln) * ln;
+            double acc = 0.0;
+            for (int t = 0; t < R; ++t) acc += Aug[r * ldx + t] * M[i * R + t];
+            Xt[r * ldx + i] = acc;                              // Xt = (M V^+)^T
+        }
+        __syncthreads();
+    }
+    // column norms of the solution (rows of Xt), wavefront w takes r = w, w + 8, ...
     {
         const int lane = tid & 63, wave = tid >> 6;
         for (int r = wave; r < R; r += ANW) {
             double ss = 0.0;
-            for (int i = lane; i < ln; i += 64) ss += X[i * R + r] * X[i * R + r];
+            for (int i = lane; i < ln; i += 64) { const double x = Xt[r * ldx + i]; ss += x * x; }
             ss = warp_sum(ss);
-            if (lane == 0) lam[r] = sqrt(ss);
+            if (lane == 0) {
+                const double nu = sqrt(ss);
+                lam[r] = nu;
+                inv_norm[r] = (nu > 0.0) ? 1.0 / nu : 1.0;
+            }
         }
     }
     __syncthreads();
     {
         float* fn = c.fac(n);
         for (int e = tid; e < ln * R; e += ANT) {
-            const double nu = lam[e % R];
-            fn[e] = (float)((nu > 0.0) ? X[e] / nu : X[e]);
+            const int i = e / R, r = e - (e / R) * R;
+            fn[e] = (float)(Xt[r * ldx + i] * inv_norm[r]);
+        }
+        // Gram of the rounded factor, recomputing its entries the same way
+        double* Gn = G + n * R * R;
+        for (int e = tid; e < R * R; e += ANT) {
+            const int r = e / R, s = e - (e / R) * R;
+            const double ir = inv_norm[r], is = inv_norm[s];
+            const double* xr = Xt + r * ldx;
+            const double* xs = Xt + s * ldx;
+            double a0 = 0.0, a1 = 0.0;
+            int i = 0;
+            for (; i + 2 <= ln; i += 2) {
+                a0 += (double)(float)(xr[i] * ir) * (double)(float)(xs[i] * is);
+                a1 += (double)(float)(xr[i + 1] * ir) * (double)(float)(xs[i + 1] * is);
+            }
+            if (i < ln) a0 += (double)(float)(xr[i] * ir) * (double)(float)(xs[i] * is);
+            Gn[e] = a0 + a1;
         }
     }
-    __syncthreads();
-    gram_of(c, n, G + n * R * R);
     __syncthreads();
     return status;
 }
 
-// Per-wavefront partial products Mpart[wave] (l_n x R, row stride 64) of the
-// mode-n product B_(n) KR(Ã_{m != n}) on the matrix cores.  The core is
-// viewed as (Ln, l_n, Rn); the contraction index k = a * Rn + b runs over the
-// other modes and is split evenly over the wavefronts; the Khatri-Rao
-// operand KR[k, r] = prod_{m != n} Ã_m[i_m(k), r] is formed on the fly from
-// the factors in LDS.
-__device__ __forceinline__ void mttkrp_mfma(const AlsCtx& c, int n, const float* B, float* Mpart) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int N = c.N, R = c.R, ln = c.l[n];
-    int lm[RCP_MAX_NDIM];
-    double inv_l[RCP_MAX_NDIM];
-    const float* fm[RCP_MAX_NDIM];
-    int Ln = 1, Rn = 1;
-#pragma unroll
-    for (int m = 0; m < RCP_MAX_NDIM; ++m) {
-        lm[m] = (m < N) ? c.l[m] : 1;
-        inv_l[m] = 1.0 / (double)lm[m];
-        fm[m] = c.fac(m < N ? m : 0);
-        if (m < n) Ln *= lm[m];
-        if (m > n && m < N) Rn *= lm[m];
-    }
-    const double inv_Rn = 1.0 / (double)Rn;
-    const int K = Ln * Rn;
-    const int nib = (ln + 15) / 16, ncb = (R + 15) / 16;
-    const int per = ((K + ANW - 1) / ANW + 3) & ~3;
-    const int k_lo = wave * per;
-    const int k_hi = min(K, k_lo + per);
-    f32x4 acc[4][4];
-#pragma unroll
-    for (int ib = 0; ib < 4; ++ib)
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) acc[ib][cb] = f32x4{0, 0, 0, 0};
-    for (int k0 = k_lo; k0 < k_hi; k0 += 4) {
-        const int k = k0 + lk;
-        const bool kv = k < k_hi;
-        const int kk = kv ? k : 0;
-        const int ai = div_exact(kk, Rn, inv_Rn);
-        const int bi = kk - ai * Rn;
-        int base[RCP_MAX_NDIM];
-        int rem = bi;
-#pragma unroll
-        for (int m = RCP_MAX_NDIM - 1; m >= 0; --m) {
-            base[m] = 0;
-            if (m > n && m < N) {
-                const int q = div_exact(rem, lm[m], inv_l[m]);
-                base[m] = (rem - q * lm[m]) * R;
-                rem = q;
-            }
-        }
-        rem = ai;
-#pragma unroll
-        for (int m = RCP_MAX_NDIM - 1; m >= 0; --m) {
-            if (m < n) {
-                const int q = div_exact(rem, lm[m], inv_l[m]);
-                base[m] = (rem - q * lm[m]) * R;
-                rem = q;
-            }
-        }
-        const int row0 = ai * ln * Rn + bi;
-        float a[4], b[4];
-#pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
-            const int i = ib * 16 + lr;
-            a[ib] = (kv && ib < nib && i < ln) ? B[row0 + i * Rn] : 0.0f;
-        }
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            const int col = cb * 16 + lr;
-            float w = 0.0f;
-            if (kv && cb < ncb && col < R) {
-                w = 1.0f;
-#pragma unroll
-                for (int m = 0; m < RCP_MAX_NDIM; ++m)
-                    if (m < N && m != n) w *= fm[m][base[m] + col];
-            }
-            b[cb] = w;
-        }
-#pragma unroll
-        for (int ib = 0; ib < 4; ++ib)
-            if (ib < nib)
-#pragma unroll
-                for (int cb = 0; cb < 4; ++cb)
-                    if (cb < ncb) acc[ib][cb] = mfma16x16x4(a[ib], b[cb], acc[ib][cb]);
-    }
-    float* mine = Mpart + wave * 64 * 64;
-#pragma unroll
-    for (int ib = 0; ib < 4; ++ib)
-        if (ib < nib)
-#pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
-                if (cb < ncb)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        mine[(ib * 16 + 4 * lk + v) * 64 + cb * 16 + lr] = acc[ib][cb][v];
-}
-
-template <bool B_IN_LDS, bool EIG_IN_LDS>
+template <int NN, bool B_IN_LDS, bool EIG_IN_LDS>
 __global__ __launch_bounds__(ANT) void k_als(AlsArgs a) {
     extern __shared__ __align__(16) unsigned char als_smem[];
     __shared__ double red[ANW];
     __shared__ double sh[128];
     __shared__ double lam[RCP_MAX_RANK];
     __shared__ double lam_tmp[RCP_MAX_RANK];
-    __shared__ int flag;
-    __shared__ int ns_valid[RCP_MAX_NDIM];
+    __shared__ double inv_norm[RCP_MAX_RANK];
     __shared__ int sl[RCP_MAX_NDIM];
     __shared__ int sfoff[RCP_MAX_NDIM];
+    __shared__ int sst[RCP_MAX_NDIM];
     const int tid = threadIdx.x;
     const int N = a.N, R = a.R;
 
@@ -568,9 +577,13 @@ __global__ __launch_bounds__(ANT) void k_als(AlsArgs a) {
         if (n < N) {
             c.S *= a.l[n];
             lmax = max(lmax, a.l[n]);
-            if (tid == 0) { sl[n] = a.l[n]; sfoff[n] = (int)(fbytes / sizeof(float)); ns_valid[n] = 0; }
+            if (tid == 0) { sl[n] = a.l[n]; sfoff[n] = (int)(fbytes / sizeof(float)); }
             fbytes += ((size_t)a.l[n] * R * sizeof(float) + 15) & ~(size_t)15;
         }
+    }
+    if (tid == 0) {
+        int st = 1;
+        for (int n = N - 1; n >= 0; --n) { sst[n] = st; st *= a.l[n]; }
     }
     c.lN = a.l[N - 1];
     c.Lh = c.S / c.lN;
@@ -579,24 +592,24 @@ __global__ __launch_bounds__(ANT) void k_als(AlsArgs a) {
     c.l = sl;
     c.foff = sfoff;
 
-    // dynamic LDS: [factors | G | V | M | X | Xinv (N R^2) | T | X2 | big: E,V (init) then the core]
+    // dynamic LDS: [factors | ones | G | M | Aug = [V | Xt] | pivot buffers | P | big: E,V (init) then the core]
+    const int Rp = (R + GB - 1) / GB * GB;
+    const int ldx = Rp + lmax;
     unsigned char* p = als_smem;
     c.fbase = (float*)p;
     p += fbytes;
+    float* ones = (float*)p; p += RCP_MAX_RANK * sizeof(float);
     double* G = (double*)p;  p += (size_t)N * R * R * sizeof(double);
-    double* V = (double*)p;  p += (size_t)R * R * sizeof(double);
     double* M = (double*)p;  p += (size_t)lmax * R * sizeof(double);
-    double* X = (double*)p;  p += (size_t)lmax * R * sizeof(double);
-    double* Xi = (double*)p; p += (size_t)N * R * R * sizeof(double);
-    double* T = (double*)p;  p += (size_t)R * R * sizeof(double);
-    double* X2 = (double*)p; p += (size_t)R * R * sizeof(double);
+    double* Aug = (double*)p; p += (size_t)Rp * ldx * sizeof(double);
+    double* pb = (double*)p; p += (size_t)2 * GB * (ldx + Rp) * sizeof(double);
+    float* P = (float*)p;    p += kAlsPartFloats * sizeof(float);
     double* E = EIG_IN_LDS ? (double*)p : a.Ebuf;
     double* Ev = E + kEigLd * kEigLd;
     double* Es = a.Ebuf;
     double* Evs = a.Ebuf + kEigLd * kEigLd;
-    double* Aug = a.Ebuf + 2 * kEigLd * kEigLd;         // 64 x 128 Gauss-Jordan scratch
     float* Bl = (float*)p;
-    float* Mpart = a.Mpart;
+    for (int r = tid; r < RCP_MAX_RANK; r += ANT) ones[r] = 1.0f;
     __syncthreads();
 
     double s = 0.0;
@@ -607,7 +620,15 @@ __global__ __launch_bounds__(ANT) void k_als(AlsArgs a) {
     int status = 0;
     for (int n = 1; n < N; ++n) {
         if (!eig_init(c, a.B, n, E, Ev)) status |= RCP_INFO_EIG_NOT_CONVERGED;
-        gram_of(c, n, G + n * R * R);
+        // Gram of the unit-norm eigenvectors
+        const float* A = c.fac(n);
+        const int ln = c.l[n];
+        for (int e = tid; e < R * R; e += ANT) {
+            const int r = e / R, q = e - (e / R) * R;
+            double acc = 0.0;
+            for (int i = 0; i < ln; ++i) acc += (double)A[i * R + r] * (double)A[i * R + q];
+            G[n * R * R + e] = acc;
+        }
     }
     __syncthreads();
     if (B_IN_LDS)
@@ -620,23 +641,17 @@ __global__ __launch_bounds__(ANT) void k_als(AlsArgs a) {
     for (it = 1; it <= a.max_iters; ++it) {
 #ifdef RCP_ALS_TIMING
         const int it_dbg = it - 1;
+#else
+        const int it_dbg = 0;
 #endif
         ALS_STAMP(0);
         for (int n = 0; n < N; ++n) {
-            mttkrp_mfma(c, n, Bs, Mpart);
-            __syncthreads();
-            const int ln = c.l[n];
-            for (int e = tid; e < ln * R; e += ANT) {
-                const int i = e / R, r = e - (e / R) * R;
-                double acc = 0.0;
-#pragma unroll
-                for (int w = 0; w < ANW; ++w) acc += (double)Mpart[w * 64 * 64 + i * 64 + r];
-                M[e] = acc;
-            }
+            hadamard_grams(c, n, G, Aug, ldx, Rp, c.l[n]);
+            mttkrp<NN>(c, n, Bs, sst, ones, P, M, Aug + Rp, ldx);
             __syncthreads();
             ALS_STAMP(2 + 2 * n);
-            status |= solve_update(c, n, G, M, X, V, Xi, T, X2, ns_valid, Aug, Es, Evs,
-                                   (n == N - 1) ? lam : lam_tmp, &flag);
+            status |= solve_update(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs,
+                                   (n == N - 1) ? lam : lam_tmp, inv_norm, it_dbg);
             ALS_STAMP(3 + 2 * n);
         }
         // ---- fit (Section 3.3): rho = 1 - (||X||^2 + ||Xhat||^2 - 2 <Xhat, X>) / ||X||^2
@@ -681,24 +696,22 @@ static size_t als_lds_fixed(int N, const int* l, int R) {
         b += ((size_t)l[n] * R * sizeof(float) + 15) & ~(size_t)15;
         lmax = lmax > l[n] ? lmax : l[n];
     }
-    b += (size_t)N * R * R * sizeof(double);          // G
-    b += (size_t)R * R * sizeof(double);              // V
-    b += 2 * (size_t)lmax * R * sizeof(double);       // M, X
-    b += (size_t)N * R * R * sizeof(double);          // inverses (Newton-Schulz warm starts)
-    b += 2 * (size_t)R * R * sizeof(double);          // T, X2
+    const int Rp = (R + GB - 1) / GB * GB;
+    const int ldx = Rp + lmax;
+    b += RCP_MAX_RANK * sizeof(float);                        // ones
+    b += (size_t)N * R * R * sizeof(double);                  // G
+    b += (size_t)lmax * R * sizeof(double);                   // M
+    b += (size_t)Rp * ldx * sizeof(double);                   // augmented system [V | M^T]
+    b += (size_t)2 * GB * (ldx + Rp) * sizeof(double);        // pivot row / column buffers
+    b += kAlsPartFloats * sizeof(float);                      // partial products
     return b;
 }
 
-// workspace: Mpart (ANW x 64 x 64 floats), then (doubles) Jacobi scratch
-// (2 x 64 x 64) and the Gauss-Jordan scratch (64 x 128)
-size_t als_workspace_floats(int N, const int* l, int R) {
-    (void)N; (void)l; (void)R;
-    return (size_t)ANW * 64 * 64;
-}
-
+// workspace (doubles): Jacobi scratch (2 x 64 x 64) for the pseudo-inverse
+// fallback and for the initialisation when it does not fit in LDS
 size_t als_workspace_doubles(int N, const int* l, int R) {
-    const size_t f = als_workspace_floats(N, l, R);
-    return (f + 1) / 2 + 2 * kEigLd * kEigLd + 64 * 128 + 64;
+    (void)N; (void)l; (void)R;
+    return 2 * kEigLd * kEigLd;
 }
 
 bool als_supported(int N, const int* l, int R) {
@@ -707,14 +720,22 @@ bool als_supported(int N, const int* l, int R) {
     return S < ((int64_t)1 << 31) && als_lds_fixed(N, l, R) <= kAlsLds;
 }
 
-template <bool BL, bool EL>
+template <int NN, bool BL, bool EL>
 static hipError_t launch_als_t(const AlsArgs& a, size_t smem, hipStream_t s) {
-    auto k = k_als<BL, EL>;
+    auto k = k_als<NN, BL, EL>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)kAlsLds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(1), dim3(ANT), smem, s, a);
     return hipGetLastError();
+}
+
+template <int NN>
+static hipError_t launch_als_n(const AlsArgs& a, bool bl, bool el, size_t smem, hipStream_t s) {
+    if (bl && el) return launch_als_t<NN, true, true>(a, smem, s);
+    if (bl) return launch_als_t<NN, true, false>(a, smem, s);
+    if (el) return launch_als_t<NN, false, true>(a, smem, s);
+    return launch_als_t<NN, false, false>(a, smem, s);
 }
 
 hipError_t launch_als(const AlsArgs& a, hipStream_t s) {
@@ -729,16 +750,17 @@ hipError_t launch_als(const AlsArgs& a, hipStream_t s) {
     if (bl) big = bsz;
     if (el && eig > big) big = eig;
     const size_t smem = fixed + big;
-    if (bl && el) return launch_als_t<true, true>(a, smem, s);
-    if (bl) return launch_als_t<true, false>(a, smem, s);
-    if (el) return launch_als_t<false, true>(a, smem, s);
-    return launch_als_t<false, false>(a, smem, s);
+    if (a.N == 3) return launch_als_n<3>(a, bl, el, smem, s);
+    if (a.N == 4) return launch_als_n<4>(a, bl, el, smem, s);
+    return launch_als_n<RCP_MAX_NDIM>(a, bl, el, smem, s);
 }
 
 }  // namespace rcp
 
 #ifdef RCP_ALS_TIMING
 extern "C" int rcp_debug_als_stamps(unsigned long long* host_out) {
-    return (int)hipMemcpyFromSymbol(host_out, HIP_SYMBOL(rcp::g_als_stamps), sizeof(rcp::g_als_stamps));
+    int e = (int)hipMemcpyFromSymbol(host_out, HIP_SYMBOL(rcp::g_als_stamps), sizeof(rcp::g_als_stamps));
+    if (e) return e;
+    return (int)hipMemcpyFromSymbol(host_out + 64, HIP_SYMBOL(rcp::g_als_ns), sizeof(rcp::g_als_ns));
 }
 #endif

@@ -312,8 +312,7 @@ rcp_status als_impl(rcp_plan_t* pl, const float* core, float* const* At, float* 
     int64_t S = 1;
     for (int n = 0; n < L.N; ++n) S *= L.l[n];
     const int R = L.R;
-    a.Mpart = pl->at<float>(L.als);
-    a.Ebuf = pl->at<double>(L.als) + (als_workspace_floats(L.N, L.l, R) + 1) / 2;
+    a.Ebuf = pl->at<double>(L.als);
     // nominal algorithmic work: N mode products of the core with R columns per sweep
     const double sweeps = (double)pl->prob.max_iters;
     RCP_TRY(timed(pl, RCP_KERNEL_ALS, sweeps * L.N * 4.0 * (double)S,

@@ -64,11 +64,9 @@ struct AlsArgs {
     float* lambda;             // R
     rcp_als_info* info;
     // workspace
-    float* Mpart;              // 8 x 64 x 64 per-wavefront partial products
-    double* Ebuf;              // Jacobi (2 x 64 x 64) and Gauss-Jordan (64 x 128) scratch
+    double* Ebuf;              // Jacobi scratch, 2 x 64 x 64
 };
 hipError_t launch_als(const AlsArgs& a, hipStream_t s);
-size_t als_workspace_floats(int N, const int* l, int R);
 size_t als_workspace_doubles(int N, const int* l, int R);
 bool als_supported(int N, const int* l, int R);
 
