@@ -47,6 +47,7 @@ constexpr int kJacobiMaxSweeps = 40;
 constexpr int kEigLd = 64;
 constexpr size_t kAlsLds = 160 * 1024 - 4096;   // dynamic LDS budget
 constexpr int kAlsPartFloats = (ANW - 1) * 256;  // partial 16 x 16 blocks of the mode products
+constexpr int kMtQuads = 8;                      // inner extents up to 32 take the pipelined path
 
 struct AlsCtx {
     int N, R;
@@ -264,38 +265,94 @@ __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, c
             }
         }
         f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-        for (int o = o_lo; o < o_hi; ++o) {
-            int boff = ioff;
-            float ob = cv ? 1.0f : 0.0f;
+        const int nq = (Kl + 3) >> 2;
+        // offset of the core row and Khatri-Rao weight of the outer part at
+        // the current digits; then step the digits to the next outer index
+        auto outer = [&](int& boff, float& ob) {
+            boff = ioff;
+            ob = cv ? 1.0f : 0.0f;
 #pragma unroll
             for (int s = 0; s < D - 1; ++s) {
                 boff += d[s] * so[s];
                 ob *= c.fbase[fo[s] + d[s] * R + ccol];
             }
-            const float* bp = B + boff;
-            // wave-uniform trip counts: the matrix-core instructions run with all lanes
-            int k0 = 0;
-            for (; k0 + 8 <= Kl; k0 += 8) {
-                const int kl = k0 + lk;
-                const float a0 = bp[kl * sl];
-                const float b0 = fin[kl * R + ccol];
-                const float a1 = bp[(kl + 4) * sl];
-                const float b1 = fin[(kl + 4) * R + ccol];
-                acc0 = mfma16x16x4(a0, ob * b0, acc0);
-                acc1 = mfma16x16x4(a1, ob * b1, acc1);
-            }
-            for (; k0 < Kl; k0 += 4) {
-                const int kl = k0 + lk;
-                float a0 = 0.0f, b0 = 0.0f;
-                if (kl < Kl) { a0 = bp[kl * sl]; b0 = fin[kl * R + ccol]; }
-                acc0 = mfma16x16x4(a0, ob * b0, acc0);
-            }
-            // next outer index
 #pragma unroll
             for (int s = D - 2; s >= 0; --s) {
                 d[s] += 1;
                 if (d[s] < lo[s]) break;
                 d[s] = 0;
+            }
+        };
+        if (nq <= kMtQuads) {
+            // software pipelined in half steps of four quads: the operands of
+            // the next half are in flight while the matrix cores work on the
+            // current one (at most nine LDS reads outstanding, within what the
+            // LDS counter can track)
+            constexpr int HQ = kMtQuads / 2;
+            float alo[HQ], blo[HQ], ahi[HQ], bhi[HQ];
+            float ob = 0.0f, ob_next = 0.0f;
+            int boff = 0, boff_next = 0;
+            auto fetch = [&](float* av, float* bv, int bo, int q0) {
+                const float* ap = B + bo;
+#pragma unroll
+                for (int q = 0; q < HQ; ++q) {
+                    const int kl = lk + 4 * (q0 + q);
+                    const int kc = (kl < Kl) ? kl : 0;
+                    av[q] = ap[kc * sl];
+                    bv[q] = fin[kc * R + ccol];
+                }
+            };
+            auto compute = [&](const float* av, const float* bv, float w, int q0) {
+#pragma unroll
+                for (int q = 0; q < HQ; ++q) {
+                    if (q0 + q < nq) {
+                        const bool kv = lk + 4 * (q0 + q) < Kl;
+                        const float x = kv ? av[q] : 0.0f;
+                        const float y = kv ? w * bv[q] : 0.0f;
+                        if (q & 1) acc1 = mfma16x16x4(x, y, acc1);
+                        else acc0 = mfma16x16x4(x, y, acc0);
+                    }
+                }
+            };
+            if (o_lo < o_hi) {
+                outer(boff, ob);
+                fetch(alo, blo, boff, 0);
+            }
+            for (int o = o_lo; o < o_hi; ++o) {
+                if (nq > HQ) fetch(ahi, bhi, boff, HQ);
+                compute(alo, blo, ob, 0);
+                const bool more = o + 1 < o_hi;
+                if (more) {
+                    outer(boff_next, ob_next);
+                    fetch(alo, blo, boff_next, 0);
+                }
+                if (nq > HQ) compute(ahi, bhi, ob, HQ);
+                ob = ob_next;
+                boff = boff_next;
+            }
+        } else {
+            for (int o = o_lo; o < o_hi; ++o) {
+                int boff;
+                float ob;
+                outer(boff, ob);
+                const float* bp = B + boff;
+                // wave-uniform trip counts: the matrix-core instructions run with all lanes
+                int k0 = 0;
+                for (; k0 + 8 <= Kl; k0 += 8) {
+                    const int kl = k0 + lk;
+                    const float x0 = bp[kl * sl];
+                    const float y0 = fin[kl * R + ccol];
+                    const float x1 = bp[(kl + 4) * sl];
+                    const float y1 = fin[(kl + 4) * R + ccol];
+                    acc0 = mfma16x16x4(x0, ob * y0, acc0);
+                    acc1 = mfma16x16x4(x1, ob * y1, acc1);
+                }
+                for (; k0 < Kl; k0 += 4) {
+                    const int kl = k0 + lk;
+                    float x0 = 0.0f, y0 = 0.0f;
+                    if (kl < Kl) { x0 = bp[kl * sl]; y0 = fin[kl * R + ccol]; }
+                    acc0 = mfma16x16x4(x0, ob * y0, acc0);
+                }
             }
         }
         f32x4 acc;

@@ -1,18 +1,29 @@
-// Orthonormal basis of a tall sketch (Algorithm 1 steps 8 and 12, the
-// economic QR Y = Q R of Section 3.1) in float64 on one workgroup.
+// Orthonormal basis of a tall sketch Y (m x n, n <= 64, float64): the
+// economic QR Y = Q R with diag(R) > 0 of Algorithm 1 steps 8 and 12
+// (Section 3.1), on one workgroup.
 //
-// Householder reflections H_k = I - tau_k v_k v_k^T with v_k(k) = 1 (the
-// elementary reflector of the LAPACK convention), then the explicit
-// Q = H_0 ... H_{n-1} [I_n; 0] formed in place, then column k of Q negated
-// when R_kk < 0 so that diag(R) >= 0.  Householder keeps Q orthonormal when Y
-// is rank deficient (noise-free low-rank inputs with l > R), which a Cholesky
-// based QR would not.  The matrix lives in LDS when it fits (m*n <= 18432),
-// else in the caller's float64 buffer (L2 resident at these sizes).
-//
-// Thread layout: lane j of a column group owns column j (CL = 32 or 64
-// columns), the G = QNT / CL groups split the rows, so the column dot
-// products and the rank-1 updates need no integer division and one LDS
-// exchange of G partial sums per column.
+// Cholesky QR passes: G = A^T A (float64 matrix cores), G = R^T R (Cholesky),
+// A <- A R^{-1} (matrix cores).  Every pass keeps span(A) and multiplies R by
+// an upper-triangular factor with positive diagonal, so the result is the
+// unique Q of Y = Q R with diag(R) > 0, as from Householder QR, up to
+// rounding.  Inside the power iteration the sketch is as ill-conditioned as
+// (T T^T) restricted to it, far beyond plain Cholesky QR, hence:
+//   1. a shifted pass (shifted Cholesky QR, Fukaya, Kannan, Nakatsukasa,
+//      Yamamoto and Yanagisawa, SIAM J. Sci. Comput. 2020): G + s I with
+//      s = 11 (m n + n (n + 1)) u ||Y||_F^2, which makes the Cholesky succeed
+//      for any full-rank Y and leaves a factor with condition number of order
+//      u^{-1/2};
+//   2. a plain pass, after which the basis is orthonormal to O(cond^2 u),
+//      enough for the next power step (only its span matters there);
+//   3. for the returned Q_n a third pass: its Gram is I + E with E small, and
+//      R3 = I + triu(E) (diagonal halved) is exact to O(|E|^2), used when
+//      max|E| <= 1e-8, else a full Cholesky.
+// A Cholesky pivot that is not positive (an exactly rank-deficient sketch)
+// switches the kernel to Householder QR on the current basis (same span, same
+// Q): reflections H_k = I - tau_k v_k v_k^T with v_k(k) = 1, the explicit Q
+// formed in place, columns negated so that diag(R) >= 0.
+// The matrix lives in LDS when it fits, else in the caller's buffer (L2
+// resident at these sizes), updated in place.
 
 #include "rcp_device.h"
 #include "rcp_kernels.h"
@@ -20,17 +31,185 @@
 namespace rcp {
 
 constexpr int QNT = 1024;
-constexpr int QR_LDS_ELEMS = 18432;          // 144 KiB of float64
+constexpr int QNW = QNT / 64;
+constexpr size_t kQrLds = 160 * 1024;
+constexpr int kQrScratch = QNW * 256;         // doubles: Gram partials / Householder partial dots
+constexpr double kCqrPivot = 1e-15;           // relative pivot floor of the unshifted passes
+constexpr double kCqrFirstOrder = 1e-8;
+constexpr double kUnitRoundoff = 1.1102230246251565e-16;
 
-// Apply H_k (stored in column k, v_k = 1) to columns k+1..n-1, rows k..m-1.
-__device__ __forceinline__ void apply_reflector(double* A, int lda, int m, int n, int k,
-                                                double tau, double* wp, int CL, int G) {
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f64x4 mfma64(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__device__ __forceinline__ double qr_block_max(double v, double* red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = red[0];
+    for (int i = 1; i < QNW; ++i) t = fmax(t, red[i]);
+    return t;
+}
+
+// G (np x np, row-major) = A^T A over the first n columns (the rest zero),
+// on the float64 matrix cores.  16 x 16 blocks of the upper triangle, the
+// rows split over the wavefronts, partial blocks summed through `part`.
+// Lane layout of v_mfma_f64_16x16x4: A operand [i][k] in lane i + 16 k,
+// B operand [k][j] in lane j + 16 k, result element v of lane l is
+// [l / 16 + 4 v][l % 16].
+__device__ __forceinline__ void gram64(const double* A, int lda, int m, int n, int np, double* G,
+                                       double* part) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nb = np >> 4;
+    const int U = nb * (nb + 1) / 2;
+    const int kp = (QNW / U) > 0 ? QNW / U : 1;
+    const int per = (((m + kp - 1) / kp) + 3) & ~3;
+    for (int u = wave; u < U * kp; u += QNW) {
+        const int blk = u % U, p = u / U;
+        int bi = 0, rem = blk;
+        while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
+        const int bj = bi + rem;
+        const int c1 = bi * 16 + li, c2 = bj * 16 + li;
+        const int r0 = p * per, r1 = min(m, r0 + per);
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = r0; k0 < r1; k0 += 4) {
+            const int r = k0 + lk;
+            const bool rv = r < r1;
+            const double a = (rv && c1 < n) ? A[r * lda + c1] : 0.0;
+            const double b = (rv && c2 < n) ? A[r * lda + c2] : 0.0;
+            acc = mfma64(a, b, acc);
+        }
+        double* dst = part + u * 256;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[(lk + 4 * v) * 16 + li] = acc[v];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < np * np; e += QNT) {
+        int i = e / np, j = e - (e / np) * np;
+        if ((i >> 4) > (j >> 4)) { const int t = i; i = j; j = t; }
+        const int bi = i >> 4, bj = j >> 4;
+        const int blk = bi * nb - bi * (bi - 1) / 2 + (bj - bi);
+        double s = 0.0;
+        for (int p = 0; p < kp; ++p) s += part[(p * U + blk) * 256 + (i & 15) * 16 + (j & 15)];
+        G[e] = s;
+    }
+    __syncthreads();
+}
+
+// Wavefront 0: upper Cholesky factor R of G + shift I (n x n, stride np)
+// into X, then R^{-1} into G; shift = shift_coef * trace(G).  Returns 0 when
+// a pivot is not above kCqrPivot times the largest diagonal entry.  Callers
+// synchronise the workgroup afterwards.
+__device__ __forceinline__ int chol_inverse(double* G, double* X, double* dinv, int n, int np,
+                                            double shift_coef) {
+    const int lane = threadIdx.x;
+    for (int e = lane; e < np * np; e += 64) X[e] = 0.0;
+    double gm = 0.0, tr = 0.0;
+    for (int j = lane; j < n; j += 64) { gm = fmax(gm, G[j * np + j]); tr += G[j * np + j]; }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        gm = fmax(gm, __shfl_xor(gm, o, 64));
+        tr += __shfl_xor(tr, o, 64);
+    }
+    const double shift = shift_coef * tr;
+    const double thr = kCqrPivot * (gm + shift);
+    wave_sync();
+    int ok = 1;
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        if (lane >= j && lane < n) {
+            double s0 = G[j * np + lane] + ((lane == j) ? shift : 0.0), s1 = 0.0;
+            int t = 0;
+            for (; t + 2 <= j; t += 2) {
+                s0 -= X[t * np + j] * X[t * np + lane];
+                s1 -= X[(t + 1) * np + j] * X[(t + 1) * np + lane];
+            }
+            if (t < j) s0 -= X[t * np + j] * X[t * np + lane];
+            s = s0 + s1;
+        }
+        const double d = __shfl(s, j, 64);
+        ok &= (d > thr) ? 1 : 0;
+        const double r = sqrt(fmax(d, thr > 0.0 ? thr : 1e-300));
+        const double ir = 1.0 / r;
+        if (lane == j) { X[j * np + j] = r; dinv[j] = ir; }
+        else if (lane > j && lane < n) X[j * np + lane] = s * ir;
+        wave_sync();
+    }
+    // R^{-1}: lane c owns column c, back substitution from the last row
+    for (int i = n - 1; i >= 0; --i) {
+        if (lane < n) {
+            double v = 0.0;
+            if (i <= lane) {
+                double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0;
+                int k = i + 1;
+                for (; k + 2 <= lane + 1; k += 2) {
+                    s0 -= X[i * np + k] * G[k * np + lane];
+                    s1 -= X[i * np + k + 1] * G[(k + 1) * np + lane];
+                }
+                if (k <= lane) s0 -= X[i * np + k] * G[k * np + lane];
+                v = (s0 + s1) * dinv[i];
+            }
+            G[i * np + lane] = v;
+        }
+        wave_sync();
+    }
+    return ok;
+}
+
+// A <- A X for upper triangular X (n x n, stride np = 16 NB), on the matrix
+// cores.  Wavefront w owns row blocks w, w + 16, ...: it reads its rows
+// completely before writing them, so the update is in place.
+template <int NB>
+__device__ __forceinline__ void apply_upper(double* A, int lda, int m, int n, const double* X) {
+    constexpr int np = 16 * NB;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int mb = (m + 15) >> 4;
+    for (int rb = wave; rb < mb; rb += QNW) {
+        f64x4 acc[NB];
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb) acc[cb] = f64x4{0.0, 0.0, 0.0, 0.0};
+        const int r = rb * 16 + li;
+        for (int k0 = 0; k0 < n; k0 += 4) {
+            const int kk = k0 + lk;
+            const double a = (r < m && kk < n) ? A[r * lda + kk] : 0.0;
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) {
+                const int c = cb * 16 + li;
+                const double b = (kk < n && c < n) ? X[kk * np + c] : 0.0;
+                acc[cb] = mfma64(a, b, acc[cb]);
+            }
+        }
+#pragma unroll
+        for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = rb * 16 + lk + 4 * v, col = cb * 16 + li;
+                if (row < m && col < n) A[row * lda + col] = acc[cb][v];
+            }
+    }
+}
+
+// Householder QR of A (m x n, stride lda) in place: A <- Q with diag(R) >= 0.
+__device__ __forceinline__ void apply_reflector(double* A, int lda, int m, int n, int k, double tau,
+                                                double* wp, int CL, int G) {
     const int j = threadIdx.x % CL, g = threadIdx.x / CL;
     const bool active = (j > k) && (j < n);
     if (active) {
         double s0 = 0.0, s1 = 0.0;
-        // row k carries v_k = 1
-        if (g == 0) s0 = A[k * lda + j];
+        if (g == 0) s0 = A[k * lda + j];            // row k carries v_k = 1
         int i = k + 1 + g;
         for (; i + G < m; i += 2 * G) {
             s0 += A[i * lda + k] * A[i * lda + j];
@@ -56,29 +235,11 @@ __device__ __forceinline__ void apply_reflector(double* A, int lda, int m, int n
     __syncthreads();
 }
 
-template <bool USE_LDS>
-__global__ __launch_bounds__(QNT) void k_qr(double* Yg, int m, int n, int ldy, float* Qpad,
-                                            int ldq, float* Qout) {
-    extern __shared__ double qsm[];
-    __shared__ double wp[QNT];              // G x CL partial dot products
-    __shared__ double taus[64];
-    __shared__ double betas[64];
-    __shared__ double red[QNT / 64];
+__device__ __forceinline__ void householder_q(double* A, int lda, int m, int n, double* wp,
+                                              double* taus, double* betas, double* red) {
     const int tid = threadIdx.x;
     const int CL = (n <= 32) ? 32 : 64;
     const int G = QNT / CL;
-    const int j = tid % CL, g = tid / CL;
-    // USE_LDS is a template parameter so that every access below compiles to
-    // LDS (ds_*) or global instructions, never to generic (flat) ones.
-    double* A = USE_LDS ? qsm : Yg;
-    const int lda = USE_LDS ? n : ldy;
-    if (USE_LDS) {
-        if (j < n)
-            for (int i = g; i < m; i += G) A[i * n + j] = Yg[i * ldy + j];
-        __syncthreads();
-    }
-
-    // --- factorisation
     for (int k = 0; k < n; ++k) {
         double s = 0.0;
         for (int i = k + 1 + tid; i < m; i += QNT) {
@@ -96,15 +257,10 @@ __global__ __launch_bounds__(QNT) void k_qr(double* Yg, int m, int n, int ldy, f
         }
         if (tau != 0.0)
             for (int i = k + 1 + tid; i < m; i += QNT) A[i * lda + k] *= scale;
-        if (tid == 0) {
-            taus[k] = tau;
-            betas[k] = beta;
-        }
+        if (tid == 0) { taus[k] = tau; betas[k] = beta; }
         __syncthreads();
         if (tau != 0.0 && k + 1 < n) apply_reflector(A, lda, m, n, k, tau, wp, CL, G);
     }
-
-    // --- explicit Q, in place, last reflector first
     for (int k = n - 1; k >= 0; --k) {
         const double tau = taus[k];
         if (k + 1 < n && tau != 0.0) apply_reflector(A, lda, m, n, k, tau, wp, CL, G);
@@ -116,34 +272,130 @@ __global__ __launch_bounds__(QNT) void k_qr(double* Yg, int m, int n, int ldy, f
         }
         __syncthreads();
     }
+    // diag(R) >= 0: R_kk = beta_k, so negate column k where beta_k < 0
+    for (int e = tid; e < m * n; e += QNT) {
+        const int i = e / n, c = e - (e / n) * n;
+        if (betas[c] < 0.0) A[i * lda + c] = -A[i * lda + c];
+    }
+    __syncthreads();
+}
 
-    // --- sign convention diag(R) >= 0, float32 outputs
-    for (int i = g; i < m; i += G) {
-        for (int c = j; c < ldq; c += CL) {
-            float v = 0.0f;
-            if (c < n) {
-                const double d = A[i * lda + c];
-                v = (float)(betas[c] < 0.0 ? -d : d);
-                if (Qout != nullptr) Qout[(int64_t)i * n + c] = v;
-            }
-            Qpad[(int64_t)i * ldq + c] = v;
+template <bool USE_LDS, int NB>
+__global__ __launch_bounds__(QNT) void k_qr(double* Yg, int m, int n, int ldy, float* Qpad, int ldq,
+                                            float* Qout, int second_pass) {
+    extern __shared__ double qsm[];
+    __shared__ double taus[64];
+    __shared__ double betas[64];
+    __shared__ double dinv[64];
+    __shared__ double red[QNW];
+    __shared__ int flag;
+    const int tid = threadIdx.x;
+    constexpr int np = 16 * NB;
+    // USE_LDS is a template parameter so that every access compiles to LDS
+    // (ds_*) or global instructions, never to generic (flat) ones.
+    const int lda = USE_LDS ? np + 1 : ldy;           // odd stride: no bank conflicts across rows
+    double* A = USE_LDS ? qsm : Yg;
+    double* G = USE_LDS ? qsm + (size_t)m * lda : qsm;
+    double* X = G + np * np;
+    double* scratch = X + np * np;
+    if (USE_LDS) {
+        for (int e = tid; e < m * np; e += QNT) {
+            const int i = e / np, c = e - (e / np) * np;
+            A[i * lda + c] = (c < n) ? Yg[(size_t)i * ldy + c] : 0.0;
         }
+    }
+    __syncthreads();
+
+    // pass 1 (shifted), pass 2, and for the returned basis pass 3
+    const double shift_coef = 11.0 * ((double)m * n + (double)n * (n + 1)) * kUnitRoundoff;
+    const int passes = second_pass ? 3 : 2;
+    for (int pass = 0; pass < passes; ++pass) {
+        gram64(A, lda, m, n, np, G, scratch);
+        bool first_order = false;
+        if (pass == 2) {
+            double e = 0.0;
+            for (int t = tid; t < n * n; t += QNT) {
+                const int i = t / n, j = t - (t / n) * n;
+                e = fmax(e, fabs(G[i * np + j] - (i == j ? 1.0 : 0.0)));
+            }
+            first_order = qr_block_max(e, red) <= kCqrFirstOrder;
+        }
+        if (first_order) {
+            // R3^{-1} = I - F to first order, F = triu(G - I) with the diagonal halved
+            for (int t = tid; t < np * np; t += QNT) {
+                const int i = t / np, j = t - (t / np) * np;
+                double v = 0.0;
+                if (i < n && j < n && i <= j) {
+                    const double f = (i == j) ? 0.5 * (G[t] - 1.0) : G[t];
+                    v = ((i == j) ? 1.0 : 0.0) - f;
+                }
+                X[t] = v;
+            }
+            __syncthreads();
+            apply_upper<NB>(A, lda, m, n, X);
+        } else {
+            if (tid < 64) {
+                const int ok = chol_inverse(G, X, dinv, n, np, pass == 0 ? shift_coef : 0.0);
+                if (tid == 0) flag = ok;
+            }
+            __syncthreads();
+            if (!flag) {
+                householder_q(A, lda, m, n, scratch, taus, betas, red);
+                break;
+            }
+            apply_upper<NB>(A, lda, m, n, G);
+        }
+        __syncthreads();
+    }
+
+    // float32 outputs, zero padding columns
+    for (int e = tid; e < m * ldq; e += QNT) {
+        const int i = e / ldq, c = e - (e / ldq) * ldq;
+        float v = 0.0f;
+        if (c < n) {
+            v = (float)A[i * lda + c];
+            if (Qout != nullptr) Qout[(int64_t)i * n + c] = v;
+        }
+        Qpad[(int64_t)i * ldq + c] = v;
+    }
+}
+
+static size_t qr_lds_bytes(int64_t m, int n) {
+    const int np = (n + 15) & ~15;
+    return ((size_t)m * (np + 1) + 2 * (size_t)np * np + kQrScratch) * sizeof(double);
+}
+
+template <bool L, int NB>
+static hipError_t launch_qr_t(double* Y, int m, int n, int ldy, float* Qpad, int ldq, float* Qout,
+                              int sp, size_t lds, hipStream_t s) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_qr<L, NB>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_qr<L, NB>), dim3(1), dim3(QNT), lds, s, Y, m, n, ldy, Qpad, ldq, Qout, sp);
+    return hipGetLastError();
+}
+
+template <bool L>
+static hipError_t launch_qr_l(double* Y, int m, int n, int ldy, float* Qpad, int ldq, float* Qout,
+                              int sp, size_t lds, hipStream_t s) {
+    switch ((n + 15) >> 4) {
+        case 1: return launch_qr_t<L, 1>(Y, m, n, ldy, Qpad, ldq, Qout, sp, lds, s);
+        case 2: return launch_qr_t<L, 2>(Y, m, n, ldy, Qpad, ldq, Qout, sp, lds, s);
+        case 3: return launch_qr_t<L, 3>(Y, m, n, ldy, Qpad, ldq, Qout, sp, lds, s);
+        default: return launch_qr_t<L, 4>(Y, m, n, ldy, Qpad, ldq, Qout, sp, lds, s);
     }
 }
 
 hipError_t launch_qr(double* Y, int64_t m, int n, int ldy, float* Qpad, int ldq, float* Qout,
-                     hipStream_t s) {
-    if (m * n <= QR_LDS_ELEMS) {
-        const size_t smem = (size_t)m * n * sizeof(double);
-        hipError_t e = hipFuncSetAttribute((const void*)k_qr<true>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(QR_LDS_ELEMS * sizeof(double)));
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_qr<true>, dim3(1), dim3(QNT), smem, s, Y, (int)m, n, ldy, Qpad, ldq, Qout);
-    } else {
-        hipLaunchKernelGGL(k_qr<false>, dim3(1), dim3(QNT), 0, s, Y, (int)m, n, ldy, Qpad, ldq, Qout);
-    }
-    return hipGetLastError();
+                     bool final_basis, hipStream_t s) {
+    const int np = (n + 15) & ~15;
+    if (n < 1 || n > 64 || ldy < np || ldq < n || m < n || m > ((int64_t)1 << 24)) return hipErrorInvalidValue;
+    const int sp = final_basis ? 1 : 0;
+    const size_t lds = qr_lds_bytes(m, n);
+    if (lds <= kQrLds - 4096)
+        return launch_qr_l<true>(Y, (int)m, n, ldy, Qpad, ldq, Qout, sp, lds, s);
+    const size_t small = (2 * (size_t)np * np + kQrScratch) * sizeof(double);
+    return launch_qr_l<false>(Y, (int)m, n, ldy, Qpad, ldq, Qout, sp, small, s);
 }
 
 }  // namespace rcp

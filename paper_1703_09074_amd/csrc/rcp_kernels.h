@@ -49,7 +49,7 @@ constexpr uint32_t omega_stream_tag(uint32_t batch, uint32_t mode) { return (bat
 // writes Q (diag(R) > 0) as float32 into Qpad (m x ldq, columns >= n zeroed)
 // and, if non-null, into Qout (m x n).
 hipError_t launch_qr(double* Y, int64_t m, int n, int ldy, float* Qpad, int ldq, float* Qout,
-                     hipStream_t s);
+                     bool final_basis, hipStream_t s);
 
 // CP-ALS on the core (als_kernel.hip)
 struct AlsArgs {
