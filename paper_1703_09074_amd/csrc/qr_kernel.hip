@@ -108,62 +108,72 @@ __device__ __forceinline__ void gram64(const double* A, int lda, int m, int n, i
     __syncthreads();
 }
 
-// Wavefront 0: upper Cholesky factor R of G + shift I (n x n, stride np)
-// into X, then R^{-1} into G; shift = shift_coef * trace(G).  Returns 0 when
-// a pivot is not above kCqrPivot times the largest diagonal entry.  Callers
-// synchronise the workgroup afterwards.
-__device__ __forceinline__ int chol_inverse(double* G, double* X, double* dinv, int n, int np,
-                                            double shift_coef) {
-    const int lane = threadIdx.x;
-    for (int e = lane; e < np * np; e += 64) X[e] = 0.0;
+// Upper Cholesky factor of G + shift I (n x n, stride np), shift =
+// shift_coef * trace(G), and its inverse, by all threads, one barrier per
+// pivot.  Right-looking: step j subtracts g_ji g_jk / g_jj from the trailing
+// entries (i, k), j < i <= k, reading only row j, which the previous step
+// finished; afterwards row j of G holds sqrt(d_j) R[j][.].  The thread that
+// finishes the next pivot also publishes its reciprocal.  Then
+// R^{-1} = D^{-1/2}-scaled back substitution, again one row per step:
+// X[j][.] = B[j][.] / R_jj and B[i][.] -= R_ij X[j][.] for i < j, with B = I
+// initially (B kept apart from X so that a step only reads what the
+// previous one wrote).  On return X = R^{-1} (upper, zero elsewhere); G and
+// B are destroyed.  Returns 0 when a pivot is not above kCqrPivot times the
+// largest diagonal entry.  Callers synchronise the workgroup before using X.
+__device__ __forceinline__ int chol_inverse(double* G, double* X, double* B, double* pinv,
+                                            double* red, int n, int np, double shift_coef) {
+    const int tid = threadIdx.x;
     double gm = 0.0, tr = 0.0;
-    for (int j = lane; j < n; j += 64) { gm = fmax(gm, G[j * np + j]); tr += G[j * np + j]; }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        gm = fmax(gm, __shfl_xor(gm, o, 64));
-        tr += __shfl_xor(tr, o, 64);
-    }
+    for (int j = tid; j < n; j += QNT) { gm = fmax(gm, G[j * np + j]); tr += G[j * np + j]; }
+    tr = block_sum(tr, red);
+    gm = qr_block_max(gm, red);
     const double shift = shift_coef * tr;
     const double thr = kCqrPivot * (gm + shift);
-    wave_sync();
+    for (int j = tid; j < n; j += QNT) G[j * np + j] += shift;
+    for (int e = tid; e < np * np; e += QNT) {
+        const int i = e / np, c = e - (e / np) * np;
+        X[e] = 0.0;
+        B[e] = (i == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) pinv[0] = 1.0 / fmax(G[0], thr);
+    __syncthreads();
     int ok = 1;
     for (int j = 0; j < n; ++j) {
-        double s = 0.0;
-        if (lane >= j && lane < n) {
-            double s0 = G[j * np + lane] + ((lane == j) ? shift : 0.0), s1 = 0.0;
-            int t = 0;
-            for (; t + 2 <= j; t += 2) {
-                s0 -= X[t * np + j] * X[t * np + lane];
-                s1 -= X[(t + 1) * np + j] * X[(t + 1) * np + lane];
-            }
-            if (t < j) s0 -= X[t * np + j] * X[t * np + lane];
-            s = s0 + s1;
-        }
-        const double d = __shfl(s, j, 64);
+        const double d = G[j * np + j];
         ok &= (d > thr) ? 1 : 0;
-        const double r = sqrt(fmax(d, thr > 0.0 ? thr : 1e-300));
-        const double ir = 1.0 / r;
-        if (lane == j) { X[j * np + j] = r; dinv[j] = ir; }
-        else if (lane > j && lane < n) X[j * np + lane] = s * ir;
-        wave_sync();
-    }
-    // R^{-1}: lane c owns column c, back substitution from the last row
-    for (int i = n - 1; i >= 0; --i) {
-        if (lane < n) {
-            double v = 0.0;
-            if (i <= lane) {
-                double s0 = (i == lane) ? 1.0 : 0.0, s1 = 0.0;
-                int k = i + 1;
-                for (; k + 2 <= lane + 1; k += 2) {
-                    s0 -= X[i * np + k] * G[k * np + lane];
-                    s1 -= X[i * np + k + 1] * G[(k + 1) * np + lane];
-                }
-                if (k <= lane) s0 -= X[i * np + k] * G[k * np + lane];
-                v = (s0 + s1) * dinv[i];
+        const double id = pinv[j];
+        const int w = n - j - 1;
+        if (w > 0) {
+            const float inv_w = __builtin_amdgcn_rcpf((float)w);
+            for (int e = tid; e < w * w; e += QNT) {
+                const int ii = small_div(e, w, inv_w), kk = e - ii * w;
+                if (kk < ii) continue;
+                const int i = j + 1 + ii, k = j + 1 + kk;
+                const double v = G[i * np + k] - G[j * np + i] * G[j * np + k] * id;
+                G[i * np + k] = v;
+                if (ii == 0 && kk == 0) pinv[j + 1] = 1.0 / fmax(v, thr);
             }
-            G[i * np + lane] = v;
         }
-        wave_sync();
+        __syncthreads();
+    }
+    // R_jj = sqrt(d_j), R_jk = g_jk / sqrt(d_j); keep 1 / R_jj in pinv
+    for (int j = tid; j < n; j += QNT) pinv[j] = 1.0 / sqrt(fmax(G[j * np + j], thr));
+    __syncthreads();
+    for (int e = tid; e < n * n; e += QNT) {
+        const int i = e / n, k = e - (e / n) * n;
+        if (k > i) G[i * np + k] *= pinv[i];
+    }
+    __syncthreads();
+    // back substitution for R^{-1}, rows from the last
+    for (int j = n - 1; j >= 0; --j) {
+        const double ir = pinv[j];
+        for (int e = tid; e < (j + 1) * (n - j); e += QNT) {
+            const int i = e / (n - j), c = j + (e - (e / (n - j)) * (n - j));
+            if (i == j) X[j * np + c] = B[j * np + c] * ir;
+            else B[i * np + c] -= G[i * np + j] * B[j * np + c] * ir;
+        }
+        __syncthreads();
     }
     return ok;
 }
@@ -288,7 +298,7 @@ __global__ __launch_bounds__(QNT) void k_qr(double* Yg, int m, int n, int ldy, f
     __shared__ double betas[64];
     __shared__ double dinv[64];
     __shared__ double red[QNW];
-    __shared__ int flag;
+    int flag;
     const int tid = threadIdx.x;
     constexpr int np = 16 * NB;
     // USE_LDS is a template parameter so that every access compiles to LDS
@@ -334,16 +344,12 @@ __global__ __launch_bounds__(QNT) void k_qr(double* Yg, int m, int n, int ldy, f
             __syncthreads();
             apply_upper<NB>(A, lda, m, n, X);
         } else {
-            if (tid < 64) {
-                const int ok = chol_inverse(G, X, dinv, n, np, pass == 0 ? shift_coef : 0.0);
-                if (tid == 0) flag = ok;
-            }
-            __syncthreads();
+            flag = chol_inverse(G, X, scratch, dinv, red, n, np, pass == 0 ? shift_coef : 0.0);
             if (!flag) {
                 householder_q(A, lda, m, n, scratch, taus, betas, red);
                 break;
             }
-            apply_upper<NB>(A, lda, m, n, G);
+            apply_upper<NB>(A, lda, m, n, X);
         }
         __syncthreads();
     }
