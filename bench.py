@@ -29,9 +29,23 @@ if HERE not in sys.path:
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
-PEAK_FP64_VALU_TFLOPS = 78.6
+PEAK_FP64_MFMA_TFLOPS = 78.6
+N_CU = 256
 
 STREAMING = ("sketch", "power", "contract_in", "contract_out")
+
+# kernel class -> (binding roofline, peak, unit, counted quantity, kernel symbol,
+# workgroups per launch: None = grid-wide)
+ROOFLINES = {
+    "sketch": ("hbm", PEAK_HBM_GBS, "GB/s", "bytes", "k_contract_out (generated Omega)", None),
+    "power": ("hbm", PEAK_HBM_GBS, "GB/s", "bytes", "k_power_fused", None),
+    "contract_in": ("hbm", PEAK_HBM_GBS, "GB/s", "bytes", "k_power_fused (resident-Q mode product)", None),
+    "contract_out": ("hbm", PEAK_HBM_GBS, "GB/s", "bytes", "k_contract_out", None),
+    "reduce": ("hbm", PEAK_HBM_GBS, "GB/s", "bytes", "k_reduce_stage1/2", None),
+    "qr": ("mfma", PEAK_FP64_MFMA_TFLOPS, "TFLOP/s", "flops", "k_qr", 1),
+    "als": ("mfma", PEAK_FP32_MFMA_TFLOPS, "TFLOP/s", "flops", "k_als", 1),
+    "expand": ("hbm", PEAK_HBM_GBS, "GB/s", "bytes", "k_expand_raw/finish", None),
+}
 
 
 def parse():
@@ -45,7 +59,22 @@ def parse():
                     help="CPU oracle sample budget (0 disables the cpu_baseline leg)")
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
                     help="HBM traffic per launch measured with rocprofv3 counters")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (reference "
+                         "reading for the FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+def calibrate_copy(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes_read": n * 4, "bytes_written": n * 4, "launches": 3}),
+          flush=True)
 
 
 def cpu_baseline(X, cfg, budget_s):
@@ -76,6 +105,9 @@ def main():
         print(f"bench.py measures one GPU: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus}); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy > 0:
+        calibrate_copy(args.calibrate_copy)
+        return
 
     import torch
     import paper_1703_09074_amd as rcpgpu
@@ -125,15 +157,17 @@ def main():
         v["ms_per_step"] = v["ms"] / args.profile_steps
     dom = max(kern, key=lambda k: kern[k]["ms"])
     d = kern[dom]
-    if dom in STREAMING or dom == "reduce":
-        ach = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS}
-    else:
-        ach = d["flops"] / (d["ms"] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VALU_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP64_VALU_TFLOPS}
-    roof["kernel"] = dom
+    bound, peak, unit, qty, kname, wgs = ROOFLINES.get(
+        dom, ("hbm", PEAK_HBM_GBS, "GB/s", "bytes", dom, None))
+    scale = 1e9 if unit == "GB/s" else 1e12
+    per_launch = d[qty] / d["launches"]
+    ach = per_launch / (d["ms_per_launch"] * 1e-3) / scale
+    roof = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+            "kernel_class": dom, "kernel": kname, "ms_per_launch": d["ms_per_launch"],
+            ("flops" if qty == "flops" else "bytes") + "_per_launch": per_launch}
+    if wgs == 1:
+        # a single-workgroup kernel can use one compute unit's share of the peak
+        roof["frac_of_one_cu"] = ach / (peak / N_CU)
     roof["traffic"] = None
     if os.path.exists(args.traffic_json):
         try:
