@@ -173,7 +173,7 @@ def main():
         try:
             tj = json.load(open(args.traffic_json))
             ent = tj.get(args.workload, {}).get(dom)
-            if ent and ent.get("source_hash") == _source_hash():
+            if ent and ent.get("source_hash") == _source_hash(dom):
                 roof["traffic"] = ent["bytes_per_launch"]
         except (ValueError, OSError):
             pass
@@ -214,11 +214,16 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def _source_hash():
+KERNEL_SOURCES = {"als": "als_kernel.hip", "qr": "qr_kernel.hip", "expand": "expand_kernel.hip"}
+
+
+def _source_hash(kernel_class):
+    """Hash of the sources a kernel class is built from (its .hip file and the
+    shared device headers): stored traffic counts are used only while it matches."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "paper_1703_09074_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in (KERNEL_SOURCES.get(kernel_class, "stream_kernels.hip"), "rcp_device.h", "rcp_kernels.h"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 

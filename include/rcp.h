@@ -192,7 +192,7 @@ enum {
     RCP_KERNEL_CONTRACT_IN = 2,  /* T x_n Q^T (compression, or stored Z) */
     RCP_KERNEL_CONTRACT_OUT = 3, /* Y = T_(n) Z with a stored Z */
     RCP_KERNEL_REDUCE = 4,       /* partial-sum reduction */
-    RCP_KERNEL_QR = 5,           /* Householder QR of a sketch */
+    RCP_KERNEL_QR = 5,           /* QR of a sketch (shifted Cholesky QR, Householder fallback) */
     RCP_KERNEL_ALS = 6,          /* CP-ALS on the core */
     RCP_KERNEL_EXPAND = 7,       /* back-projection and renormalisation */
     RCP_KERNEL_OTHER = 8,

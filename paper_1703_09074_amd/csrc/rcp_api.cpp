@@ -249,8 +249,10 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
 
     const double S = (double)count_of(cur, N);
     const double J = S / (double)I;
+    // nominal QR work: per Cholesky QR pass a Gram (I l^2) and a triangular
+    // product (I l^2) in float64; two passes, three for the returned basis
     const double qr_bytes = (double)I * l * 8.0 + (double)I * LP * 4.0;
-    const double qr_flops = 4.0 * (double)I * l * l;
+    const double qr_flops = 2.0 * 2.0 * (double)I * l * l;
     RCP_TRY(timed(pl, RCP_KERNEL_SKETCH, 4.0 * S + 4.0 * I * l, 2.0 * S * l, [&] {
         return launch_contract_out(g, l, nullptr, pl->prob.seed, tag, part, P,
                                    norm_out ? sq : nullptr, pl->stream);
@@ -259,7 +261,7 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
     if (st != RCP_OK) return st;
     const bool fused = power_fused_fits(I, l, pl->smem_limit);
     for (int it = 0; it < pl->prob.q; ++it) {
-        RCP_TRY(timed(pl, RCP_KERNEL_QR, qr_bytes, qr_flops,
+        RCP_TRY(timed(pl, RCP_KERNEL_QR, qr_bytes, 2.0 * qr_flops,
                       [&] { return launch_qr(Y, I, l, LP, Qt, LP, nullptr, false, pl->stream); }));
         if (fused) {
             RCP_TRY(timed(pl, RCP_KERNEL_POWER, 4.0 * S + 4.0 * I * l, 4.0 * S * l,
@@ -275,7 +277,7 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
         st = reduce_y(pl, P, I, LP, nullptr, 0, nullptr);
         if (st != RCP_OK) return st;
     }
-    RCP_TRY(timed(pl, RCP_KERNEL_QR, qr_bytes, qr_flops,
+    RCP_TRY(timed(pl, RCP_KERNEL_QR, qr_bytes, 3.0 * qr_flops,
                   [&] { return launch_qr(Y, I, l, LP, Qt, LP, Q, true, pl->stream); }));
     return RCP_OK;
 }

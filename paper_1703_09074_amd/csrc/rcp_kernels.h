@@ -45,9 +45,11 @@ hipError_t launch_pad_q(const float* Q, int64_t I, int l, float* Qpad, int ldq, 
 constexpr uint32_t omega_stream_tag(uint32_t batch, uint32_t mode) { return (batch << 8) | (mode & 0xFFu); }
 
 // small dense kernels (qr_kernel.hip)
-// Householder QR of the m x n float64 matrix Y (row stride ldy, overwritten);
-// writes Q (diag(R) > 0) as float32 into Qpad (m x ldq, columns >= n zeroed)
-// and, if non-null, into Qout (m x n).
+// QR of the m x n float64 matrix Y (row stride ldy, overwritten): two
+// Cholesky QR passes (the first shifted), a third for the returned basis
+// (final_basis), Householder when a pivot vanishes.  Writes Q (diag(R) > 0) as
+// float32 into Qpad (m x ldq, columns >= n zeroed) and, if non-null, into
+// Qout (m x n).
 hipError_t launch_qr(double* Y, int64_t m, int n, int ldy, float* Qpad, int ldq, float* Qout,
                      bool final_basis, hipStream_t s);
 
