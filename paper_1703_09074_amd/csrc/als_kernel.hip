@@ -46,8 +46,22 @@ constexpr double kPivotRtol = 1e-13;
 constexpr int kJacobiMaxSweeps = 40;
 constexpr int kEigLd = 64;
 constexpr size_t kAlsLds = 160 * 1024 - 4096;   // dynamic LDS budget
-constexpr int kAlsPartFloats = (ANW - 1) * 256;  // partial 16 x 16 blocks of the mode products
 constexpr int kMtQuads = 8;                      // inner extents up to 32 take the pipelined path
+
+// Floats of LDS for the partial 16 x 16 blocks of the mode products: a mode
+// with `blocks` output blocks splits its contraction over up to
+// ANW / blocks wavefronts, all but the first slice of a block go to LDS.
+__host__ __device__ inline int als_part_floats(int N, const int* l, int R) {
+    int mx = 0;
+    const int ncb = (R + 15) / 16;
+    for (int n = 0; n < N; ++n) {
+        const int blocks = ((l[n] + 15) / 16) * ncb;
+        const int kp = (blocks >= ANW) ? 1 : ANW / blocks;
+        const int f = (kp - 1) * blocks * 256;
+        mx = mx > f ? mx : f;
+    }
+    return mx;
+}
 
 struct AlsCtx {
     int N, R;
@@ -657,10 +671,10 @@ __global__ __launch_bounds__(ANT) void k_als(AlsArgs a) {
     p += fbytes;
     float* ones = (float*)p; p += RCP_MAX_RANK * sizeof(float);
     double* G = (double*)p;  p += (size_t)N * R * R * sizeof(double);
-    double* M = (double*)p;  p += (size_t)lmax * R * sizeof(double);
     double* Aug = (double*)p; p += (size_t)Rp * ldx * sizeof(double);
     double* pb = (double*)p; p += (size_t)2 * GB * (ldx + Rp) * sizeof(double);
-    float* P = (float*)p;    p += kAlsPartFloats * sizeof(float);
+    float* P = (float*)p;    p += (size_t)als_part_floats(N, a.l, R) * sizeof(float);
+    double* M = a.Ebuf + 2 * kEigLd * kEigLd;            // l_n x R, global (read by the fit and the fallback)
     double* E = EIG_IN_LDS ? (double*)p : a.Ebuf;
     double* Ev = E + kEigLd * kEigLd;
     double* Es = a.Ebuf;
@@ -757,18 +771,19 @@ static size_t als_lds_fixed(int N, const int* l, int R) {
     const int ldx = Rp + lmax;
     b += RCP_MAX_RANK * sizeof(float);                        // ones
     b += (size_t)N * R * R * sizeof(double);                  // G
-    b += (size_t)lmax * R * sizeof(double);                   // M
     b += (size_t)Rp * ldx * sizeof(double);                   // augmented system [V | M^T]
     b += (size_t)2 * GB * (ldx + Rp) * sizeof(double);        // pivot row / column buffers
-    b += kAlsPartFloats * sizeof(float);                      // partial products
+    b += (size_t)als_part_floats(N, l, R) * sizeof(float);    // partial products
     return b;
 }
 
 // workspace (doubles): Jacobi scratch (2 x 64 x 64) for the pseudo-inverse
-// fallback and for the initialisation when it does not fit in LDS
+// fallback and for the initialisation when it does not fit in LDS, then the
+// mode product M_n (l_n x R)
 size_t als_workspace_doubles(int N, const int* l, int R) {
-    (void)N; (void)l; (void)R;
-    return 2 * kEigLd * kEigLd;
+    int lmax = 0;
+    for (int n = 0; n < N; ++n) lmax = lmax > l[n] ? lmax : l[n];
+    return 2 * kEigLd * kEigLd + (size_t)lmax * R;
 }
 
 bool als_supported(int N, const int* l, int R) {

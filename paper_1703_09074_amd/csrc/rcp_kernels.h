@@ -66,7 +66,7 @@ struct AlsArgs {
     float* lambda;             // R
     rcp_als_info* info;
     // workspace
-    double* Ebuf;              // Jacobi scratch, 2 x 64 x 64
+    double* Ebuf;              // Jacobi scratch (2 x 64 x 64), then M_n (l_max x R)
 };
 hipError_t launch_als(const AlsArgs& a, hipStream_t s);
 size_t als_workspace_doubles(int N, const int* l, int R);

@@ -147,6 +147,55 @@ WORKLOADS = {
 }
 
 
+def low_rank_device(dims: Sequence[int], R: int, noise: float, seed: int,
+                    kind: str = "gaussian", cos: float = 0.8, device="cuda"):
+    """The same recipe as ``low_rank`` (factors drawn with numpy from ``seed``),
+    assembled on the GPU with torch, for tensors too large to build on the
+    host quickly.  The noise comes from torch's generator seeded with ``seed``
+    (a different stream from numpy's, so the tensor differs from
+    ``low_rank``'s by its noise).  Returns (X float32 on device, factors,
+    weights, sigma)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    dims = [int(d) for d in dims]
+    if kind == "gaussian":
+        factors = _gaussian_factors(rng, dims, R)
+    elif kind == "logweights":
+        factors = _gaussian_factors(rng, dims, R)
+        norms = 10.0 ** (2.0 * rng.uniform(0.0, 1.0, R))
+        factors[0] = factors[0] / np.linalg.norm(factors[0], axis=0, keepdims=True) * norms[None, :]
+    elif kind == "collinear":
+        factors = _collinear_factors(rng, dims, R, cos)
+    else:
+        raise ValueError(f"unknown factor kind {kind!r}")
+    weights = np.ones(R)
+    dev = torch.device(device)
+    tail = torch.ones((1, R), dtype=torch.float64, device=dev)
+    for A in factors[1:]:
+        At = torch.from_numpy(A).to(dev)
+        tail = (tail[:, None, :] * At[None, :, :]).reshape(-1, R)
+    head = torch.from_numpy(factors[0]).to(dev)
+    X = torch.empty(dims, dtype=torch.float32, device=dev)
+    Xf = X.view(dims[0], -1)
+    slab = max(1, int(2 ** 26 // max(1, tail.shape[0])))
+    sumsq = 0.0
+    for i0 in range(0, dims[0], slab):
+        i1 = min(dims[0], i0 + slab)
+        block = head[i0:i1] @ tail.T
+        sumsq += float((block * block).sum())
+        Xf[i0:i1] = block.to(torch.float32)
+    rms = float(np.sqrt(sumsq / float(np.prod(dims))))
+    sigma = float(noise) * rms
+    if sigma > 0.0:
+        g = torch.Generator(device=dev)
+        g.manual_seed(int(seed))
+        for i0 in range(0, dims[0], slab):
+            i1 = min(dims[0], i0 + slab)
+            E = torch.randn((i1 - i0, Xf.shape[1]), generator=g, dtype=torch.float64, device=dev)
+            Xf[i0:i1] = (Xf[i0:i1].to(torch.float64) + sigma * E).to(torch.float32)
+    return X, factors, weights, sigma
+
+
 def make(name: str, **overrides) -> Workload:
     cfg = dict(WORKLOADS[name])
     cfg.update(overrides)
