@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rcp400")
     ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--mixed-steps", type=int, default=10,
+                    help="timed solves with bfloat16 and float16 operands (0 skips the comparison)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU oracle sample budget (0 disables the cpu_baseline leg)")
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
@@ -85,18 +87,22 @@ def cpu_baseline(X, cfg, budget_s):
     cores = len(os.sched_getaffinity(0))
     X64 = X.astype(np.float64)
     n = 0
+    rel_err = None
     t0 = time.perf_counter()
     while True:
-        rcp.rcp_als(X64, cfg["k"], cfg["p"], cfg["q"], cfg["iters"], 0.0, cfg["seed"])
+        r = rcp.rcp_als(X64, cfg["k"], cfg["p"], cfg["q"], cfg["iters"], 0.0, cfg["seed"])
+        if rel_err is None:
+            rel_err = float(np.sqrt(max(0.0, 1.0 - r.rho)))
         n += 1
         if time.perf_counter() - t0 >= budget_s or n >= 20:
             break
     dt = time.perf_counter() - t0
     threads = os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS")
-    return {"value": n / dt, "unit": "solves/s",
-            "cores": int(threads) if threads and threads.isdigit() else cores,
-            "kind": "oracle",
-            "sample": f"{n} whole solve(s) of the same workload in float64 NumPy/SciPy ({dt:.1f} s)"}
+    return ({"value": n / dt, "unit": "solves/s",
+             "cores": int(threads) if threads and threads.isdigit() else cores,
+             "kind": "oracle",
+             "sample": f"{n} whole solve(s) of the same workload in float64 NumPy/SciPy ({dt:.1f} s)"},
+            rel_err)
 
 
 def main():
@@ -119,29 +125,30 @@ def main():
     torch.cuda.set_device(dev)
     X = torch.from_numpy(w.X).to(dev)
     dims = list(w.X.shape)
-    plan = rcpgpu.Plan(dims, cfg["k"], cfg["p"], cfg["q"], cfg["iters"], 0.0, cfg["seed"],
-                       device=dev)
-    A = [torch.empty((d, cfg["k"]), dtype=torch.float32, device=dev) for d in dims]
-    lam = torch.empty((cfg["k"],), dtype=torch.float32, device=dev)
-    info = plan._info_buffer()
+    def run(precision, steps, warmup):
+        plan = rcpgpu.Plan(dims, cfg["k"], cfg["p"], cfg["q"], cfg["iters"], 0.0, cfg["seed"],
+                           device=dev, precision=precision)
+        A = [torch.empty((d, cfg["k"]), dtype=torch.float32, device=dev) for d in dims]
+        lam = torch.empty((cfg["k"],), dtype=torch.float32, device=dev)
+        info = plan._info_buffer()
+        for _ in range(warmup):
+            plan.decompose_into(X, A, lam, info)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            plan.decompose_into(X, A, lam, info)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1) / steps
+        return plan, (A, lam, info), ms, wall, rcpgpu.Plan.read_info(info)
 
-    for _ in range(args.warmup):
-        plan.decompose_into(X, A, lam, info)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream(dev)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        plan.decompose_into(X, A, lam, info)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    ms_per_step = ms / args.steps
+    plan, (A, lam, info), ms_per_step, wall, res = run("fp32", args.steps, args.warmup)
     value = 1000.0 / ms_per_step
-    res = rcpgpu.Plan.read_info(info)
 
     # per-kernel timing (separate pass with an event pair around every launch)
     plan.profile(True)
@@ -185,6 +192,14 @@ def main():
                   "frac_fp32_mfma": sf / (sm * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS,
                   "ms_per_step": sm / args.profile_steps} if sm > 0 else None
 
+    mixed = {}
+    if args.mixed_steps > 0:
+        for prec in ("bf16", "fp16"):
+            _, _, mms, _, mres = run(prec, args.mixed_steps, 1)
+            mixed[prec] = {"ms_per_step": mms, "solves_per_s": 1000.0 / mms,
+                           "speedup_vs_fp32": ms_per_step / mms, "rel_err": mres["rel_err"],
+                           "rel_err_minus_fp32": mres["rel_err"] - res["rel_err"]}
+
     out = {
         "metric": "rCP solves/sec + sketch/TTM TFLOP/s (% peak), mixed vs FP32 at equal rel. error",
         "value": value,
@@ -207,10 +222,17 @@ def main():
         "roofline": roof,
         "sketch_ttm": sketch_ttm,
         "kernels": kern,
+        "mixed_vs_fp32": mixed or None,
         "cpu_baseline": None,
     }
     if args.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(w.X, cfg, args.cpu_seconds)
+        cb, oracle_err = cpu_baseline(w.X, cfg, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        out["oracle_rel_err"] = oracle_err
+        # mixed precision counts only at equal error: both within 1e-4 of the oracle's
+        fp32_ok = abs(res["rel_err"] - oracle_err) <= 1e-4
+        for m in mixed.values():
+            m["valid_at_equal_error"] = bool(fp32_ok and abs(m["rel_err"] - oracle_err) <= 1e-4)
     print(json.dumps(out), flush=True)
 
 

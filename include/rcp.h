@@ -46,7 +46,15 @@ typedef enum rcp_status {
     RCP_ERR_UNSUPPORTED = 5    /* valid request this build does not implement */
 } rcp_status;
 
-/* rcp_problem.precision: operand precision of the streaming contractions. */
+/* rcp_problem.precision: operand precision of the range finder's
+ * contractions (the sketch and the power-iteration products of Algorithm 1
+ * steps 6, 9 and 10).  FP32 feeds the matrix cores float32 operands; BF16 /
+ * FP16 round the float32 tensor tiles and the test-matrix or basis operands
+ * to bfloat16 / float16 (nearest even) on their way to the matrix cores.
+ * Their rounding only perturbs the basis Q_n.  The mode products of step 13,
+ * whose output is the core itself, keep float32 operands in every precision.
+ * Accumulation is float32, and the cross-workgroup sums, the QR and every
+ * ALS solve stay float64 in all cases; X is read as float32. */
 enum { RCP_PREC_FP32 = 0, RCP_PREC_BF16 = 1, RCP_PREC_FP16 = 2 };
 
 /* rcp_problem.scheme (Section 3.1): SEQUENTIAL sketches mode n on the tensor
@@ -105,7 +113,9 @@ rcp_status rcp_workspace_size(const rcp_problem* prob, size_t* bytes);
  *   k + p > 64, k > l_n for some n, max_iters < 1, tol < 0, unknown
  *   precision/scheme, reserved != 0, or a null plan / problem pointer.
  * RCP_ERR_WORKSPACE: null or too small workspace.
- * RCP_ERR_UNSUPPORTED: a precision other than FP32 in this build. */
+ * RCP_ERR_UNSUPPORTED: the core factors and Gram matrices of CP-ALS do not
+ *   fit one workgroup's LDS (rank and l too large together), or the device
+ *   is not gfx950. */
 rcp_status rcp_init(rcp_plan* plan, const rcp_problem* prob, void* workspace,
                     size_t workspace_bytes, void* hip_stream);
 

@@ -255,7 +255,7 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
     const double qr_flops = 2.0 * 2.0 * (double)I * l * l;
     RCP_TRY(timed(pl, RCP_KERNEL_SKETCH, 4.0 * S + 4.0 * I * l, 2.0 * S * l, [&] {
         return launch_contract_out(g, l, nullptr, pl->prob.seed, tag, part, P,
-                                   norm_out ? sq : nullptr, pl->stream);
+                                   norm_out ? sq : nullptr, pl->stream, pl->prob.precision);
     }));
     rcp_status st = reduce_y(pl, P, I, LP, norm_out ? sq : nullptr, P * nIB, norm_out);
     if (st != RCP_OK) return st;
@@ -265,13 +265,13 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
                       [&] { return launch_qr(Y, I, l, LP, Qt, LP, nullptr, false, pl->stream); }));
         if (fused) {
             RCP_TRY(timed(pl, RCP_KERNEL_POWER, 4.0 * S + 4.0 * I * l, 4.0 * S * l,
-                          [&] { return launch_power_fused(g, l, Qt, part, P, pl->stream); }));
+                          [&] { return launch_power_fused(g, l, Qt, part, P, pl->stream, pl->prob.precision); }));
         } else {
             float* Z = pl->at<float>(pl->L.zbuf);
             RCP_TRY(timed(pl, RCP_KERNEL_CONTRACT_IN, 4.0 * S + 4.0 * J * LP, 2.0 * S * l,
-                          [&] { return launch_contract_in(g, l, Qt, LP, Z, P, pl->stream); }));
+                          [&] { return launch_contract_in(g, l, Qt, LP, Z, P, pl->stream, pl->prob.precision); }));
             RCP_TRY(timed(pl, RCP_KERNEL_CONTRACT_OUT, 4.0 * S + 4.0 * J * LP, 2.0 * S * l, [&] {
-                return launch_contract_out(g, l, Z, 0, 0, part, P, nullptr, pl->stream);
+                return launch_contract_out(g, l, Z, 0, 0, part, P, nullptr, pl->stream, pl->prob.precision);
             }));
         }
         st = reduce_y(pl, P, I, LP, nullptr, 0, nullptr);
@@ -292,8 +292,9 @@ rcp_status compress_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int
     const double S = (double)count_of(cur, pl->L.N);
     RCP_TRY(timed(pl, RCP_KERNEL_CONTRACT_IN, 4.0 * S + 4.0 * (S / (double)I) * l,
                   2.0 * S * l, [&] {
+                      // the compressed tensor is the core: float32 operands in every precision
                       return launch_contract_in(g, l, pl->at<float>(pl->L.qt), l, T_out, P,
-                                                pl->stream);
+                                                pl->stream, RCP_PREC_FP32);
                   }));
     return RCP_OK;
 }
@@ -377,7 +378,6 @@ rcp_status rcp_init(rcp_plan* plan, const rcp_problem* prob, void* workspace,
     if (plan == nullptr) return RCP_ERR_INVALID_ARG;
     *plan = nullptr;
     if (!valid_problem(prob)) return RCP_ERR_INVALID_ARG;
-    if (prob->precision != RCP_PREC_FP32) return RCP_ERR_UNSUPPORTED;
     const Layout L = make_layout(prob);
     if (!als_supported(L.N, L.l, L.R)) return RCP_ERR_UNSUPPORTED;
     if (workspace == nullptr || workspace_bytes < L.total || !aligned(workspace, kAlign))

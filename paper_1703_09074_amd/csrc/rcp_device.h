@@ -120,4 +120,38 @@ __device__ __forceinline__ int small_div(int a, int d, float inv_d) {
     return q;
 }
 
+// ---------------------------------------------------------------------------
+// 16-bit matrix-core operands (values of rcp_problem.precision)
+constexpr int kPrecFp32 = 0;
+constexpr int kPrecBf16 = 1;
+constexpr int kPrecFp16 = 2;
+
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
+
+// four float32 values rounded to nearest even in the 16-bit operand format
+template <int PR>
+__device__ __forceinline__ s16x4 to_lp(float4 v) {
+    if constexpr (PR == kPrecBf16) {
+        const bf16x4_t b = {(__bf16)v.x, (__bf16)v.y, (__bf16)v.z, (__bf16)v.w};
+        return __builtin_bit_cast(s16x4, b);
+    } else {
+        const f16x4_t h = {(_Float16)v.x, (_Float16)v.y, (_Float16)v.z, (_Float16)v.w};
+        return __builtin_bit_cast(s16x4, h);
+    }
+}
+
+// D += A B with A 16 x 16 (lane l: row l % 16, k = 4 (l / 16) .. + 3),
+// B 16 x 16 (lane l: column l % 16, same k), float32 accumulation; D in the
+// layout of mfma16x16x4.
+template <int PR>
+__device__ __forceinline__ f32x4 mfma_lp(s16x4 a, s16x4 b, f32x4 c) {
+    if constexpr (PR == kPrecBf16)
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(f16x4_t, a),
+                                                     __builtin_bit_cast(f16x4_t, b), c, 0, 0, 0);
+}
+
 }  // namespace rcp

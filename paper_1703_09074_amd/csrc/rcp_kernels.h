@@ -24,15 +24,24 @@ struct StreamGeom {
 StreamGeom make_geom(const float* T, const int64_t* dims, int ndim, int mode);
 
 // streaming contractions (stream_kernels.hip)
+// precision: matrix-core operand type of the contraction (RCP_PREC_*)
 hipError_t launch_contract_out(const StreamGeom& g, int l, const float* Z, uint64_t seed,
                                uint32_t tag, float* part, int P, double* sq_part,
-                               hipStream_t s);
+                               hipStream_t s, int precision);
 int contract_out_row_blocks(int64_t I);
 bool power_fused_fits(int64_t I, int l, size_t smem_limit);
 hipError_t launch_power_fused(const StreamGeom& g, int l, const float* Qt, float* part, int P,
-                              hipStream_t s);
+                              hipStream_t s, int precision);
 hipError_t launch_contract_in(const StreamGeom& g, int l, const float* Qpadded, int lout,
-                              float* out, int P, hipStream_t s);
+                              float* out, int P, hipStream_t s, int precision);
+// the 16-bit operand instantiations (stream_kernels_lp.hip)
+hipError_t launch_contract_out_lp(int precision, const StreamGeom& g, int l, const float* Z,
+                                  uint64_t seed, uint32_t tag, float* part, int P, double* sq_part,
+                                  hipStream_t s);
+hipError_t launch_power_fused_lp(int precision, const StreamGeom& g, int l, const float* Qt,
+                                 float* part, int P, hipStream_t s);
+hipError_t launch_contract_in_lp(int precision, const StreamGeom& g, int l, const float* Qpadded,
+                                 int lout, float* out, int P, hipStream_t s);
 int reduce_split(int P);
 hipError_t launch_reduce_partials(const float* part, int P, int64_t count, double* red1,
                                   double* Y, const double* sq_part, int nsq, double* sq_out,

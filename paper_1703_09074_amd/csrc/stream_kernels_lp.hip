@@ -1,0 +1,32 @@
+// Streaming contractions with 16-bit matrix-core operands (bfloat16 or
+// float16, rounded to nearest even from the float32 tiles in LDS; float32
+// accumulation): the precision variant of the sketch, power-iteration and
+// mode-product kernels.
+
+#include "stream_tiles.h"
+
+namespace rcp {
+
+hipError_t launch_contract_out_lp(int precision, const StreamGeom& g, int l, const float* Z,
+                                  uint64_t seed, uint32_t tag, float* part, int P, double* sq_part,
+                                  hipStream_t s) {
+    if (precision == kPrecBf16) return launch_contract_out_t<kPrecBf16>(g, l, Z, seed, tag, part, P, sq_part, s);
+    if (precision == kPrecFp16) return launch_contract_out_t<kPrecFp16>(g, l, Z, seed, tag, part, P, sq_part, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_power_fused_lp(int precision, const StreamGeom& g, int l, const float* Qt,
+                                 float* part, int P, hipStream_t s) {
+    if (precision == kPrecBf16) return launch_power_fused_t<kPrecBf16>(g, l, Qt, part, P, s);
+    if (precision == kPrecFp16) return launch_power_fused_t<kPrecFp16>(g, l, Qt, part, P, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_contract_in_lp(int precision, const StreamGeom& g, int l, const float* Qpadded,
+                                 int lout, float* out, int P, hipStream_t s) {
+    if (precision == kPrecBf16) return launch_contract_in_t<kPrecBf16>(g, l, Qpadded, lout, out, P, s);
+    if (precision == kPrecFp16) return launch_contract_in_t<kPrecFp16>(g, l, Qpadded, lout, out, P, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace rcp

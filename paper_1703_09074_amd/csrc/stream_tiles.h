@@ -1,0 +1,602 @@
+// Streaming contractions over the current tensor T (Algorithm 1 steps 6,
+// 9, 10 and 13), hand-written for gfx950.
+//
+// T is C-order with dims (I_0..I_{N-1}); around mode n it is viewed as a
+// 3-D array (L, I, Rr): L = prod of dims before n, Rr = prod after n.  The
+// mode-n unfolding T_(n) is I x J with column j = a*Rr + b and is never
+// materialised.  Its columns are cut into tiles of JT consecutive j that
+// stay contiguous in memory:
+//   case A (Rr >= JT): a tile is (fixed a, b in [b0, b0+JT)), one run of
+//     JT floats per row i;
+//   case B (Rr <  JT): a tile is TA whole a-slabs (all b), i.e. one
+//     contiguous block of TA*I*Rr floats.
+// A workgroup loads a tile (all rows of its row block) into LDS with
+// coalesced loads and feeds the matrix cores (v_mfma_f32_16x16x4_f32) from
+// there.  The sketch width l is padded to LP (a multiple of 16) with zero
+// columns.
+
+//
+// This header holds the tile machinery and the kernel templates, shared by
+// the float32 instantiations (stream_kernels.hip) and the 16-bit operand
+// ones (stream_kernels_lp.hip).  PR selects the matrix-core operand type:
+// float32 (v_mfma_f32_16x16x4_f32), or bfloat16 / float16 rounded from the
+// float32 tiles in LDS (v_mfma_f32_16x16x16_bf16 / _f16); accumulation is
+// float32 in every case.
+#pragma once
+
+#include "rcp_device.h"
+#include "rcp_kernels.h"
+
+namespace rcp {
+
+
+constexpr int JT = 32;            // tile width along the unfolding's columns
+constexpr int TS = JT + 4;        // LDS row stride of a tile (16-byte aligned rows)
+constexpr int NT = 256;           // threads per workgroup of the small kernels
+constexpr int NTS = 512;          // threads per workgroup of the streaming kernels (8 wavefronts)
+constexpr int NWS = NTS / 64;
+
+struct TileInfo {
+    int64_t j0;      // first unfolding column of the tile
+    int64_t a0;      // first a (case A: the a of the tile)
+    int64_t b0;      // first b (case A), 0 in case B
+    int width;       // number of valid columns (<= JT)
+    int na;          // case B: number of a-slabs in the tile
+};
+
+__device__ __forceinline__ TileInfo tile_info(const StreamGeom& g, int64_t t) {
+    TileInfo ti;
+    if (!g.caseB) {
+        const int64_t a = t / g.tiles_per_a;
+        const int64_t b0 = (t - a * g.tiles_per_a) * JT;
+        ti.a0 = a;
+        ti.b0 = b0;
+        ti.j0 = a * g.Rr + b0;
+        const int64_t w = g.Rr - b0;
+        ti.width = (int)(w < JT ? w : JT);
+        ti.na = 1;
+    } else {
+        const int64_t a0 = t * g.TA;
+        const int64_t left = g.L - a0;
+        ti.na = (int)(left < g.TA ? left : g.TA);
+        ti.a0 = a0;
+        ti.b0 = 0;
+        ti.j0 = a0 * g.Rr;
+        ti.width = ti.na * (int)g.Rr;
+    }
+    return ti;
+}
+
+// Register staging of one tile (rows [i_lo, i_lo + nrows) of a row block of
+// 64*MB rows): MB float4 slots per thread.  Case A slot f = tid + s*NTS
+// covers row f / 8, columns 4*(f % 8) .. +3 (one 16-byte load when aligned);
+// case B slot covers 4 consecutive floats of the contiguous slab data.
+template <int MB>
+struct TileRegs {
+    float4 v[MB];
+};
+
+// Case A (Rr >= JT) staging: row f / 8, columns 4*(f % 8) .. +3 of slot
+// f = tid + s*NTS.  Case B tiles (small trailing modes) use load_tile.
+template <int MB>
+__device__ __forceinline__ void tile_issue(const StreamGeom& g, const TileInfo& ti, int64_t i_lo,
+                                           int nrows, TileRegs<MB>& pf) {
+    const int tid = threadIdx.x;
+    const float* base = g.T + ((ti.a0 * g.I + i_lo) * g.Rr + ti.b0);
+#pragma unroll
+    for (int s = 0; s < MB; ++s) {
+        const int f = tid + s * NTS;
+        const int r = f >> 3, c0 = (f & 7) * 4;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (r < nrows && c0 < ti.width) {
+            const float* p = base + (int64_t)r * g.Rr + c0;
+            if (g.vec4 && c0 + 4 <= ti.width) {
+                v = *reinterpret_cast<const float4*>(p);
+            } else {
+                v.x = p[0];
+                if (c0 + 1 < ti.width) v.y = p[1];
+                if (c0 + 2 < ti.width) v.z = p[2];
+                if (c0 + 3 < ti.width) v.w = p[3];
+            }
+        }
+        pf.v[s] = v;
+    }
+}
+
+// Writes the staged tile into Ts (64*MB rows x JT, stride TS); every cell is
+// written (zeros outside the valid rows / columns).  Returns the float64
+// sum of squares of the staged values.
+template <int MB>
+__device__ __forceinline__ double tile_commit(const TileRegs<MB>& pf, float* Ts, bool want_sq) {
+    const int tid = threadIdx.x;
+    double sq = 0.0;
+#pragma unroll
+    for (int s = 0; s < MB; ++s) {
+        const int f = tid + s * NTS;
+        const int r = f >> 3, c0 = (f & 7) * 4;
+        *reinterpret_cast<float4*>(Ts + r * TS + c0) = pf.v[s];
+        if (want_sq) {
+            const float4 v = pf.v[s];
+            sq += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+        }
+    }
+    return sq;
+}
+
+// Unstaged load of rows [i_lo, i_lo + nrows) into Ts (rows_alloc x JT),
+// zero-filled outside the valid cells; returns the float64 sum of squares.
+__device__ __forceinline__ double load_tile(const StreamGeom& g, const TileInfo& ti, int64_t i_lo,
+                                            int nrows, int rows_alloc, float* Ts, bool want_sq) {
+    const int tid = threadIdx.x;
+    double sq = 0.0;
+    if (ti.width < JT || nrows < rows_alloc) {
+        for (int e = tid; e < rows_alloc * JT; e += NTS) {
+            const int r = e / JT, jj = e % JT;
+            if (r >= nrows || jj >= ti.width) Ts[r * TS + jj] = 0.0f;
+        }
+    }
+    if (!g.caseB) {
+        const float* base = g.T + ((ti.a0 * g.I + i_lo) * g.Rr + ti.b0);
+        const int total = nrows * JT;
+        for (int e = tid; e < total; e += NTS) {
+            const int r = e / JT, jj = e % JT;
+            if (jj < ti.width) {
+                const float v = base[(int64_t)r * g.Rr + jj];
+                Ts[r * TS + jj] = v;
+                if (want_sq) sq += (double)v * v;
+            }
+        }
+    } else {
+        const int rr = (int)g.Rr;
+        const int slab = nrows * rr;
+        const float inv_slab = 1.0f / (float)slab, inv_rr = 1.0f / (float)rr;
+        const int total = ti.na * slab;
+        for (int e = tid; e < total; e += NTS) {
+            const int arel = small_div(e, slab, inv_slab);
+            const int rem = e - arel * slab;
+            const int r = small_div(rem, rr, inv_rr);
+            const int b = rem - r * rr;
+            const float v = g.T[((ti.a0 + arel) * g.I + i_lo) * g.Rr + rem];
+            Ts[r * TS + arel * rr + b] = v;
+            if (want_sq) sq += (double)v * v;
+        }
+    }
+    return sq;
+}
+
+// Y[rows, 0:16*NB] += Ts[rows, 0:JT] * W[0:JT, 0:16*NB] for the row blocks
+// this wavefront owns: rb = wave + 8*m, m < MH = ceil(MB/2) (4*MB row blocks
+// of 16 rows in all; blocks past the end are skipped).
+template <int MB>
+struct MHalf { static constexpr int v = (MB + 1) / 2; };
+
+template <int NB, int MB, int PR>
+__device__ __forceinline__ void tile_times_w(const float* Ts, const float* W, int ldw,
+                                             f32x4 (&acc)[MHalf<MB>::v][NB]) {
+    constexpr int MH = MHalf<MB>::v;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    if constexpr (PR != kPrecFp32) {
+        // 16-bit operands: lane (lr, lk) feeds k = 4 lk .. 4 lk + 3 of a 16-deep step
+#pragma unroll
+        for (int k0 = 0; k0 < JT; k0 += 16) {
+            s16x4 b[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const float* wp = W + (k0 + 4 * lk) * ldw + nb * 16 + lr;
+                b[nb] = to_lp<PR>(make_float4(wp[0], wp[ldw], wp[2 * ldw], wp[3 * ldw]));
+            }
+#pragma unroll
+            for (int m = 0; m < MH; ++m) {
+                const int rb = wave + NWS * m;
+                if (rb < 4 * MB) {
+                    const s16x4 a = to_lp<PR>(
+                        *reinterpret_cast<const float4*>(Ts + (rb * 16 + lr) * TS + k0 + 4 * lk));
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) acc[m][nb] = mfma_lp<PR>(a, b[nb], acc[m][nb]);
+                }
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int k0 = 0; k0 < JT; k0 += 4) {
+        float b[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) b[nb] = W[(k0 + lk) * ldw + nb * 16 + lr];
+#pragma unroll
+        for (int m = 0; m < MH; ++m) {
+            const int rb = wave + NWS * m;
+            if (rb < 4 * MB) {
+                const float a = Ts[(rb * 16 + lr) * TS + k0 + lk];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) acc[m][nb] = mfma16x16x4(a, b[nb], acc[m][nb]);
+            }
+        }
+    }
+}
+
+// Partial z[jb*16 .. +16, 0:16*NB] = Ts[r, jb-block]^T Qs[r, :] over one
+// quarter of the rows: wavefront w takes column block jb = w / 4 and row
+// quarter w % 4 (rows is a multiple of 16).
+template <int NB, int PR>
+__device__ __forceinline__ void tile_t_times_q(const float* Ts, const float* Qs, int ldq,
+                                               int rows, f32x4 (&zacc)[NB]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int jb = wave >> 2, quarter = wave & 3;
+    const int per = rows / 4;
+    const int r_lo = quarter * per, r_hi = r_lo + per;
+    if constexpr (PR != kPrecFp32) {
+        // per is a multiple of 16 (rows = 64 MB or IC)
+        for (int k0 = r_lo; k0 < r_hi; k0 += 16) {
+            const float* tp = Ts + (k0 + 4 * lk) * TS + jb * 16 + lr;
+            const s16x4 a = to_lp<PR>(make_float4(tp[0], tp[TS], tp[2 * TS], tp[3 * TS]));
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const float* qp = Qs + (k0 + 4 * lk) * ldq + nb * 16 + lr;
+                zacc[nb] = mfma_lp<PR>(a, to_lp<PR>(make_float4(qp[0], qp[ldq], qp[2 * ldq], qp[3 * ldq])),
+                                       zacc[nb]);
+            }
+        }
+        return;
+    }
+#pragma unroll 2
+    for (int k0 = r_lo; k0 < r_hi; k0 += 4) {
+        const float a = Ts[(k0 + lk) * TS + jb * 16 + lr];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+            zacc[nb] = mfma16x16x4(a, Qs[(k0 + lk) * ldq + nb * 16 + lr], zacc[nb]);
+    }
+}
+
+// Store the wavefronts' partial z into zp[quarter][jj][c] and sum into zs.
+template <int NB>
+__device__ __forceinline__ void reduce_z(const f32x4 (&zacc)[NB], float* zp, float* zs) {
+    constexpr int LPc = NB * 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int jb = wave >> 2, quarter = wave & 3;
+    float* my = zp + quarter * JT * LPc;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            my[(jb * 16 + 4 * lk + v) * LPc + nb * 16 + lr] = zacc[nb][v];
+    __syncthreads();
+    for (int e = threadIdx.x; e < JT * LPc; e += NTS)
+        zs[e] = zp[e] + zp[JT * LPc + e] + zp[2 * JT * LPc + e] + zp[3 * JT * LPc + e];
+    __syncthreads();
+}
+
+template <int NB, int MB>
+__device__ __forceinline__ void store_partial(const f32x4 (&acc)[MHalf<MB>::v][NB], float* part,
+                                              int64_t I, int64_t row0) {
+    constexpr int LPc = NB * 16;
+    constexpr int MH = MHalf<MB>::v;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < MH; ++m) {
+        const int rb = wave + NWS * m;
+        if (rb < 4 * MB) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = row0 + rb * 16 + 4 * lk + v;
+                if (row < I) {
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) part[row * LPc + nb * 16 + lr] = acc[m][nb][v];
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// contract_out: partial Y = T_(n) W over the tiles of this workgroup, for
+// the row block blockIdx.y (64*MB rows).  W is the Gaussian test matrix
+// generated in registers (GEN) or a stored J x LP matrix in the layout
+// (L, LP, Rr) (power iteration with a stored Z).  Optional float64 partial
+// sum of squares of T (used for ||X||^2 in the first pass).
+
+template <int NB, int MB, bool GEN, bool CB, int PR>
+__global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const float* Z,
+                                                     uint64_t seed, uint32_t tag, float* part,
+                                                     double* sq_part) {
+    constexpr int LPc = NB * 16;
+    constexpr int IB = 64 * MB;
+    extern __shared__ __align__(16) float smem[];
+    float* Ts = smem;                       // IB x TS
+    float* Ws = Ts + IB * TS;               // JT x LPc
+    __shared__ double red[NWS];
+
+    const int64_t row0 = (int64_t)blockIdx.y * IB;
+    const int64_t rows_left = g.I - row0;
+    const int nrows = (int)(rows_left < IB ? rows_left : IB);
+
+    f32x4 acc[MHalf<MB>::v][NB];
+#pragma unroll
+    for (int m = 0; m < MHalf<MB>::v; ++m)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    double sq = 0.0;
+    const bool want_sq = sq_part != nullptr;
+    TileRegs<MB> pf;
+    int64_t t = blockIdx.x;
+    if (!CB && t < g.ntiles) tile_issue<MB>(g, tile_info(g, t), row0, nrows, pf);
+    for (; t < g.ntiles; t += gridDim.x) {
+        const TileInfo ti = tile_info(g, t);
+        __syncthreads();
+        if (CB) sq += load_tile(g, ti, row0, nrows, IB, Ts, want_sq);
+        else sq += tile_commit<MB>(pf, Ts, want_sq);
+        if (GEN) {
+            constexpr int NG = LPc / 4;
+            for (int e = threadIdx.x; e < JT * NG; e += NTS) {
+                const int jj = e / NG, gi = e % NG;
+                float z[4] = {0.f, 0.f, 0.f, 0.f};
+                if (jj < ti.width) omega4(seed, tag, (uint64_t)(ti.j0 + jj), (uint32_t)gi, z);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int c = 4 * gi + v;
+                    Ws[jj * LPc + c] = (c < l) ? z[v] : 0.0f;
+                }
+            }
+        } else {
+            for (int e = threadIdx.x; e < JT * LPc; e += NTS) {
+                const int jj = e % JT, c = e / JT;
+                float v = 0.0f;
+                if (jj < ti.width) {
+                    int64_t a, b;
+                    if (!g.caseB) { a = ti.a0; b = ti.b0 + jj; }
+                    else { a = ti.a0 + jj / g.Rr; b = jj % g.Rr; }
+                    v = Z[(a * LPc + c) * g.Rr + b];
+                }
+                Ws[jj * LPc + c] = v;
+            }
+        }
+        const int64_t tn = t + gridDim.x;
+        if (!CB && tn < g.ntiles) tile_issue<MB>(g, tile_info(g, tn), row0, nrows, pf);
+        __syncthreads();
+        tile_times_w<NB, MB, PR>(Ts, Ws, LPc, acc);
+    }
+    store_partial<NB, MB>(acc, part + (int64_t)blockIdx.x * g.I * LPc, g.I, row0);
+    if (want_sq) {
+        const double s = block_sum(sq, red);
+        if (threadIdx.x == 0) sq_part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// power_fused: partial Y = T_(n) (T_(n)^T Qt) in one pass over T.  Each tile
+// (all I rows, I <= 64*MB) is held in LDS: first z = tile^T Qt (JT x LP),
+// then Y += tile z.  The normalisation of Z in Algorithm 1 step 9 is an
+// invertible upper-triangular right factor, which the QR of the next sketch
+// absorbs, so it is not applied.
+
+template <int NB, int MB, bool FUSED, bool CB, int PR>
+__global__ __launch_bounds__(NTS) void k_power_fused(StreamGeom g, const float* Qt, float* part,
+                                                    int lout, float* out) {
+    constexpr int LPc = NB * 16;
+    constexpr int IB = 64 * MB;
+    extern __shared__ __align__(16) float smem[];
+    float* Ts = smem;                       // IB x TS
+    float* Qs = Ts + IB * TS;               // IB x LPc
+    float* zp = Qs + IB * LPc;              // 4 x JT x LPc
+    float* zs = zp + 4 * JT * LPc;          // JT x LPc
+
+    const int I = (int)g.I;
+    for (int e = threadIdx.x; e < IB * LPc; e += NTS) {
+        const int r = e / LPc;
+        Qs[e] = (r < I) ? Qt[e] : 0.0f;
+    }
+
+    f32x4 acc[MHalf<MB>::v][NB];
+#pragma unroll
+    for (int m = 0; m < MHalf<MB>::v; ++m)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    TileRegs<MB> pf;
+    int64_t t = blockIdx.x;
+    if (!CB && t < g.ntiles) tile_issue<MB>(g, tile_info(g, t), 0, I, pf);
+    for (; t < g.ntiles; t += gridDim.x) {
+        const TileInfo ti = tile_info(g, t);
+        __syncthreads();
+        if (CB) load_tile(g, ti, 0, I, IB, Ts, false);
+        else tile_commit<MB>(pf, Ts, false);
+        const int64_t tn = t + gridDim.x;
+        if (!CB && tn < g.ntiles) tile_issue<MB>(g, tile_info(g, tn), 0, I, pf);
+        __syncthreads();
+        f32x4 zacc[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) zacc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        tile_t_times_q<NB, PR>(Ts, Qs, LPc, IB, zacc);
+        reduce_z<NB>(zacc, zp, zs);
+        if (FUSED) {
+            tile_times_w<NB, MB, PR>(Ts, zs, LPc, acc);
+        } else {
+            // mode product: write z^T into the (L, lout, Rr) output
+            for (int e = threadIdx.x; e < lout * JT; e += NTS) {
+                const int c = e / JT, jj = e % JT;
+                if (jj < ti.width) {
+                    int64_t a, b;
+                    if (!g.caseB) { a = ti.a0; b = ti.b0 + jj; }
+                    else { a = ti.a0 + jj / g.Rr; b = jj % g.Rr; }
+                    out[(a * lout + c) * g.Rr + b] = zs[jj * LPc + c];
+                }
+            }
+        }
+    }
+    if (FUSED) store_partial<NB, MB>(acc, part + (int64_t)blockIdx.x * g.I * LPc, g.I, 0);
+}
+
+// ---------------------------------------------------------------------------
+// contract_in: out[a, c, b] = sum_i Q[i, c] T[a, i, b] for c < lout
+// (Algorithm 1 step 13, T x_n Q^T; also Z = T_(n)^T Qt for the two-pass
+// power iteration).  Rows are streamed in chunks of IC through LDS.
+
+constexpr int IC = 128;
+
+template <int NB, int PR>
+__global__ __launch_bounds__(NTS) void k_contract_in(StreamGeom g, const float* Q, int lout,
+                                                    float* out) {
+    constexpr int LPc = NB * 16;
+    extern __shared__ float smem[];
+    float* Ts = smem;                       // IC x TS
+    float* Qs = Ts + IC * TS;               // IC x LPc
+    float* zp = Qs + IC * LPc;              // 4 x JT x LPc
+    float* zs = zp + 4 * JT * LPc;          // JT x LPc
+
+    for (int64_t t = blockIdx.x; t < g.ntiles; t += gridDim.x) {
+        const TileInfo ti = tile_info(g, t);
+        f32x4 zacc[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) zacc[nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int64_t i_lo = 0; i_lo < g.I; i_lo += IC) {
+            const int64_t left = g.I - i_lo;
+            const int nrows = (int)(left < IC ? left : IC);
+            __syncthreads();
+            load_tile(g, ti, i_lo, nrows, IC, Ts, false);
+            for (int e = threadIdx.x; e < IC * LPc; e += NTS) {
+                const int r = e / LPc;
+                Qs[e] = (r < nrows) ? Q[(i_lo + r) * LPc + (e - r * LPc)] : 0.0f;
+            }
+            __syncthreads();
+            tile_t_times_q<NB, PR>(Ts, Qs, LPc, IC, zacc);
+        }
+        reduce_z<NB>(zacc, zp, zs);
+        // write z^T into the (L, lout, Rr) output
+        for (int e = threadIdx.x; e < lout * JT; e += NTS) {
+            const int c = e / JT, jj = e % JT;
+            if (jj < ti.width) {
+                int64_t a, b;
+                if (!g.caseB) { a = ti.a0; b = ti.b0 + jj; }
+                else { a = ti.a0 + jj / g.Rr; b = jj % g.Rr; }
+                out[(a * lout + c) * g.Rr + b] = zs[jj * LPc + c];
+            }
+        }
+    }
+}
+
+inline int lp_blocks(int l) { return (l + 15) / 16; }
+
+inline size_t contract_out_smem(int NB, int MB) {
+    return (size_t)(64 * MB * TS + JT * NB * 16) * sizeof(float);
+}
+
+inline size_t power_fused_smem(int NB, int MB) {
+    const int IB = 64 * MB, LPc = NB * 16;
+    return (size_t)(IB * TS + IB * LPc + 4 * JT * LPc + JT * LPc) * sizeof(float);
+}
+
+inline size_t contract_in_smem(int NB) {
+    const int LPc = NB * 16;
+    return (size_t)(IC * TS + IC * LPc + 4 * JT * LPc + JT * LPc) * sizeof(float);
+}
+
+template <int NB, int MB, bool GEN, int PR>
+static hipError_t launch_co(dim3 grid, size_t smem, hipStream_t s, const StreamGeom& g, int l,
+                            const float* Z, uint64_t seed, uint32_t tag, float* part,
+                            double* sq) {
+    auto k = g.caseB ? k_contract_out<NB, MB, GEN, true, PR> : k_contract_out<NB, MB, GEN, false, PR>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, grid, dim3(NTS), smem, s, g, l, Z, seed, tag, part, sq);
+    return hipGetLastError();
+}
+
+#define RCP_MB_SWITCH(MBV, ...)                                   \
+    switch (MBV) {                                                \
+        case 1: { constexpr int MB = 1; __VA_ARGS__; } break;     \
+        case 2: { constexpr int MB = 2; __VA_ARGS__; } break;     \
+        case 3: { constexpr int MB = 3; __VA_ARGS__; } break;     \
+        case 4: { constexpr int MB = 4; __VA_ARGS__; } break;     \
+        case 5: { constexpr int MB = 5; __VA_ARGS__; } break;     \
+        case 6: { constexpr int MB = 6; __VA_ARGS__; } break;     \
+        case 7: { constexpr int MB = 7; __VA_ARGS__; } break;     \
+        default: { constexpr int MB = 8; __VA_ARGS__; } break;    \
+    }
+
+#define RCP_NB_SWITCH(NBV, ...)                                   \
+    switch (NBV) {                                                \
+        case 1: { constexpr int NB = 1; __VA_ARGS__; } break;     \
+        case 2: { constexpr int NB = 2; __VA_ARGS__; } break;     \
+        case 3: { constexpr int NB = 3; __VA_ARGS__; } break;     \
+        default: { constexpr int NB = 4; __VA_ARGS__; } break;    \
+    }
+
+template <int PR>
+hipError_t launch_contract_out_t(const StreamGeom& g, int l, const float* Z, uint64_t seed,
+                                 uint32_t tag, float* part, int P, double* sq_part,
+                                 hipStream_t s) {
+    const int NBv = lp_blocks(l);
+    int MBv = (int)((g.I + 63) / 64);
+    if (MBv > 8) MBv = 8;
+    const int IB = 64 * MBv;
+    const unsigned nIB = (unsigned)((g.I + IB - 1) / IB);
+    const size_t smem = contract_out_smem(NBv, MBv);
+    const dim3 grid((unsigned)P, nIB);
+    hipError_t e = hipSuccess;
+    if (Z == nullptr) {
+        RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_co<NB, MB, true, PR>(grid, smem, s, g, l, Z, seed, tag, part, sq_part))));
+    } else {
+        RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_co<NB, MB, false, PR>(grid, smem, s, g, l, Z, seed, tag, part, sq_part))));
+    }
+    return e;
+}
+
+template <int NB, int MB, bool FUSED, int PR>
+static hipError_t launch_pf(int P, size_t smem, hipStream_t s, const StreamGeom& g,
+                            const float* Qt, float* part, int lout, float* out) {
+    auto k = g.caseB ? k_power_fused<NB, MB, FUSED, true, PR> : k_power_fused<NB, MB, FUSED, false, PR>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)P), dim3(NTS), smem, s, g, Qt, part, lout, out);
+    return hipGetLastError();
+}
+
+template <int PR>
+hipError_t launch_power_fused_t(const StreamGeom& g, int l, const float* Qt, float* part, int P,
+                                hipStream_t s) {
+    const int NBv = lp_blocks(l);
+    const int MBv = (int)((g.I + 63) / 64);
+    const size_t smem = power_fused_smem(NBv, MBv);
+    hipError_t e = hipSuccess;
+    RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_pf<NB, MB, true, PR>(P, smem, s, g, Qt, part, 0, nullptr))));
+    return e;
+}
+
+template <int NB, int PR>
+static hipError_t launch_ci(int P, size_t smem, hipStream_t s, const StreamGeom& g,
+                            const float* Q, int lout, float* out) {
+    auto k = k_contract_in<NB, PR>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)P), dim3(NTS), smem, s, g, Q, lout, out);
+    return hipGetLastError();
+}
+
+// T x_n Q^T (or Z = T_(n)^T Q): the whole basis resident in LDS when the
+// mode is short enough, else streamed in row chunks.
+template <int PR>
+hipError_t launch_contract_in_t(const StreamGeom& g, int l, const float* Qpadded, int lout,
+                                float* out, int P, hipStream_t s) {
+    const int NBv = lp_blocks(l);
+    hipError_t e = hipSuccess;
+    if (power_fused_fits(g.I, l, 160 * 1024)) {
+        const int MBv = (int)((g.I + 63) / 64);
+        const size_t smem = power_fused_smem(NBv, MBv);
+        RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_pf<NB, MB, false, PR>(P, smem, s, g, Qpadded, nullptr, lout, out))));
+        return e;
+    }
+    const size_t smem = contract_in_smem(NBv);
+    RCP_NB_SWITCH(NBv, e = (launch_ci<NB, PR>(P, smem, s, g, Qpadded, lout, out)));
+    return e;
+}
+
+
+}  // namespace rcp
