@@ -411,23 +411,70 @@ __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, c
 // Blocked Gauss-Jordan elimination without pivoting on the augmented system
 // Aug = [V | Xt] (Rp x (Rp + ln), row stride ldx), V symmetric positive
 // definite (padded with identity up to Rp, a multiple of GB): on return the
-// right part holds V^{-1} Xt.  GB pivots per step: every thread inverts the
-// GB x GB pivot block in registers (plain Gauss-Jordan, whose pivots are the
-// successive Schur complements, i.e. the pivots of unblocked elimination)
-// and updates its elements with the GB pivot rows and columns.  The pivot
-// rows and columns of the next step are written to a second buffer while the
-// current ones are read, so a step needs a single barrier; columns left of
-// the pivot block are never read again and are not updated.  pb holds
-// 2 GB (ldx + Rp) doubles.  Returns 0 when a pivot of the first R is not
-// above thr.
+// right part holds V^{-1} Xt.  GB pivots per step: the update of entry
+// (i, c) is a_ic - sum_t f_it u_tc with u = P^{-1} p_c, P the GB x GB pivot
+// block (plain Gauss-Jordan inverse, whose pivots are the successive Schur
+// complements, i.e. the pivots of unblocked elimination), p_c and f_i the
+// pivot rows and columns.  Wavefront 0 owns the next pivot block: it updates
+// those GB x GB entries itself, inverts the result and publishes the inverse
+// while the other wavefronts update the rest, so nobody inverts on the
+// critical path of a step and a step needs one barrier.  The pivot rows and
+// columns of the next step go to the other half of a double buffer.
+// Columns left of the pivot block are never read again and are not updated.
+// pb holds 2 GB (ldx + Rp) + 2 GB^2 + 1 doubles.  Returns 0 when a pivot of
+// the first R is not above thr.
 constexpr int GB = 4;
+
+// Gauss-Jordan inverse of the GB x GB block m (destroyed); pivots of rows
+// row0 + t < R must exceed thr.
+__device__ __forceinline__ int invert_block(double (&m)[GB][GB], double (&inv)[GB][GB], int row0,
+                                            int R, double thr) {
+    int ok = 1;
+#pragma unroll
+    for (int t = 0; t < GB; ++t)
+#pragma unroll
+        for (int s2 = 0; s2 < GB; ++s2) inv[t][s2] = (t == s2) ? 1.0 : 0.0;
+#pragma unroll
+    for (int t = 0; t < GB; ++t) {
+        const double piv = m[t][t];
+        const bool real = row0 + t < R;
+        if (real && !(piv > thr)) ok = 0;
+        const double ip = 1.0 / (piv > thr ? piv : (real ? thr : 1.0));
+#pragma unroll
+        for (int s2 = 0; s2 < GB; ++s2) { m[t][s2] *= ip; inv[t][s2] *= ip; }
+#pragma unroll
+        for (int r = 0; r < GB; ++r) {
+            if (r == t) continue;
+            const double f = m[r][t];
+#pragma unroll
+            for (int s2 = 0; s2 < GB; ++s2) {
+                m[r][s2] -= f * m[t][s2];
+                inv[r][s2] -= f * inv[t][s2];
+            }
+        }
+    }
+    return ok;
+}
+
+// entry e = t GB + s of a register block, selected without dynamic indexing
+__device__ __forceinline__ double pick_block(const double (&m)[GB][GB], int e) {
+    double v = 0.0;
+#pragma unroll
+    for (int t = 0; t < GB; ++t)
+#pragma unroll
+        for (int s2 = 0; s2 < GB; ++s2)
+            if (e == t * GB + s2) v = m[t][s2];
+    return v;
+}
 
 __device__ __forceinline__ int block_gj(double* Aug, int ldx, int R, int Rp, int ln, double* pb,
                                         double thr) {
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int W = Rp + ln;
-    double* prow0 = pb;                       // [2][GB][ldx]
-    double* pcol0 = pb + 2 * GB * ldx;        // [2][GB][Rp]
+    double* prow0 = pb;                              // [2][GB][ldx]
+    double* pcol0 = pb + 2 * GB * ldx;               // [2][GB][Rp]
+    double* pinv0 = pcol0 + 2 * GB * Rp;             // [2][GB][GB]
+    double* okp = pinv0 + 2 * GB * GB;               // 1.0 while every pivot is fine
     for (int e = tid; e < GB * W; e += ANT) {
         const int t = e / W, cc = e - (e / W) * W;
         prow0[t * ldx + cc] = Aug[t * ldx + cc];
@@ -436,48 +483,32 @@ __device__ __forceinline__ int block_gj(double* Aug, int ldx, int R, int Rp, int
         const int t = e / Rp, i = e - (e / Rp) * Rp;
         pcol0[t * Rp + i] = Aug[i * ldx + t];
     }
-    __syncthreads();
-    int ok = 1;
-    for (int j = 0; j < Rp; j += GB) {
-        const int cur = (j / GB) & 1, nxt = cur ^ 1;
-        const double* pr = prow0 + cur * GB * ldx;
-        const double* pc = pcol0 + cur * GB * Rp;
-        double* nr = prow0 + nxt * GB * ldx;
-        double* nc = pcol0 + nxt * GB * Rp;
-        // inverse of the pivot block
+    if (wave == 0) {
         double m[GB][GB], inv[GB][GB];
 #pragma unroll
         for (int t = 0; t < GB; ++t)
 #pragma unroll
-            for (int s2 = 0; s2 < GB; ++s2) {
-                m[t][s2] = pr[t * ldx + j + s2];
-                inv[t][s2] = (t == s2) ? 1.0 : 0.0;
-            }
+            for (int s2 = 0; s2 < GB; ++s2) m[t][s2] = Aug[t * ldx + s2];
+        const int ok = invert_block(m, inv, 0, R, thr);
+        if (lane < GB * GB) pinv0[lane] = pick_block(inv, lane);
+        if (lane == 0) *okp = ok ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < Rp; j += GB) {
+        const int cur = (j / GB) & 1, nxt = cur ^ 1;
+        const double* pr = prow0 + cur * GB * ldx;
+        const double* pc = pcol0 + cur * GB * Rp;
+        const double* pv = pinv0 + cur * GB * GB;
+        double* nr = prow0 + nxt * GB * ldx;
+        double* nc = pcol0 + nxt * GB * Rp;
+        double inv[GB][GB];
 #pragma unroll
-        for (int t = 0; t < GB; ++t) {
-            const double piv = m[t][t];
-            const bool real = j + t < R;
-            if (real && !(piv > thr)) ok = 0;
-            const double ip = 1.0 / (piv > thr ? piv : (real ? thr : 1.0));
+        for (int t = 0; t < GB; ++t)
 #pragma unroll
-            for (int s2 = 0; s2 < GB; ++s2) { m[t][s2] *= ip; inv[t][s2] *= ip; }
-#pragma unroll
-            for (int r = 0; r < GB; ++r) {
-                if (r == t) continue;
-                const double f = m[r][t];
-#pragma unroll
-                for (int s2 = 0; s2 < GB; ++s2) {
-                    m[r][s2] -= f * m[t][s2];
-                    inv[r][s2] -= f * inv[t][s2];
-                }
-            }
-        }
-        const int wc = W - j - GB;
-        const int cnt = Rp * wc;
-        const float inv_wc = __builtin_amdgcn_rcpf((float)wc);
-        for (int e = tid; e < cnt; e += ANT) {
-            const int i = small_div(e, wc, inv_wc);
-            const int cc = j + GB + (e - i * wc);
+            for (int s2 = 0; s2 < GB; ++s2) inv[t][s2] = pv[t * GB + s2];
+        const int jn = j + GB;                       // first row / column of the next block
+        // update of entry (i, cc) of this step, the same arithmetic for everyone
+        auto updated = [&](int i, int cc) -> double {
             double p[GB], u[GB];
 #pragma unroll
             for (int t = 0; t < GB; ++t) p[t] = pr[t * ldx + cc];
@@ -499,15 +530,72 @@ __device__ __forceinline__ int block_gj(double* Aug, int ldx, int R, int Rp, int
 #pragma unroll
                 for (int t = 0; t < GB; ++t) na -= pc[t * Rp + i] * u[t];
             }
-            Aug[i * ldx + cc] = na;
-            const int tn = i - (j + GB);
-            if (tn >= 0 && tn < GB) nr[tn * ldx + cc] = na;
-            const int cn = cc - (j + GB);
-            if (cn >= 0 && cn < GB) nc[cn * Rp + i] = na;
+            return na;
+        };
+        if (wave == 0) {
+            if (jn < Rp) {
+                // the next pivot block: update, gather, invert, publish
+                const int tn = (lane >> 2) & (GB - 1), cn = lane & (GB - 1);
+                double na = 0.0;
+                if (lane < GB * GB) {
+                    const int i = jn + tn, cc = jn + cn;
+                    na = updated(i, cc);
+                    Aug[i * ldx + cc] = na;
+                    nr[tn * ldx + cc] = na;
+                    nc[cn * Rp + i] = na;
+                }
+                double m[GB][GB], inv2[GB][GB];
+#pragma unroll
+                for (int t = 0; t < GB; ++t)
+#pragma unroll
+                    for (int s2 = 0; s2 < GB; ++s2) m[t][s2] = __shfl(na, t * GB + s2, 64);
+                const int ok = invert_block(m, inv2, jn, R, thr);
+                if (lane < GB * GB) pinv0[nxt * GB * GB + lane] = pick_block(inv2, lane);
+                if (lane == 0 && !ok) *okp = 0.0;
+            }
+        } else {
+            // thread t owns column jn + t % wc and rows t / wc, + G, ... so that
+            // u = P^{-1} p of its column is formed once
+            const int wc = W - jn;
+            const int G = max(1, (ANT - 64) / wc);
+            const int t = tid - 64;
+            if (t < G * wc) {
+                const int g = small_div(t, wc, __builtin_amdgcn_rcpf((float)wc));
+                const int cc = jn + (t - g * wc);
+                const int cn = cc - jn;
+                double p[GB], u[GB];
+#pragma unroll
+                for (int q = 0; q < GB; ++q) p[q] = pr[q * ldx + cc];
+#pragma unroll
+                for (int q = 0; q < GB; ++q) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int s2 = 0; s2 < GB; ++s2) acc += inv[q][s2] * p[s2];
+                    u[q] = acc;
+                }
+                for (int i = g; i < Rp; i += G) {
+                    const int tn = i - jn;
+                    if (tn >= 0 && tn < GB && cn < GB) continue;     // wavefront 0's block
+                    const int ti = i - j;
+                    double na;
+                    if (ti >= 0 && ti < GB) {
+                        na = u[0];
+#pragma unroll
+                        for (int q = 1; q < GB; ++q) if (ti == q) na = u[q];
+                    } else {
+                        na = Aug[i * ldx + cc];
+#pragma unroll
+                        for (int q = 0; q < GB; ++q) na -= pc[q * Rp + i] * u[q];
+                    }
+                    Aug[i * ldx + cc] = na;
+                    if (tn >= 0 && tn < GB) nr[tn * ldx + cc] = na;
+                    if (cn < GB) nc[cn * Rp + i] = na;
+                }
+            }
         }
         __syncthreads();
     }
-    return ok;
+    return *okp != 0.0;
 }
 
 // Left block of the augmented system: V = *_{m != n} G_m, identity padding up
@@ -672,7 +760,7 @@ __global__ __launch_bounds__(ANT) void k_als(AlsArgs a) {
     float* ones = (float*)p; p += RCP_MAX_RANK * sizeof(float);
     double* G = (double*)p;  p += (size_t)N * R * R * sizeof(double);
     double* Aug = (double*)p; p += (size_t)Rp * ldx * sizeof(double);
-    double* pb = (double*)p; p += (size_t)2 * GB * (ldx + Rp) * sizeof(double);
+    double* pb = (double*)p; p += (size_t)(2 * GB * (ldx + Rp) + 2 * GB * GB + 1) * sizeof(double);
     float* P = (float*)p;    p += (size_t)als_part_floats(N, a.l, R) * sizeof(float);
     double* M = a.Ebuf + 2 * kEigLd * kEigLd;            // l_n x R, global (read by the fit and the fallback)
     double* E = EIG_IN_LDS ? (double*)p : a.Ebuf;
@@ -772,7 +860,7 @@ static size_t als_lds_fixed(int N, const int* l, int R) {
     b += RCP_MAX_RANK * sizeof(float);                        // ones
     b += (size_t)N * R * R * sizeof(double);                  // G
     b += (size_t)Rp * ldx * sizeof(double);                   // augmented system [V | M^T]
-    b += (size_t)2 * GB * (ldx + Rp) * sizeof(double);        // pivot row / column buffers
+    b += (size_t)(2 * GB * (ldx + Rp) + 2 * GB * GB + 1) * sizeof(double);  // pivot buffers
     b += (size_t)als_part_floats(N, l, R) * sizeof(float);    // partial products
     return b;
 }
