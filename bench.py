@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rcp400")
     ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--concurrent", type=int, default=6, metavar="S",
+                    help="also time independent solves on S streams (0 skips)")
     ap.add_argument("--mixed-steps", type=int, default=10,
                     help="timed solves with bfloat16 and float16 operands (0 skips the comparison)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -192,6 +194,37 @@ def main():
                   "frac_fp32_mfma": sf / (sm * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS,
                   "ms_per_step": sm / args.profile_steps} if sm > 0 else None
 
+    conc = None
+    if args.concurrent > 1:
+        # S independent plans, each bound to its own stream: one solve's single-CU ALS
+        # overlaps the next solves' grid-wide streaming passes
+        S = args.concurrent
+        streams = [torch.cuda.Stream(device=dev) for _ in range(S)]
+        slots = []
+        for st in streams:
+            with torch.cuda.stream(st):
+                pl = rcpgpu.Plan(dims, cfg["k"], cfg["p"], cfg["q"], cfg["iters"], 0.0, cfg["seed"],
+                                 device=dev)
+                As = [torch.empty((d, cfg["k"]), dtype=torch.float32, device=dev) for d in dims]
+                ls = torch.empty((cfg["k"],), dtype=torch.float32, device=dev)
+                slots.append((pl, As, ls, pl._info_buffer()))
+        torch.cuda.synchronize()
+        for pl, As, ls, inf in slots:
+            pl.decompose_into(X, As, ls, inf)
+        torch.cuda.synchronize()
+        total = S * max(2, args.steps // S)
+        t0 = time.perf_counter()
+        for i in range(total):
+            pl, As, ls, inf = slots[i % S]
+            pl.decompose_into(X, As, ls, inf)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        errs = [rcpgpu.Plan.read_info(inf)["rel_err"] for _, _, _, inf in slots]
+        conc = {"streams": S, "solves": total, "solves_per_s": total / dt,
+                "speedup_vs_one_stream": (total / dt) / value,
+                "rel_err_max_abs_diff": max(abs(e - res["rel_err"]) for e in errs),
+                "timing": "host wall clock around the issue of all solves and a device sync"}
+
     mixed = {}
     if args.mixed_steps > 0:
         for prec in ("bf16", "fp16"):
@@ -223,6 +256,7 @@ def main():
         "sketch_ttm": sketch_ttm,
         "kernels": kern,
         "mixed_vs_fp32": mixed or None,
+        "concurrent_streams": conc,
         "cpu_baseline": None,
     }
     if args.cpu_seconds > 0:
