@@ -212,6 +212,38 @@ rcp_status rcp_profile(rcp_plan plan, int32_t enable);
 rcp_status rcp_profile_read(rcp_plan plan, int32_t kernel_class, int64_t* launches, double* ms,
                             double* bytes, double* flops);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent problems.  Algorithms 1 and 2 applied to `count`
+ * unrelated tensors (uneven shapes, ranks and seeds) as one unit of work:
+ * the compression passes of every problem are enqueued back to back, then
+ * one launch runs CP-ALS for all of them (one workgroup per problem) and one
+ * launch the back-projection.  The paper treats one tensor at a time; this is
+ * the throughput form for many small ones.  Each problem gives exactly the
+ * result rcp_decompose gives it alone.
+ *
+ * rcp_batch_workspace_size: bytes of device workspace for probs[0..count).
+ *   RCP_ERR_INVALID_ARG / RCP_ERR_UNSUPPORTED as rcp_init for any problem.
+ * rcp_batch_init: binds the workspace (device, 256-byte aligned) and the
+ *   stream, and fixes the outputs: A[i][n] (device, I_n x k_i float32,
+ *   row-major), lambda[i] (device, k_i float32) and info[i] (device array of
+ *   count rcp_als_info).  A and lambda are host arrays of device pointers,
+ *   read during the call only.  The device argument tables of the batched
+ *   launches are written into the workspace with a synchronous copy.
+ * rcp_batch_decompose: X[i] (host array of count device pointers to the
+ *   C-order float32 tensors).  On a non-null stream the first call records
+ *   the whole sequence in a HIP graph and launches it; later calls with the
+ *   same X pointers relaunch the graph (other pointers re-record it).  On
+ *   the null stream the kernels are enqueued directly.  Asynchronous like
+ *   every other call; numeric outcomes land in info[i].
+ * rcp_batch_destroy: frees the host-side state (the graph included). */
+typedef struct rcp_batch_t* rcp_batch;
+rcp_status rcp_batch_workspace_size(const rcp_problem* probs, int32_t count, size_t* bytes);
+rcp_status rcp_batch_init(rcp_batch* batch, const rcp_problem* probs, int32_t count,
+                          float* const* const* A, float* const* lambda, rcp_als_info* info,
+                          void* workspace, size_t workspace_bytes, void* hip_stream);
+rcp_status rcp_batch_decompose(rcp_batch batch, const float* const* X);
+rcp_status rcp_batch_destroy(rcp_batch batch);
+
 /* Static description of a status code. */
 const char* rcp_status_string(rcp_status status);
 

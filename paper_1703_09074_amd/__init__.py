@@ -226,6 +226,87 @@ class Plan:
         return out
 
 
+class Batch:
+    """Independent problems decomposed as one unit (rcp_batch_*): the outputs
+    (factors, lambda, info) are allocated here and bound at creation; the
+    batch runs on the current HIP stream of ``device`` at creation (a
+    non-default stream records the work in a HIP graph on the first call).
+
+    problems: sequence of dicts with keys dims, k and optionally p, q,
+    max_iters, tol, seed, precision, scheme.
+    """
+
+    def __init__(self, problems, device="cuda"):
+        torch = _torch()
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        self.count = len(problems)
+        arr = (_lib.Problem * self.count)()
+        self.dims = []
+        self.k = []
+        for i, pr in enumerate(problems):
+            dims = [int(d) for d in pr["dims"]]
+            arr[i] = _lib.make_problem(dims, pr["k"], pr.get("p", 10), pr.get("q", 2),
+                                       pr.get("max_iters", 50), pr.get("tol", 0.0),
+                                       pr.get("seed", 0), pr.get("precision", "fp32"),
+                                       pr.get("scheme", "sequential"))
+            self.dims.append(dims)
+            self.k.append(int(pr["k"]))
+        self._problems = arr
+        nbytes = ctypes.c_size_t(0)
+        _lib.check(self.lib.rcp_batch_workspace_size(arr, self.count, ctypes.byref(nbytes)),
+                   "rcp_batch_workspace_size")
+        self.workspace = torch.empty(max(256, nbytes.value), dtype=torch.uint8, device=self.device)
+        self.A = [[torch.empty((d, k), dtype=torch.float32, device=self.device) for d in dims]
+                  for dims, k in zip(self.dims, self.k)]
+        self.lam = [torch.empty((k,), dtype=torch.float32, device=self.device) for k in self.k]
+        self.info = torch.zeros(self.count * ctypes.sizeof(_lib.AlsInfo), dtype=torch.uint8,
+                                device=self.device)
+        rows = [_lib.ptr_array([a.data_ptr() for a in As]) for As in self.A]
+        self._rows = rows
+        A_arg = (ctypes.POINTER(ctypes.c_void_p) * self.count)(
+            *[ctypes.cast(r, ctypes.POINTER(ctypes.c_void_p)) for r in rows])
+        lam_arg = _lib.ptr_array([t.data_ptr() for t in self.lam])
+        self.stream = _stream_handle(torch, self.device)
+        handle = ctypes.c_void_p(0)
+        _lib.check(self.lib.rcp_batch_init(ctypes.byref(handle), arr, self.count, A_arg, lam_arg,
+                                           ctypes.c_void_p(self.info.data_ptr()),
+                                           ctypes.c_void_p(self.workspace.data_ptr()),
+                                           ctypes.c_size_t(self.workspace.numel()), self.stream),
+                   "rcp_batch_init")
+        self.handle = handle
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.rcp_batch_destroy(h)
+            self.handle = None
+
+    def decompose(self, Xs) -> None:
+        """Enqueue the decomposition of every tensor (float32 CUDA, shapes as
+        given at creation); results land in .A, .lam and .info."""
+        if len(Xs) != self.count:
+            raise ValueError(f"expected {self.count} tensors, got {len(Xs)}")
+        for X, dims in zip(Xs, self.dims):
+            _f32(X, "X")
+            if list(X.shape) != dims:
+                raise ValueError(f"tensor of shape {list(X.shape)} where {dims} was planned")
+        self._X = list(Xs)
+        _lib.check(self.lib.rcp_batch_decompose(self.handle,
+                                                _lib.ptr_array([X.data_ptr() for X in Xs])),
+                   "rcp_batch_decompose")
+
+    def read_info(self):
+        raw = bytes(self.info.cpu().numpy().tobytes())
+        sz = ctypes.sizeof(_lib.AlsInfo)
+        out = []
+        for i in range(self.count):
+            info = _lib.AlsInfo.from_buffer_copy(raw[i * sz:(i + 1) * sz])
+            out.append(dict(iters=info.iters, status=info.status, rho=info.rho,
+                            rel_err=info.rel_err, normX2=info.normX2))
+        return out
+
+
 def decompose(X, k: int, p: int = 10, q: int = 2, iters: int = 50, tol: float = 0.0,
               seed: int = 0, scheme: str = "sequential", precision: str = "fp32"):
     """Randomized CP of X (Algorithm 2).  Returns (lambda, [A_n], info dict)."""

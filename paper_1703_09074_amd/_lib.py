@@ -76,6 +76,13 @@ SIGNATURES = {
     "rcp_profile_read": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_double)]),
+    "rcp_batch_workspace_size": (_st, [ctypes.POINTER(Problem), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_size_t)]),
+    "rcp_batch_init": (_st, [ctypes.POINTER(_vp), ctypes.POINTER(Problem), ctypes.c_int32,
+                             ctypes.POINTER(ctypes.POINTER(_vp)), ctypes.POINTER(_vp), _vp, _vp,
+                             ctypes.c_size_t, _vp]),
+    "rcp_batch_decompose": (_st, [_vp, ctypes.POINTER(_vp)]),
+    "rcp_batch_destroy": (_st, [_vp]),
     "rcp_status_string": (ctypes.c_char_p, [_st]),
     "rcp_version": (ctypes.c_char_p, []),
 }

@@ -712,7 +712,7 @@ __device__ __forceinline__ int solve_update(const AlsCtx& c, int n, double* G, c
 }
 
 template <int NN, bool B_IN_LDS, bool EIG_IN_LDS>
-__global__ __launch_bounds__(ANT) void k_als(AlsArgs a) {
+__device__ __forceinline__ void als_body(const AlsArgs& a) {
     extern __shared__ __align__(16) unsigned char als_smem[];
     __shared__ double red[ANW];
     __shared__ double sh[128];
@@ -848,6 +848,19 @@ __global__ __launch_bounds__(ANT) void k_als(AlsArgs a) {
     }
 }
 
+template <int NN, bool B_IN_LDS, bool EIG_IN_LDS>
+__global__ __launch_bounds__(ANT) void k_als(AlsArgs a) {
+    als_body<NN, B_IN_LDS, EIG_IN_LDS>(a);
+}
+
+// One workgroup per problem of a batch; every problem's layout fits the
+// launch's LDS size and template choice (the launcher takes the maxima).
+template <int NN, bool B_IN_LDS, bool EIG_IN_LDS>
+__global__ __launch_bounds__(ANT) void k_als_batch(const AlsArgs* args) {
+    const AlsArgs& a = args[blockIdx.x];
+    als_body<NN, B_IN_LDS, EIG_IN_LDS>(a);
+}
+
 static size_t als_lds_fixed(int N, const int* l, int R) {
     size_t b = 0;
     int lmax = 0;
@@ -913,6 +926,52 @@ hipError_t launch_als(const AlsArgs& a, hipStream_t s) {
     if (a.N == 3) return launch_als_n<3>(a, bl, el, smem, s);
     if (a.N == 4) return launch_als_n<4>(a, bl, el, smem, s);
     return launch_als_n<RCP_MAX_NDIM>(a, bl, el, smem, s);
+}
+
+template <int NN, bool BL, bool EL>
+static hipError_t launch_als_batch_t(const AlsArgs* dargs, int count, size_t smem, hipStream_t s) {
+    auto k = k_als_batch<NN, BL, EL>;
+    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kAlsLds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)count), dim3(ANT), smem, s, dargs);
+    return hipGetLastError();
+}
+
+template <int NN>
+static hipError_t launch_als_batch_n(const AlsArgs* dargs, int count, bool bl, bool el, size_t smem,
+                                     hipStream_t s) {
+    if (bl && el) return launch_als_batch_t<NN, true, true>(dargs, count, smem, s);
+    if (bl) return launch_als_batch_t<NN, true, false>(dargs, count, smem, s);
+    if (el) return launch_als_batch_t<NN, false, true>(dargs, count, smem, s);
+    return launch_als_batch_t<NN, false, false>(dargs, count, smem, s);
+}
+
+hipError_t launch_als_batch(const AlsArgs* dargs, const AlsArgs* hargs, int count, hipStream_t s) {
+    if (count < 1) return hipSuccess;
+    size_t fixed = 0, bmax = 0;
+    int N0 = hargs[0].N;
+    bool sameN = true;
+    for (int i = 0; i < count; ++i) {
+        const AlsArgs& a = hargs[i];
+        const size_t f = als_lds_fixed(a.N, a.l, a.R);
+        fixed = f > fixed ? f : fixed;
+        int64_t S = 1;
+        for (int n = 0; n < a.N; ++n) S *= a.l[n];
+        const size_t b = (size_t)S * sizeof(float);
+        bmax = b > bmax ? b : bmax;
+        sameN = sameN && a.N == N0;
+    }
+    const size_t eig = 2 * kEigLd * kEigLd * sizeof(double);
+    const bool bl = fixed + bmax <= kAlsLds;
+    const bool el = fixed + eig <= kAlsLds;
+    size_t big = 0;
+    if (bl) big = bmax;
+    if (el && eig > big) big = eig;
+    const size_t smem = fixed + big;
+    if (sameN && N0 == 3) return launch_als_batch_n<3>(dargs, count, bl, el, smem, s);
+    if (sameN && N0 == 4) return launch_als_batch_n<4>(dargs, count, bl, el, smem, s);
+    return launch_als_batch_n<RCP_MAX_NDIM>(dargs, count, bl, el, smem, s);
 }
 
 }  // namespace rcp

@@ -503,13 +503,11 @@ rcp_status rcp_expand(rcp_plan plan, const float* const* Q, const float* const* 
     return expand_impl(plan, Q, At, lambda_in, A, lambda_out);
 }
 
-rcp_status rcp_decompose(rcp_plan plan, const float* X, float* const* A, float* lambda,
-                         rcp_als_info* info) {
-    if (plan == nullptr || X == nullptr || A == nullptr || lambda == nullptr || info == nullptr)
-        return RCP_ERR_INVALID_ARG;
-    for (int n = 0; n < plan->L.N; ++n)
-        if (A[n] == nullptr || !aligned(A[n], 4)) return RCP_ERR_INVALID_ARG;
-    if (!aligned(X, 4) || !aligned(info, 8)) return RCP_ERR_INVALID_ARG;
+namespace {
+
+// Algorithm 1 over every mode: leaves the bases in the plan's qb buffers and
+// the core in the tb buffer of the last mode; *core_out points at it.
+rcp_status compress_all(rcp_plan_t* plan, const float* X, const float** core_out) {
     const Layout& L = plan->L;
     const int N = L.N;
     double* normX2 = plan->at<double>(L.norm);
@@ -544,15 +542,226 @@ rcp_status rcp_decompose(rcp_plan plan, const float* X, float* const* A, float* 
             T = out;
         }
     }
+    *core_out = T;
+    return RCP_OK;
+}
+
+AlsArgs core_als_args(rcp_plan_t* plan, const float* core, rcp_als_info* info) {
+    const Layout& L = plan->L;
+    AlsArgs a{};
+    a.B = core;
+    a.N = L.N;
+    for (int n = 0; n < L.N; ++n) { a.l[n] = L.l[n]; a.At[n] = plan->at<float>(L.at[n]); }
+    a.R = L.R;
+    a.max_iters = plan->prob.max_iters;
+    a.tol = plan->prob.tol;
+    a.normX2 = plan->at<double>(L.norm);
+    a.lambda = plan->at<float>(L.lam);
+    a.info = info;
+    a.Ebuf = plan->at<double>(L.als);
+    return a;
+}
+
+ExpandArgs core_expand_args(rcp_plan_t* plan, float* const* A, float* lambda) {
+    const Layout& L = plan->L;
+    ExpandArgs e{};
+    e.N = L.N;
+    e.R = L.R;
+    for (int n = 0; n < L.N; ++n) {
+        e.I[n] = L.dims[n];
+        e.l[n] = L.l[n];
+        e.Q[n] = plan->at<float>(L.qb[n]);
+        e.At[n] = plan->at<float>(L.at[n]);
+        e.A[n] = A[n];
+    }
+    e.lambda_in = plan->at<float>(L.lam);
+    e.lambda_out = lambda;
+    e.raw = plan->at<double>(L.raw);
+    return e;
+}
+
+}  // namespace
+
+rcp_status rcp_decompose(rcp_plan plan, const float* X, float* const* A, float* lambda,
+                         rcp_als_info* info) {
+    if (plan == nullptr || X == nullptr || A == nullptr || lambda == nullptr || info == nullptr)
+        return RCP_ERR_INVALID_ARG;
+    for (int n = 0; n < plan->L.N; ++n)
+        if (A[n] == nullptr || !aligned(A[n], 4)) return RCP_ERR_INVALID_ARG;
+    if (!aligned(X, 4) || !aligned(info, 8)) return RCP_ERR_INVALID_ARG;
+    const Layout& L = plan->L;
+    const int N = L.N;
+    const float* core = nullptr;
+    rcp_status st = compress_all(plan, X, &core);
+    if (st != RCP_OK) return st;
     float* At[RCP_MAX_NDIM];
     for (int n = 0; n < N; ++n) At[n] = plan->at<float>(L.at[n]);
     float* lam = plan->at<float>(L.lam);
-    st = als_impl(plan, T, At, lam, normX2, info);
+    st = als_impl(plan, core, At, lam, plan->at<double>(L.norm), info);
     if (st != RCP_OK) return st;
     const float* Qc[RCP_MAX_NDIM];
     const float* Atc[RCP_MAX_NDIM];
-    for (int n = 0; n < N; ++n) { Qc[n] = Qb[n]; Atc[n] = At[n]; }
+    for (int n = 0; n < N; ++n) { Qc[n] = plan->at<float>(L.qb[n]); Atc[n] = At[n]; }
     return expand_impl(plan, Qc, Atc, lam, A, lambda);
+}
+
+// ---------------------------------------------------------------------------
+// Batches of independent problems
+
+struct rcp_batch_t {
+    int count = 0;
+    hipStream_t stream = nullptr;
+    std::vector<rcp_plan_t*> plans;
+    std::vector<AlsArgs> h_als;
+    std::vector<ExpandArgs> h_exp;
+    AlsArgs* d_als = nullptr;
+    ExpandArgs* d_exp = nullptr;
+    std::vector<const float*> X;          // inputs of the captured graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool use_graph = false;
+};
+
+namespace {
+
+struct BatchLayout {
+    std::vector<size_t> off, size;
+    size_t als = 0, exp = 0, total = 0;
+};
+
+rcp_status batch_layout(const rcp_problem* probs, int32_t count, BatchLayout* out) {
+    if (probs == nullptr || count < 1) return RCP_ERR_INVALID_ARG;
+    BatchLayout B;
+    size_t off = 0;
+    for (int i = 0; i < count; ++i) {
+        if (!valid_problem(&probs[i])) return RCP_ERR_INVALID_ARG;
+        const Layout L = make_layout(&probs[i]);
+        if (!als_supported(L.N, L.l, L.R)) return RCP_ERR_UNSUPPORTED;
+        B.off.push_back(off);
+        B.size.push_back(L.total);
+        off = align_up(off + L.total);
+    }
+    B.als = off;
+    off = align_up(off + (size_t)count * sizeof(AlsArgs));
+    B.exp = off;
+    off = align_up(off + (size_t)count * sizeof(ExpandArgs));
+    B.total = off;
+    *out = B;
+    return RCP_OK;
+}
+
+rcp_status batch_enqueue(rcp_batch_t* b, const float* const* X) {
+    for (int i = 0; i < b->count; ++i) {
+        const float* core = nullptr;
+        rcp_status st = compress_all(b->plans[i], X[i], &core);
+        if (st != RCP_OK) return st;
+        if (core != b->h_als[i].B) return RCP_ERR_HIP;   // layout invariant
+    }
+    RCP_TRY(launch_als_batch(b->d_als, b->h_als.data(), b->count, b->stream));
+    RCP_TRY(launch_expand_batch(b->d_exp, b->h_exp.data(), b->count, b->stream));
+    return RCP_OK;
+}
+
+void batch_drop_graph(rcp_batch_t* b) {
+    if (b->exec != nullptr) hipGraphExecDestroy(b->exec);
+    if (b->graph != nullptr) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+}  // namespace
+
+rcp_status rcp_batch_workspace_size(const rcp_problem* probs, int32_t count, size_t* bytes) {
+    if (bytes == nullptr) return RCP_ERR_INVALID_ARG;
+    BatchLayout B;
+    rcp_status st = batch_layout(probs, count, &B);
+    if (st != RCP_OK) return st;
+    *bytes = B.total;
+    return RCP_OK;
+}
+
+rcp_status rcp_batch_init(rcp_batch* batch, const rcp_problem* probs, int32_t count,
+                          float* const* const* A, float* const* lambda, rcp_als_info* info,
+                          void* workspace, size_t workspace_bytes, void* hip_stream) {
+    if (batch == nullptr) return RCP_ERR_INVALID_ARG;
+    *batch = nullptr;
+    BatchLayout B;
+    rcp_status st = batch_layout(probs, count, &B);
+    if (st != RCP_OK) return st;
+    if (A == nullptr || lambda == nullptr || info == nullptr || !aligned(info, 8))
+        return RCP_ERR_INVALID_ARG;
+    for (int i = 0; i < count; ++i) {
+        if (A[i] == nullptr || lambda[i] == nullptr) return RCP_ERR_INVALID_ARG;
+        for (int n = 0; n < probs[i].ndim; ++n)
+            if (A[i][n] == nullptr || !aligned(A[i][n], 4)) return RCP_ERR_INVALID_ARG;
+    }
+    if (workspace == nullptr || workspace_bytes < B.total || !aligned(workspace, kAlign))
+        return RCP_ERR_WORKSPACE;
+    rcp_batch_t* b = new (std::nothrow) rcp_batch_t;
+    if (b == nullptr) return RCP_ERR_HIP;
+    b->count = count;
+    b->stream = (hipStream_t)hip_stream;
+    char* ws = (char*)workspace;
+    for (int i = 0; i < count; ++i) {
+        rcp_plan pl = nullptr;
+        st = rcp_init(&pl, &probs[i], ws + B.off[i], B.size[i], hip_stream);
+        if (st != RCP_OK) { rcp_batch_destroy(b); return st; }
+        b->plans.push_back(pl);
+        const Layout& L = pl->L;
+        const float* core = pl->at<float>(L.tb[(L.N - 1) % 2]);
+        b->h_als.push_back(core_als_args(pl, core, info + i));
+        b->h_exp.push_back(core_expand_args(pl, A[i], lambda[i]));
+    }
+    b->d_als = (AlsArgs*)(ws + B.als);
+    b->d_exp = (ExpandArgs*)(ws + B.exp);
+    if (hipMemcpy(b->d_als, b->h_als.data(), count * sizeof(AlsArgs), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b->d_exp, b->h_exp.data(), count * sizeof(ExpandArgs), hipMemcpyHostToDevice) != hipSuccess) {
+        rcp_batch_destroy(b);
+        return RCP_ERR_HIP;
+    }
+    b->use_graph = hip_stream != nullptr;
+    *batch = b;
+    return RCP_OK;
+}
+
+rcp_status rcp_batch_decompose(rcp_batch batch, const float* const* X) {
+    if (batch == nullptr || X == nullptr) return RCP_ERR_INVALID_ARG;
+    for (int i = 0; i < batch->count; ++i)
+        if (X[i] == nullptr || !aligned(X[i], 4)) return RCP_ERR_INVALID_ARG;
+    if (!batch->use_graph) return batch_enqueue(batch, X);
+    bool same = batch->exec != nullptr && (int)batch->X.size() == batch->count;
+    for (int i = 0; same && i < batch->count; ++i) same = batch->X[i] == X[i];
+    if (!same) {
+        batch_drop_graph(batch);
+        if (hipStreamBeginCapture(batch->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            batch->use_graph = false;
+            return batch_enqueue(batch, X);
+        }
+        const rcp_status st = batch_enqueue(batch, X);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(batch->stream, &g);
+        if (st != RCP_OK) {
+            if (g != nullptr) hipGraphDestroy(g);
+            return st;
+        }
+        if (ec != hipSuccess || g == nullptr) return RCP_ERR_HIP;
+        batch->graph = g;
+        if (hipGraphInstantiate(&batch->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            batch_drop_graph(batch);
+            return RCP_ERR_HIP;
+        }
+        batch->X.assign(X, X + batch->count);
+    }
+    RCP_TRY(hipGraphLaunch(batch->exec, batch->stream));
+    return RCP_OK;
+}
+
+rcp_status rcp_batch_destroy(rcp_batch batch) {
+    if (batch == nullptr) return RCP_ERR_INVALID_ARG;
+    batch_drop_graph(batch);
+    for (rcp_plan_t* p : batch->plans) rcp_destroy(p);
+    delete batch;
+    return RCP_OK;
 }
 
 rcp_status rcp_get_bases(rcp_plan plan, float** Q) {

@@ -78,6 +78,8 @@ struct AlsArgs {
     double* Ebuf;              // Jacobi scratch (2 x 64 x 64), then M_n (l_max x R)
 };
 hipError_t launch_als(const AlsArgs& a, hipStream_t s);
+// one launch for `count` problems: dargs on the device, hargs the same on the host
+hipError_t launch_als_batch(const AlsArgs* dargs, const AlsArgs* hargs, int count, hipStream_t s);
 size_t als_workspace_doubles(int N, const int* l, int R);
 bool als_supported(int N, const int* l, int R);
 
@@ -95,5 +97,7 @@ struct ExpandArgs {
     double* raw;               // scratch: sum_n I_n x R
 };
 hipError_t launch_expand(const ExpandArgs& a, hipStream_t s);
+hipError_t launch_expand_batch(const ExpandArgs* dargs, const ExpandArgs* hargs, int count,
+                               hipStream_t s);
 
 }  // namespace rcp

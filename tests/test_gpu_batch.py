@@ -1,0 +1,88 @@
+"""Batches of independent problems (rcp_batch_*): uneven shapes, ranks and
+seeds in one unit of work, CP-ALS and the back-projection in one launch each.
+
+  * every problem of a batch gets exactly what rcp_decompose gives it alone
+    (the same kernels and arithmetic);
+  * every problem matches the float64 oracle (relative error within 1e-4,
+    congruence >= 0.999);
+  * on a non-default stream the batch is recorded in a HIP graph: three
+    replays, with eager PyTorch work and synchronisations between them, each
+    equal the directly enqueued batch.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1703_09074_amd as rcpgpu  # noqa: E402
+from oracle import evaluate, rcp  # noqa: E402
+from paper_1703_09074_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _problems(count, seed, lo, hi, iters):
+    probs, tensors = [], []
+    for dims, R, dseed in synth.batch_problems(count, seed, lo=lo, hi=hi, rlo=3, rhi=8):
+        w = synth.low_rank(dims, R, 0.05, dseed)
+        probs.append(dict(dims=dims, k=R, p=10, q=2, max_iters=iters, seed=dseed % 9973))
+        tensors.append(w.X)
+    return probs, tensors
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def test_batch_equals_single_and_oracle():
+    probs, tensors = _problems(10, 5, 24, 60, 30)
+    Xs = [torch.from_numpy(x).cuda() for x in tensors]
+    b = rcpgpu.Batch(probs)
+    b.decompose(Xs)
+    torch.cuda.synchronize()
+    infos = b.read_info()
+    for i, (pr, x) in enumerate(zip(probs, tensors)):
+        plan = rcpgpu.Plan(pr["dims"], pr["k"], pr["p"], pr["q"], pr["max_iters"], 0.0, pr["seed"])
+        lam, A, info = plan.decompose(Xs[i])
+        torch.cuda.synchronize()
+        single = rcpgpu.Plan.read_info(info)
+        assert infos[i]["iters"] == pr["max_iters"] and infos[i]["status"] == single["status"]
+        assert infos[i]["rho"] == single["rho"], (i, infos[i]["rho"], single["rho"])
+        np.testing.assert_array_equal(_np(b.lam[i]), _np(lam))
+        for n in range(len(pr["dims"])):
+            np.testing.assert_array_equal(_np(b.A[i][n]), _np(A[n]))
+        ref = rcp.rcp_als(x.astype(np.float64), pr["k"], pr["p"], pr["q"], pr["max_iters"], 0.0,
+                          pr["seed"])
+        e_ref = evaluate.relative_error(x, ref.lam, ref.factors)
+        e_gpu = evaluate.relative_error(x, _np(b.lam[i]), [_np(a) for a in b.A[i]])
+        cong = evaluate.congruence([_np(a) for a in b.A[i]], ref.factors)[0]
+        assert abs(e_gpu - e_ref) <= 1e-4, (i, e_gpu, e_ref)
+        assert cong >= 0.999, (i, cong)
+
+
+def test_batch_graph_replays():
+    probs, tensors = _problems(6, 9, 20, 48, 20)
+    Xs = [torch.from_numpy(x).cuda() for x in tensors]
+    eager = rcpgpu.Batch(probs)                 # default stream: no graph
+    eager.decompose(Xs)
+    torch.cuda.synchronize()
+    want_lam = [_np(t) for t in eager.lam]
+    want_A = [[_np(a) for a in As] for As in eager.A]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = rcpgpu.Batch(probs)
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            g.decompose(Xs)                     # first call records, then replays
+        torch.cuda.synchronize()
+        for i in range(len(probs)):
+            np.testing.assert_array_equal(_np(g.lam[i]), want_lam[i])
+            for n in range(len(probs[i]["dims"])):
+                np.testing.assert_array_equal(_np(g.A[i][n]), want_A[i][n])
+        # eager work of the program between replays
+        for t in g.lam:
+            t.zero_()
+        for As in g.A:
+            for a in As:
+                a.fill_(3.0)
+        torch.cuda.synchronize()
