@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 if HERE not in sys.path:
     sys.path.insert(0, HERE)
@@ -57,6 +59,9 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--concurrent", type=int, default=6, metavar="S",
                     help="also time independent solves on S streams (0 skips)")
+    ap.add_argument("--batch", type=int, default=512, metavar="COUNT",
+                    help="also time a batch of COUNT independent small problems (0 skips)")
+    ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--mixed-steps", type=int, default=10,
                     help="timed solves with bfloat16 and float16 operands (0 skips the comparison)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -105,6 +110,71 @@ def cpu_baseline(X, cfg, budget_s):
              "kind": "oracle",
              "sample": f"{n} whole solve(s) of the same workload in float64 NumPy/SciPy ({dt:.1f} s)"},
             rel_err)
+
+
+def batch_workload(count, seed=20170331):
+    """The batched workload: `count` independent 3-way tensors, every mode size
+    uniform on [32, 256], true rank R uniform on [4, 16], factors N(0,1),
+    noise 0.05 rms; k = R, p = 10, q = 2, 50 sweeps, bfloat16 range finder."""
+    from paper_1703_09074_amd import synth
+    probs = []
+    for dims, R, dseed in synth.batch_problems(count, seed, lo=32, hi=256, rlo=4, rhi=16):
+        probs.append(dict(dims=list(dims), k=R, p=10, q=2, max_iters=50, seed=dseed % 100003,
+                          precision="bf16", R=R, data_seed=dseed))
+    return probs
+
+
+def run_batch(args, torch, rcpgpu, dev):
+    from paper_1703_09074_amd import synth
+    probs = batch_workload(args.batch)
+    Xs = []
+    for pr in probs:
+        X, _, _, _ = synth.low_rank_device(pr["dims"], pr["R"], 0.05, pr["data_seed"], device=dev)
+        Xs.append(X)
+    elems = sum(int(np.prod(pr["dims"])) for pr in probs)
+    s = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        b = rcpgpu.Batch([{k: v for k, v in pr.items() if k not in ("R", "data_seed")} for pr in probs],
+                         device=dev)
+        t0 = time.perf_counter()
+        b.decompose(Xs)                       # records the graph and runs it once
+    torch.cuda.synchronize()
+    first = time.perf_counter() - t0
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(s):
+        e0.record(s)
+        for _ in range(args.batch_steps):
+            b.decompose(Xs)
+        e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.batch_steps
+    infos = b.read_info()
+    errs = [i["rel_err"] for i in infos]
+    out = {"problems": args.batch, "elements": elems, "ms_per_batch": ms,
+           "solves_per_s": args.batch * 1000.0 / ms, "first_call_s_with_graph_recording": first,
+           "rel_err_mean": float(np.mean(errs)), "rel_err_max": float(np.max(errs)),
+           "status_nonzero": int(sum(1 for i in infos if i["status"] != 0)),
+           "workload": "3-way tensors, modes U{32..256}, R U{4..16}, noise 0.05, k=R, p=10, q=2, "
+                       "50 sweeps, bf16 range finder"}
+    if args.cpu_seconds > 0:
+        # the oracle on a bounded sample of the same problems
+        from oracle import rcp
+        n, t0, diffs = 0, time.perf_counter(), []
+        for i, pr in enumerate(probs):
+            x = Xs[i].cpu().numpy().astype(np.float64)
+            r = rcp.rcp_als(x, pr["k"], pr["p"], pr["q"], pr["max_iters"], 0.0, pr["seed"])
+            diffs.append(abs(float(np.sqrt(max(0.0, 1.0 - r.rho))) - errs[i]))
+            n += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n / dt, "unit": "solves/s",
+                               "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+                               "sample": f"the first {n} problems of the batch in float64 ({dt:.1f} s)",
+                               "max_abs_rel_err_diff_vs_gpu": float(max(diffs))}
+    return out
 
 
 def main():
@@ -225,6 +295,8 @@ def main():
                 "rel_err_max_abs_diff": max(abs(e - res["rel_err"]) for e in errs),
                 "timing": "host wall clock around the issue of all solves and a device sync"}
 
+    batched = run_batch(args, torch, rcpgpu, dev) if args.batch > 0 else None
+
     mixed = {}
     if args.mixed_steps > 0:
         for prec in ("bf16", "fp16"):
@@ -257,6 +329,7 @@ def main():
         "kernels": kern,
         "mixed_vs_fp32": mixed or None,
         "concurrent_streams": conc,
+        "batched": batched,
         "cpu_baseline": None,
     }
     if args.cpu_seconds > 0:
