@@ -215,9 +215,10 @@ rcp_status rcp_profile_read(rcp_plan plan, int32_t kernel_class, int64_t* launch
 /* ------------------------------------------------------------------------
  * Batches of independent problems.  Algorithms 1 and 2 applied to `count`
  * unrelated tensors (uneven shapes, ranks and seeds) as one unit of work:
- * the compression passes of every problem are enqueued back to back, then
- * one launch runs CP-ALS for all of them (one workgroup per problem) and one
- * launch the back-projection.  The paper treats one tensor at a time; this is
+ * the compression passes of the problems are spread over a few internal
+ * streams forked from and joined back into the batch stream (so small
+ * problems' kernels run side by side), then one launch runs CP-ALS for all
+ * of them (one workgroup per problem) and one launch the back-projection.  The paper treats one tensor at a time; this is
  * the throughput form for many small ones.  Each problem gives exactly the
  * result rcp_decompose gives it alone.
  *

@@ -608,9 +608,14 @@ rcp_status rcp_decompose(rcp_plan plan, const float* X, float* const* A, float* 
 // ---------------------------------------------------------------------------
 // Batches of independent problems
 
+constexpr int kBatchStreams = 16;       // branches the problems' compressions are spread over
+
 struct rcp_batch_t {
     int count = 0;
     hipStream_t stream = nullptr;
+    hipStream_t side[kBatchStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kBatchStreams] = {};
     std::vector<rcp_plan_t*> plans;
     std::vector<AlsArgs> h_als;
     std::vector<ExpandArgs> h_exp;
@@ -650,12 +655,22 @@ rcp_status batch_layout(const rcp_problem* probs, int32_t count, BatchLayout* ou
     return RCP_OK;
 }
 
+// The compressions of the problems go round-robin to the side streams (forked
+// from and joined back into the batch stream by events, so a recorded graph
+// gets independent branches); CP-ALS and the back-projection of all problems
+// then run as one launch each on the batch stream.
 rcp_status batch_enqueue(rcp_batch_t* b, const float* const* X) {
+    RCP_TRY(hipEventRecord(b->fork, b->stream));
+    for (int s = 0; s < kBatchStreams; ++s) RCP_TRY(hipStreamWaitEvent(b->side[s], b->fork, 0));
     for (int i = 0; i < b->count; ++i) {
         const float* core = nullptr;
         rcp_status st = compress_all(b->plans[i], X[i], &core);
         if (st != RCP_OK) return st;
         if (core != b->h_als[i].B) return RCP_ERR_HIP;   // layout invariant
+    }
+    for (int s = 0; s < kBatchStreams; ++s) {
+        RCP_TRY(hipEventRecord(b->join[s], b->side[s]));
+        RCP_TRY(hipStreamWaitEvent(b->stream, b->join[s], 0));
     }
     RCP_TRY(launch_als_batch(b->d_als, b->h_als.data(), b->count, b->stream));
     RCP_TRY(launch_expand_batch(b->d_exp, b->h_exp.data(), b->count, b->stream));
@@ -701,10 +716,15 @@ rcp_status rcp_batch_init(rcp_batch* batch, const rcp_problem* probs, int32_t co
     if (b == nullptr) return RCP_ERR_HIP;
     b->count = count;
     b->stream = (hipStream_t)hip_stream;
+    bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+    for (int s = 0; ok && s < kBatchStreams; ++s)
+        ok = hipStreamCreateWithFlags(&b->side[s], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&b->join[s], hipEventDisableTiming) == hipSuccess;
+    if (!ok) { rcp_batch_destroy(b); return RCP_ERR_HIP; }
     char* ws = (char*)workspace;
     for (int i = 0; i < count; ++i) {
         rcp_plan pl = nullptr;
-        st = rcp_init(&pl, &probs[i], ws + B.off[i], B.size[i], hip_stream);
+        st = rcp_init(&pl, &probs[i], ws + B.off[i], B.size[i], b->side[i % kBatchStreams]);
         if (st != RCP_OK) { rcp_batch_destroy(b); return st; }
         b->plans.push_back(pl);
         const Layout& L = pl->L;
@@ -760,6 +780,11 @@ rcp_status rcp_batch_destroy(rcp_batch batch) {
     if (batch == nullptr) return RCP_ERR_INVALID_ARG;
     batch_drop_graph(batch);
     for (rcp_plan_t* p : batch->plans) rcp_destroy(p);
+    for (int s = 0; s < kBatchStreams; ++s) {
+        if (batch->side[s] != nullptr) hipStreamDestroy(batch->side[s]);
+        if (batch->join[s] != nullptr) hipEventDestroy(batch->join[s]);
+    }
+    if (batch->fork != nullptr) hipEventDestroy(batch->fork);
     delete batch;
     return RCP_OK;
 }
