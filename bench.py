@@ -192,11 +192,17 @@ def main():
     from paper_1703_09074_amd import synth
 
     cfg = dict(synth.WORKLOADS[args.workload])
-    w = synth.make(args.workload)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    X = torch.from_numpy(w.X).to(dev)
-    dims = list(w.X.shape)
+    dims = list(cfg["dims"])
+    if int(np.prod(dims)) <= 100_000_000:
+        w_X = synth.make(args.workload).X
+        X = torch.from_numpy(w_X).to(dev)
+    else:
+        # too large to build on the host quickly: the same recipe assembled on the GPU
+        X, _, _, _ = synth.low_rank_device(dims, cfg["R"], cfg["noise"], cfg["data_seed"],
+                                           kind=cfg["kind"], device=dev)
+        w_X = None
     def run(precision, steps, warmup):
         plan = rcpgpu.Plan(dims, cfg["k"], cfg["p"], cfg["q"], cfg["iters"], 0.0, cfg["seed"],
                            device=dev, precision=precision)
@@ -332,8 +338,8 @@ def main():
         "batched": batched,
         "cpu_baseline": None,
     }
-    if args.cpu_seconds > 0:
-        cb, oracle_err = cpu_baseline(w.X, cfg, args.cpu_seconds)
+    if args.cpu_seconds > 0 and w_X is not None:
+        cb, oracle_err = cpu_baseline(w_X, cfg, args.cpu_seconds)
         out["cpu_baseline"] = cb
         out["oracle_rel_err"] = oracle_err
         # mixed precision counts only at equal error: both within 1e-4 of the oracle's

@@ -19,6 +19,7 @@ struct StreamGeom {
     int32_t pad_;
     int64_t tiles_per_a;   // case A
     int64_t ntiles;
+    int64_t Is;            // rows between consecutive a-slabs in memory (I unless a row slice)
 };
 
 StreamGeom make_geom(const float* T, const int64_t* dims, int ndim, int mode);

@@ -101,6 +101,7 @@ StreamGeom make_geom(const float* T, const int64_t* dims, int ndim, int mode) {
     for (int m = 0; m < mode; ++m) g.L *= dims[m];
     for (int m = mode + 1; m < ndim; ++m) g.Rr *= dims[m];
     g.I = dims[mode];
+    g.Is = g.I;
     g.vec4 = ((g.Rr % 4) == 0 && ((uintptr_t)T % 16) == 0) ? 1 : 0;
     if (g.Rr >= JT) {
         g.caseB = 0;

@@ -82,7 +82,7 @@ template <int MB>
 __device__ __forceinline__ void tile_issue(const StreamGeom& g, const TileInfo& ti, int64_t i_lo,
                                            int nrows, TileRegs<MB>& pf) {
     const int tid = threadIdx.x;
-    const float* base = g.T + ((ti.a0 * g.I + i_lo) * g.Rr + ti.b0);
+    const float* base = g.T + ((ti.a0 * g.Is + i_lo) * g.Rr + ti.b0);
 #pragma unroll
     for (int s = 0; s < MB; ++s) {
         const int f = tid + s * NTS;
@@ -136,7 +136,7 @@ __device__ __forceinline__ double load_tile(const StreamGeom& g, const TileInfo&
         }
     }
     if (!g.caseB) {
-        const float* base = g.T + ((ti.a0 * g.I + i_lo) * g.Rr + ti.b0);
+        const float* base = g.T + ((ti.a0 * g.Is + i_lo) * g.Rr + ti.b0);
         const int total = nrows * JT;
         for (int e = tid; e < total; e += NTS) {
             const int r = e / JT, jj = e % JT;
@@ -156,7 +156,7 @@ __device__ __forceinline__ double load_tile(const StreamGeom& g, const TileInfo&
             const int rem = e - arel * slab;
             const int r = small_div(rem, rr, inv_rr);
             const int b = rem - r * rr;
-            const float v = g.T[((ti.a0 + arel) * g.I + i_lo) * g.Rr + rem];
+            const float v = g.T[((ti.a0 + arel) * g.Is + i_lo) * g.Rr + rem];
             Ts[r * TS + arel * rr + b] = v;
             if (want_sq) sq += (double)v * v;
         }
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const
 
 template <int NB, int MB, bool FUSED, bool CB, int PR>
 __global__ __launch_bounds__(NTS) void k_power_fused(StreamGeom g, const float* Qt, float* part,
-                                                    int lout, float* out) {
+                                                    int lout, float* out, int accumulate) {
     constexpr int LPc = NB * 16;
     constexpr int IB = 64 * MB;
     extern __shared__ __align__(16) float smem[];
@@ -423,7 +423,8 @@ __global__ __launch_bounds__(NTS) void k_power_fused(StreamGeom g, const float* 
                     int64_t a, b;
                     if (!g.caseB) { a = ti.a0; b = ti.b0 + jj; }
                     else { a = ti.a0 + jj / g.Rr; b = jj % g.Rr; }
-                    out[(a * lout + c) * g.Rr + b] = zs[jj * LPc + c];
+                    float* o = out + (a * lout + c) * g.Rr + b;
+                    *o = accumulate ? *o + zs[jj * LPc + c] : zs[jj * LPc + c];
                 }
             }
         }
@@ -549,12 +550,13 @@ hipError_t launch_contract_out_t(const StreamGeom& g, int l, const float* Z, uin
 
 template <int NB, int MB, bool FUSED, int PR>
 static hipError_t launch_pf(int P, size_t smem, hipStream_t s, const StreamGeom& g,
-                            const float* Qt, float* part, int lout, float* out) {
+                            const float* Qt, float* part, int lout, float* out,
+                            int accumulate = 0) {
     auto k = g.caseB ? k_power_fused<NB, MB, FUSED, true, PR> : k_power_fused<NB, MB, FUSED, false, PR>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)smem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((unsigned)P), dim3(NTS), smem, s, g, Qt, part, lout, out);
+    hipLaunchKernelGGL(k, dim3((unsigned)P), dim3(NTS), smem, s, g, Qt, part, lout, out, accumulate);
     return hipGetLastError();
 }
 
@@ -591,6 +593,26 @@ hipError_t launch_contract_in_t(const StreamGeom& g, int l, const float* Qpadded
         const int MBv = (int)((g.I + 63) / 64);
         const size_t smem = power_fused_smem(NBv, MBv);
         RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_pf<NB, MB, false, PR>(P, smem, s, g, Qpadded, nullptr, lout, out))));
+        return e;
+    }
+    // Taller modes: slices of the rows whose basis rows fit in LDS, each a
+    // resident-basis pass over its rows that adds its share of T^T Q into
+    // the output (in slice order, so the sums are deterministic).
+    int MBs = 8;
+    while (MBs > 1 && power_fused_smem(NBv, MBs) > 160 * 1024) --MBs;
+    if (power_fused_smem(NBv, MBs) <= 160 * 1024) {
+        const int64_t Ir = 64 * MBs;
+        for (int64_t i0 = 0; i0 < g.I; i0 += Ir) {
+            StreamGeom g2 = g;
+            g2.T = g.T + i0 * g.Rr;
+            g2.I = (g.I - i0 < Ir) ? g.I - i0 : Ir;
+            const int MBv = (int)((g2.I + 63) / 64);
+            const size_t smem = power_fused_smem(NBv, MBv);
+            const float* Qs = Qpadded + i0 * (int64_t)(16 * NBv);
+            const int acc = i0 > 0 ? 1 : 0;
+            RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_pf<NB, MB, false, PR>(P, smem, s, g2, Qs, nullptr, lout, out, acc))));
+            if (e != hipSuccess) return e;
+        }
         return e;
     }
     const size_t smem = contract_in_smem(NBv);
