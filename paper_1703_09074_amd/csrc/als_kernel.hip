@@ -621,9 +621,41 @@ __device__ __forceinline__ void hadamard_grams(const AlsCtx& c, int n, const dou
     }
 }
 
+// G = F^T F (R x R, float64) of the float32 factor F (l_n x R, LDS) on the
+// float64 matrix cores: 16 x 16 blocks of the upper triangle, one wavefront
+// per block, mirrored into the lower triangle.
+__device__ __forceinline__ void gram_mfma(const float* F, int ln, int R, double* G) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nb = (R + 15) >> 4;
+    const int U = nb * (nb + 1) / 2;
+    for (int u = wave; u < U; u += ANW) {
+        int bi = 0, rem = u;
+        while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
+        const int bj = bi + rem;
+        const int c1 = bi * 16 + li, c2 = bj * 16 + li;
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < ln; k0 += 4) {
+            const int k = k0 + lk;
+            const double a = (k < ln && c1 < R) ? (double)F[k * R + c1] : 0.0;
+            const double b = (k < ln && c2 < R) ? (double)F[k * R + c2] : 0.0;
+            acc = mfma64(a, b, acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = bi * 16 + lk + 4 * v, s = bj * 16 + li;
+            if (r < R && s < R) {
+                G[r * R + s] = acc[v];
+                if (bi != bj) G[s * R + r] = acc[v];
+            }
+        }
+    }
+}
+
 // Ã_n = M V^+ (V and M^T already in the augmented system), then unit
 // columns: lambda_r = ||column r||, the float32 factor in c.fac(n) and
-// G_n = Ã_n^T Ã_n of exactly that float32 factor.  Returns RCP_INFO_* bits.
+// G_n = Ã_n^T Ã_n of exactly that float32 factor (matrix cores).  Returns
+// RCP_INFO_* bits.
 __device__ __forceinline__ int solve_update(const AlsCtx& c, int n, double* G, const double* M,
                                             double* Aug, int ldx, int Rp, double* pb, double* E,
                                             double* Ev, double* lam, double* inv_norm, int dbg_it) {
@@ -690,23 +722,9 @@ __device__ __forceinline__ int solve_update(const AlsCtx& c, int n, double* G, c
             const int i = e / R, r = e - (e / R) * R;
             fn[e] = (float)(Xt[r * ldx + i] * inv_norm[r]);
         }
-        // Gram of the rounded factor, recomputing its entries the same way
-        double* Gn = G + n * R * R;
-        for (int e = tid; e < R * R; e += ANT) {
-            const int r = e / R, s = e - (e / R) * R;
-            const double ir = inv_norm[r], is = inv_norm[s];
-            const double* xr = Xt + r * ldx;
-            const double* xs = Xt + s * ldx;
-            double a0 = 0.0, a1 = 0.0;
-            int i = 0;
-            for (; i + 2 <= ln; i += 2) {
-                a0 += (double)(float)(xr[i] * ir) * (double)(float)(xs[i] * is);
-                a1 += (double)(float)(xr[i + 1] * ir) * (double)(float)(xs[i + 1] * is);
-            }
-            if (i < ln) a0 += (double)(float)(xr[i] * ir) * (double)(float)(xs[i] * is);
-            Gn[e] = a0 + a1;
-        }
     }
+    __syncthreads();
+    gram_mfma(c.fac(n), ln, R, G + n * R * R);
     __syncthreads();
     return status;
 }
@@ -779,15 +797,7 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
     int status = 0;
     for (int n = 1; n < N; ++n) {
         if (!eig_init(c, a.B, n, E, Ev)) status |= RCP_INFO_EIG_NOT_CONVERGED;
-        // Gram of the unit-norm eigenvectors
-        const float* A = c.fac(n);
-        const int ln = c.l[n];
-        for (int e = tid; e < R * R; e += ANT) {
-            const int r = e / R, q = e - (e / R) * R;
-            double acc = 0.0;
-            for (int i = 0; i < ln; ++i) acc += (double)A[i * R + r] * (double)A[i * R + q];
-            G[n * R * R + e] = acc;
-        }
+        gram_mfma(c.fac(n), c.l[n], R, G + n * R * R);   // Gram of the unit-norm eigenvectors
     }
     __syncthreads();
     if (B_IN_LDS)

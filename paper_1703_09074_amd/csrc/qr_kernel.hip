@@ -38,12 +38,6 @@ constexpr double kCqrPivot = 1e-15;           // relative pivot floor of the uns
 constexpr double kCqrFirstOrder = 1e-8;
 constexpr double kUnitRoundoff = 1.1102230246251565e-16;
 
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ f64x4 mfma64(double a, double b, f64x4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();

@@ -154,4 +154,13 @@ __device__ __forceinline__ f32x4 mfma_lp(s16x4 a, s16x4 b, f32x4 c) {
                                                      __builtin_bit_cast(f16x4_t, b), c, 0, 0, 0);
 }
 
+// D += A B on the float64 matrix cores (v_mfma_f64_16x16x4_f64): A operand
+// [i][k] in lane i + 16 k, B operand [k][j] in lane j + 16 k, result element
+// v of lane l is [l / 16 + 4 v][l % 16].
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f64x4 mfma64(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 }  // namespace rcp
