@@ -165,6 +165,30 @@ __device__ __forceinline__ int desc_rank(const double* A, int n, int e) {
     return r;
 }
 
+// Leading R eigenvectors of the symmetric l_n x l_n matrix in E (stride
+// kEigLd, destroyed), in descending eigenvalue order, each with its
+// largest-magnitude entry positive, into the factor c.fac(n).
+__device__ __forceinline__ bool eig_leading(const AlsCtx& c, int n, double* E, double* V) {
+    const int tid = threadIdx.x;
+    const int ln = c.l[n];
+    const bool ok = jacobi_eig(E, V, ln, c.red, c.sh);
+    for (int e = tid; e < ln; e += ANT) {
+        const int r = desc_rank(E, ln, e);
+        if (r < c.R) {
+            int best = 0;
+            double bv = -1.0;
+            for (int i = 0; i < ln; ++i) {
+                const double v = fabs(V[i * kEigLd + e]);
+                if (v > bv) { bv = v; best = i; }
+            }
+            const double sg = (V[best * kEigLd + e] < 0.0) ? -1.0 : 1.0;
+            for (int i = 0; i < ln; ++i) c.fac(n)[i * c.R + r] = (float)(sg * V[i * kEigLd + e]);
+        }
+    }
+    __syncthreads();
+    return ok;
+}
+
 // Algorithm 2 step 2: leading R eigenvectors of B_(n) B_(n)^T.
 __device__ __forceinline__ bool eig_init(const AlsCtx& c, const float* Bg, int n, double* E,
                                          double* V) {
@@ -188,22 +212,7 @@ __device__ __forceinline__ bool eig_init(const AlsCtx& c, const float* Bg, int n
         E[i2 * kEigLd + i] = s;
     }
     __syncthreads();
-    const bool ok = jacobi_eig(E, V, ln, c.red, c.sh);
-    for (int e = tid; e < ln; e += ANT) {
-        const int r = desc_rank(E, ln, e);
-        if (r < c.R) {
-            int best = 0;
-            double bv = -1.0;
-            for (int i = 0; i < ln; ++i) {
-                const double v = fabs(V[i * kEigLd + e]);
-                if (v > bv) { bv = v; best = i; }
-            }
-            const double sg = (V[best * kEigLd + e] < 0.0) ? -1.0 : 1.0;
-            for (int i = 0; i < ln; ++i) c.fac(n)[i * c.R + r] = (float)(sg * V[i * kEigLd + e]);
-        }
-    }
-    __syncthreads();
-    return ok;
+    return eig_leading(c, n, E, V);
 }
 
 // ---------------------------------------------------------------------------
@@ -871,6 +880,166 @@ __global__ __launch_bounds__(ANT) void k_als_batch(const AlsArgs* args) {
     als_body<NN, B_IN_LDS, EIG_IN_LDS>(a);
 }
 
+// ---------------------------------------------------------------------------
+// Grid-wide form for cores larger than LDS.  Per mode, B_(n) KR runs over the
+// whole GPU (the Khatri-Rao kind of the streaming mode product, partials
+// reduced in float64 into a.Y); the one-workgroup kernels below take it from
+// there with the same solve, normalisation, Gram and fit as the persistent
+// kernel.  The sweep state lives in a.state:
+//   ints  [0] stop flag, [1] sweeps done, [2] RCP_INFO_* bits
+//   double[2] rho of the last sweep
+//   double[kStG ..] G_0 .. G_{N-1} (R x R each), then lambda (R)
+// The stop flag makes every later launch of the sweep loop (these kernels
+// and the mode products) return at once, so the host can enqueue all
+// max_iters sweeps up front.
+constexpr int kStG = 4;
+
+size_t als_state_doubles(int N, int R) { return kStG + (size_t)N * R * R + R; }
+
+__device__ __forceinline__ void wide_ctx(const AlsArgs& a, AlsCtx& c, int* sl, int* sfoff,
+                                         float* fbase, double* red, double* sh) {
+    const int tid = threadIdx.x;
+    if (tid < RCP_MAX_NDIM) {
+        sl[tid] = tid < a.N ? a.l[tid] : 1;
+        sfoff[tid] = 0;                       // only factor n is held, at fbase
+    }
+    c.N = a.N;
+    c.R = a.R;
+    c.S = 1;
+    for (int m = 0; m < a.N; ++m) c.S *= a.l[m];
+    c.lN = a.l[a.N - 1];
+    c.Lh = c.S / c.lN;
+    c.l = sl;
+    c.foff = sfoff;
+    c.fbase = fbase;
+    c.red = red;
+    c.sh = sh;
+    __syncthreads();
+}
+
+// Algorithm 2 step 2 for mode n (>= 1) from the Gram B_(n) B_(n)^T (upper
+// triangle of a.Y, row stride a.ldy); mode 1 also resets the sweep state.
+__global__ __launch_bounds__(ANT) void k_als_wide_init(AlsArgs a, int n) {
+    extern __shared__ __align__(16) unsigned char als_smem[];
+    __shared__ double red[ANW];
+    __shared__ double sh[128];
+    __shared__ int sl[RCP_MAX_NDIM];
+    __shared__ int sfoff[RCP_MAX_NDIM];
+    const int tid = threadIdx.x;
+    const int R = a.R, ln = a.l[n];
+    double* E = (double*)als_smem;
+    double* V = E + kEigLd * kEigLd;
+    AlsCtx c;
+    wide_ctx(a, c, sl, sfoff, (float*)(V + kEigLd * kEigLd), red, sh);
+    for (int e = tid; e < ln * ln; e += ANT) {
+        const int i = e / ln, j = e - (e / ln) * ln;
+        const int lo = min(i, j), hi = max(i, j);
+        E[i * kEigLd + j] = a.Y[lo * a.ldy + hi];
+    }
+    __syncthreads();
+    const bool ok = eig_leading(c, n, E, V);
+    double* G = a.state + kStG;
+    gram_mfma(c.fac(n), ln, R, G + n * R * R);
+    for (int e = tid; e < ln * R; e += ANT) a.At[n][e] = c.fac(n)[e];
+    if (tid == 0) {
+        int* fl = (int*)a.state;
+        const int bit = ok ? 0 : RCP_INFO_EIG_NOT_CONVERGED;
+        if (n == 1) {
+            fl[0] = 0;
+            fl[1] = 0;
+            fl[2] = bit;
+            a.state[2] = 0.0;
+        } else {
+            fl[2] |= bit;
+        }
+    }
+}
+
+// Algorithm 2 steps 4-10 for mode n of one sweep from M_n in a.Y (row
+// stride a.ldy); after the last mode the fit of Section 3.3 and the
+// stopping rule, with lambda and info written every sweep.
+__global__ __launch_bounds__(ANT) void k_als_wide_step(AlsArgs a, int n) {
+    extern __shared__ __align__(16) unsigned char als_smem[];
+    __shared__ double red[ANW];
+    __shared__ double sh[128];
+    __shared__ double lam[RCP_MAX_RANK];
+    __shared__ double inv_norm[RCP_MAX_RANK];
+    __shared__ int sl[RCP_MAX_NDIM];
+    __shared__ int sfoff[RCP_MAX_NDIM];
+    int* fl = (int*)a.state;
+    if (fl[0] != 0) return;
+    const int tid = threadIdx.x;
+    const int N = a.N, R = a.R, ln = a.l[n];
+    int lmax = 0;
+    for (int m = 0; m < N; ++m) lmax = max(lmax, a.l[m]);
+    const int Rp = (R + GB - 1) / GB * GB;
+    const int ldx = Rp + lmax;
+    double* Aug = (double*)als_smem;
+    double* pb = Aug + Rp * ldx;
+    float* fbase = (float*)(pb + 2 * GB * (ldx + Rp) + 2 * GB * GB + 1);
+    AlsCtx c;
+    wide_ctx(a, c, sl, sfoff, fbase, red, sh);
+    double* G = a.state + kStG;
+    double* M = a.Ebuf + 2 * kEigLd * kEigLd;      // l_n x R
+    double* Es = a.Ebuf;
+    double* Evs = a.Ebuf + kEigLd * kEigLd;
+
+    hadamard_grams(c, n, G, Aug, ldx, Rp, ln);
+    for (int e = tid; e < ln * R; e += ANT) {
+        const int i = e / R, r = e - (e / R) * R;
+        const double v = a.Y[i * a.ldy + r];
+        M[e] = v;
+        Aug[r * ldx + Rp + i] = v;
+    }
+    __syncthreads();
+    int status = solve_update(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs, lam, inv_norm, 0);
+    for (int e = tid; e < ln * R; e += ANT) a.At[n][e] = c.fac(n)[e];
+    if (n < N - 1) {
+        if (tid == 0 && status != 0) fl[2] |= status;
+        return;
+    }
+    // fit (Section 3.3) on the core, as in the persistent kernel
+    double pi = 0.0;
+    const float* AN = c.fac(N - 1);
+    for (int e = tid; e < c.lN * R; e += ANT) pi += lam[e % R] * M[e] * (double)AN[e];
+    double pm = 0.0;
+    for (int e = tid; e < R * R; e += ANT) {
+        double v = lam[e / R] * lam[e % R];
+        for (int m = 0; m < N; ++m) v *= G[m * R * R + e];
+        pm += v;
+    }
+    const double inner = block_sum(pi, red);
+    const double model = block_sum(pm, red);
+    const double normX2 = *a.normX2;
+    const double err2 = normX2 - 2.0 * inner + model;
+    const double rho = (normX2 > 0.0) ? 1.0 - err2 / normX2 : 0.0;
+    const int it = fl[1] + 1;
+    bool stop = it >= a.max_iters;
+    if (!isfinite(rho)) {
+        status |= RCP_INFO_NONFINITE;
+        stop = true;
+    } else if (a.tol > 0.0 && it >= 2 && fabs(rho - a.state[2]) < a.tol) {
+        stop = true;
+    }
+    for (int r = tid; r < R; r += ANT) {
+        a.lambda[r] = (float)lam[r];
+        a.state[kStG + (size_t)N * R * R + r] = lam[r];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int st = fl[2] | status;
+        fl[2] = st;
+        fl[1] = it;
+        a.state[2] = rho;
+        a.info->iters = it;
+        a.info->status = st;
+        a.info->rho = rho;
+        a.info->rel_err = sqrt(fmax(0.0, 1.0 - rho));
+        a.info->normX2 = normX2;
+        if (stop) fl[0] = 1;
+    }
+}
+
 static size_t als_lds_fixed(int N, const int* l, int R) {
     size_t b = 0;
     int lmax = 0;
@@ -895,6 +1064,43 @@ size_t als_workspace_doubles(int N, const int* l, int R) {
     int lmax = 0;
     for (int n = 0; n < N; ++n) lmax = lmax > l[n] ? lmax : l[n];
     return 2 * kEigLd * kEigLd + (size_t)lmax * R;
+}
+
+bool als_core_in_lds(int N, const int* l, int R) {
+    int64_t S = 1;
+    for (int n = 0; n < N; ++n) S *= l[n];
+    return als_lds_fixed(N, l, R) + (size_t)S * sizeof(float) <= kAlsLds;
+}
+
+static size_t wide_step_lds(const AlsArgs& a) {
+    int lmax = 0;
+    for (int m = 0; m < a.N; ++m) lmax = lmax > a.l[m] ? lmax : a.l[m];
+    const int Rp = (a.R + GB - 1) / GB * GB;
+    const int ldx = Rp + lmax;
+    return (size_t)(Rp * ldx + 2 * GB * (ldx + Rp) + 2 * GB * GB + 1) * sizeof(double) +
+           (size_t)lmax * a.R * sizeof(float);
+}
+
+hipError_t launch_als_wide_init(const AlsArgs& a, int n, hipStream_t s) {
+    if (n < 1 || n >= a.N || a.Y == nullptr || a.state == nullptr) return hipErrorInvalidValue;
+    const size_t smem = 2 * kEigLd * kEigLd * sizeof(double) + (size_t)a.l[n] * a.R * sizeof(float);
+    hipError_t e = hipFuncSetAttribute((const void*)k_als_wide_init,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kAlsLds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_als_wide_init, dim3(1), dim3(ANT), smem, s, a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_als_wide_step(const AlsArgs& a, int n, hipStream_t s) {
+    if (n < 0 || n >= a.N || a.Y == nullptr || a.state == nullptr || a.normX2 == nullptr)
+        return hipErrorInvalidValue;
+    const size_t smem = wide_step_lds(a);
+    if (smem > kAlsLds) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute((const void*)k_als_wide_step,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kAlsLds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_als_wide_step, dim3(1), dim3(ANT), smem, s, a, n);
+    return hipGetLastError();
 }
 
 bool als_supported(int N, const int* l, int R) {

@@ -31,8 +31,8 @@ struct Layout {
     int64_t Imax;
     int LPmax;
     // offsets (bytes)
-    size_t part, red1, y64, qt, sq, norm, qb[RCP_MAX_NDIM], tb[2], zbuf, als, at[RCP_MAX_NDIM], lam,
-        raw, total;
+    size_t part, red1, y64, qt, sq, norm, qb[RCP_MAX_NDIM], tb[2], zbuf, als, alsst,
+        at[RCP_MAX_NDIM], lam, raw, total;
     size_t part_elems, tb_elems[2], zbuf_elems, als_doubles;
     int64_t core_dims[RCP_MAX_NDIM];
 };
@@ -117,6 +117,7 @@ Layout make_layout(const rcp_problem* p) {
     L.tb[1] = take(L.tb_elems[1] * sizeof(float));
     L.zbuf = take(L.zbuf_elems * sizeof(float));
     L.als = take(L.als_doubles * sizeof(double));
+    L.alsst = take(als_state_doubles(L.N, L.R) * sizeof(double));
     for (int n = 0; n < L.N; ++n) L.at[n] = take((size_t)L.l[n] * L.R * sizeof(float));
     L.lam = take((size_t)L.R * sizeof(float));
     size_t raw = 0;
@@ -299,6 +300,65 @@ rcp_status compress_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int
     return RCP_OK;
 }
 
+// CP-ALS for a core larger than LDS: per mode, the mode product over the
+// whole GPU (Khatri-Rao kind of the streaming kernel), its float64
+// reduction, and the one-workgroup solve; all max_iters sweeps are enqueued,
+// and the device-side stop flag turns the launches after convergence into
+// no-ops.  The factors live in At throughout.
+hipError_t als_wide(rcp_plan_t* pl, AlsArgs a) {
+    const Layout& L = pl->L;
+    const int N = L.N, R = L.R;
+    int64_t cd[RCP_MAX_NDIM];
+    int64_t S = 1;
+    for (int n = 0; n < N; ++n) { cd[n] = L.l[n]; S *= L.l[n]; }
+    double* state = pl->at<double>(L.alsst);
+    float* part = pl->at<float>(L.part);
+    double* red1 = pl->at<double>(L.red1);
+    double* Y = pl->at<double>(L.y64);
+    a.Y = Y;
+    a.state = state;
+    if (a.normX2 == nullptr) {
+        // ||core||^2 into a spare slot of the state (double 3)
+        const int nb = (int)std::min<int64_t>(256, std::max<int64_t>(1, S / 4096));
+        hipError_t e = launch_sumsq(a.B, S, red1, nb, state + 3, pl->stream);
+        if (e != hipSuccess) return e;
+        a.normX2 = state + 3;
+    }
+    // Algorithm 2 step 2: Grams B_(n) B_(n)^T as Y = T (T^T I) over the GPU
+    for (int n = 1; n < N; ++n) {
+        const StreamGeom g = make_geom(a.B, cd, N, n);
+        const int P = (int)std::max<int64_t>(1, std::min<int64_t>(pl->P, g.ntiles));
+        const int LPn = lp_of(L.l[n]);
+        float* eye = pl->at<float>(L.qt);
+        hipError_t e = launch_eye(eye, L.l[n], LPn, pl->stream);
+        if (e == hipSuccess) e = launch_power_fused(g, L.l[n], eye, part, P, pl->stream, RCP_PREC_FP32);
+        if (e == hipSuccess)
+            e = launch_reduce_partials(part, P, (int64_t)L.l[n] * LPn, red1, Y, nullptr, 0, nullptr,
+                                       pl->stream);
+        a.ldy = LPn;
+        if (e == hipSuccess) e = launch_als_wide_init(a, n, pl->stream);
+        if (e != hipSuccess) return e;
+    }
+    const float* facs[RCP_MAX_NDIM];
+    for (int n = 0; n < N; ++n) facs[n] = a.At[n];
+    const int LPR = lp_of(R);
+    a.ldy = LPR;
+    for (int it = 0; it < a.max_iters; ++it) {
+        for (int n = 0; n < N; ++n) {
+            const StreamGeom g = make_geom(a.B, cd, N, n);
+            const int P = (int)std::max<int64_t>(1, std::min<int64_t>(pl->P, g.ntiles));
+            const KrSpec kr = kr_spec(N, n, L.l, R, facs, (const int*)state);
+            hipError_t e = launch_mttkrp(g, kr, part, P, pl->stream);
+            if (e == hipSuccess)
+                e = launch_reduce_partials(part, P, (int64_t)L.l[n] * LPR, red1, Y, nullptr, 0,
+                                           nullptr, pl->stream);
+            if (e == hipSuccess) e = launch_als_wide_step(a, n, pl->stream);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
 rcp_status als_impl(rcp_plan_t* pl, const float* core, float* const* At, float* lambda,
                     const double* normX2, rcp_als_info* info) {
     const Layout& L = pl->L;
@@ -318,9 +378,11 @@ rcp_status als_impl(rcp_plan_t* pl, const float* core, float* const* At, float* 
     a.Ebuf = pl->at<double>(L.als);
     // nominal algorithmic work: N mode products of the core with R columns per sweep
     const double sweeps = (double)pl->prob.max_iters;
+    const bool in_lds = als_core_in_lds(L.N, L.l, R);
     RCP_TRY(timed(pl, RCP_KERNEL_ALS, sweeps * L.N * 4.0 * (double)S,
-                  sweeps * L.N * 2.0 * (double)S * R,
-                  [&] { return launch_als(a, pl->stream); }));
+                  sweeps * L.N * 2.0 * (double)S * R, [&] {
+                      return in_lds ? launch_als(a, pl->stream) : als_wide(pl, a);
+                  }));
     return RCP_OK;
 }
 

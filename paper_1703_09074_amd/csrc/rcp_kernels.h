@@ -43,6 +43,26 @@ hipError_t launch_power_fused_lp(int precision, const StreamGeom& g, int l, cons
                                  float* part, int P, hipStream_t s);
 hipError_t launch_contract_in_lp(int precision, const StreamGeom& g, int l, const float* Qpadded,
                                  int lout, float* out, int P, hipStream_t s);
+// Khatri-Rao operand of the mode-n product of the core: column j of the
+// unfolding B_(n) is a mixed-radix number whose digits index the rows of the
+// other modes' factors; entry (j, c) of the operand is the product of those
+// rows' entries in column c (zero for c >= R).  Digits come out of j by
+// division by invariant integers (multiply-high and shift, Granlund and
+// Montgomery 1994), set up on the host by kr_spec().
+struct KrSpec {
+    int N, n, R, ftotal;                // ftotal: floats of all factors, packed
+    int l[RCP_MAX_NDIM];
+    int foff[RCP_MAX_NDIM];             // offset of factor m in the packed copy
+    uint32_t mul[RCP_MAX_NDIM];
+    uint32_t shr[RCP_MAX_NDIM];
+    const float* fac[RCP_MAX_NDIM];     // l_m x R, row-major (device)
+    const int* skip;                    // nonzero: the launch does nothing
+};
+KrSpec kr_spec(int N, int n, const int* l, int R, const float* const* fac, const int* skip);
+// partial M = B_(n) KR (per workgroup, I x 16*ceil(R/16)) for the reduction
+hipError_t launch_mttkrp(const StreamGeom& g, const KrSpec& kr, float* part, int P, hipStream_t s);
+// Qpad (I x ldq) <- the identity padded with zero columns
+hipError_t launch_eye(float* Qpad, int64_t I, int ldq, hipStream_t s);
 int reduce_split(int P);
 hipError_t launch_reduce_partials(const float* part, int P, int64_t count, double* red1,
                                   double* Y, const double* sq_part, int nsq, double* sq_out,
@@ -77,12 +97,29 @@ struct AlsArgs {
     rcp_als_info* info;
     // workspace
     double* Ebuf;              // Jacobi scratch (2 x 64 x 64), then M_n (l_max x R)
+    // grid-wide form (cores larger than LDS): reduced mode product or Gram
+    // (l_n x ldy float64) and the sweep state (als_state_doubles)
+    const double* Y;
+    int ldy;
+    double* state;
 };
 hipError_t launch_als(const AlsArgs& a, hipStream_t s);
 // one launch for `count` problems: dargs on the device, hargs the same on the host
 hipError_t launch_als_batch(const AlsArgs* dargs, const AlsArgs* hargs, int count, hipStream_t s);
 size_t als_workspace_doubles(int N, const int* l, int R);
 bool als_supported(int N, const int* l, int R);
+// the core fits in one workgroup's LDS: the whole sweep loop in one launch
+bool als_core_in_lds(int N, const int* l, int R);
+// Grid-wide form for larger cores: per mode the product B_(n) KR runs over
+// the whole GPU (launch_mttkrp), these one-workgroup kernels do the rest.
+// The sweep state (iteration, stop flag, Grams, lambda) lives in a.state;
+// the stop flag (an int at a.state) makes every later launch return at once.
+size_t als_state_doubles(int N, int R);
+// Algorithm 2 step 2 for mode n from its Gram B_(n) B_(n)^T in a.Y
+hipError_t launch_als_wide_init(const AlsArgs& a, int n, hipStream_t s);
+// steps 4-10 for mode n from its reduced mode product in a.Y; after the
+// last mode, the fit and the stopping rule
+hipError_t launch_als_wide_step(const AlsArgs& a, int n, hipStream_t s);
 
 // back-projection (expand_kernel.hip)
 struct ExpandArgs {

@@ -90,8 +90,60 @@ __global__ __launch_bounds__(NT) void k_pad_q(const float* Q, int64_t I, int l, 
     Qpad[e] = (c < l) ? Q[i * l + c] : 0.0f;
 }
 
+__global__ __launch_bounds__(NT) void k_eye(float* Qpad, int64_t I, int ldq) {
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= I * ldq) return;
+    const int64_t i = e / ldq;
+    Qpad[e] = (e - i * ldq == i) ? 1.0f : 0.0f;
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launchers.
+
+hipError_t launch_eye(float* Qpad, int64_t I, int ldq, hipStream_t s) {
+    const int64_t n = I * ldq;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eye, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, Qpad, I, ldq);
+    return hipGetLastError();
+}
+
+// multiplier and shift for x / d with x < 2^32 (round-up method)
+static void udiv_magic(uint32_t d, uint32_t* mul, uint32_t* shr) {
+    uint32_t sh = 0;
+    while (((uint64_t)1 << sh) < d) ++sh;
+    *shr = sh;
+    *mul = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << sh) - d)) / d + 1);
+}
+
+KrSpec kr_spec(int N, int n, const int* l, int R, const float* const* fac, const int* skip) {
+    KrSpec k{};
+    k.N = N;
+    k.n = n;
+    k.R = R;
+    int off = 0;
+    for (int m = 0; m < N; ++m) {
+        k.l[m] = l[m];
+        k.foff[m] = off;
+        off += l[m] * R;
+        udiv_magic((uint32_t)l[m], &k.mul[m], &k.shr[m]);
+        k.fac[m] = fac[m];
+    }
+    k.ftotal = off;
+    k.skip = skip;
+    return k;
+}
+
+hipError_t launch_mttkrp(const StreamGeom& g, const KrSpec& kr, float* part, int P, hipStream_t s) {
+    if (g.I > 64 || kr.R < 1 || kr.R > RCP_MAX_RANK) return hipErrorInvalidValue;
+    const int NBv = lp_blocks(kr.R);
+    const size_t smem = contract_out_smem(NBv, 1) + (size_t)kr.ftotal * sizeof(float);
+    if (smem > 160 * 1024) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)P, 1);
+    hipError_t e = hipSuccess;
+    RCP_NB_SWITCH(NBv, e = (launch_co<NB, 1, kWKr, kPrecFp32>(grid, smem, s, g, kr.R, nullptr, 0, 0,
+                                                              part, nullptr, kr)));
+    return e;
+}
 
 StreamGeom make_geom(const float* T, const int64_t* dims, int ndim, int mode) {
     StreamGeom g;

@@ -294,21 +294,67 @@ __device__ __forceinline__ void store_partial(const f32x4 (&acc)[MHalf<MB>::v][N
 
 // ---------------------------------------------------------------------------
 // contract_out: partial Y = T_(n) W over the tiles of this workgroup, for
-// the row block blockIdx.y (64*MB rows).  W is the Gaussian test matrix
-// generated in registers (GEN) or a stored J x LP matrix in the layout
-// (L, LP, Rr) (power iteration with a stored Z).  Optional float64 partial
-// sum of squares of T (used for ||X||^2 in the first pass).
+// the row block blockIdx.y (64*MB rows).  W (J x LP) is never stored whole;
+// per tile its JT rows are
+//   WK = kWStored: read from a stored matrix in the layout (L, LP, Rr)
+//                  (power iteration with a stored Z),
+//   WK = kWOmega:  the Gaussian test matrix, generated in registers,
+//   WK = kWKr:     the Khatri-Rao product of the other modes' factors (the
+//                  mode product of CP-ALS, Algorithm 2 steps 4/6/8), formed
+//                  from a packed copy of the factors in LDS.
+// Optional float64 partial sum of squares of T (used for ||X||^2 in the
+// first pass).
 
-template <int NB, int MB, bool GEN, bool CB, int PR>
+constexpr int kWStored = 0;
+constexpr int kWOmega = 1;
+constexpr int kWKr = 2;
+
+__device__ __forceinline__ uint32_t fast_udiv(uint32_t x, uint32_t mul, uint32_t shr) {
+    return (uint32_t)(((uint64_t)__umulhi(x, mul) + x) >> shr);
+}
+
+// Khatri-Rao entry (column c) for the unfolding column with outer index a
+// (modes before n) and inner index b (modes after n): digits come out
+// least significant first, i.e. from the last mode down.
+__device__ __forceinline__ float kr_entry(const KrSpec& kr, const float* Fs, uint32_t a, uint32_t b,
+                                          int c) {
+    float p = 1.0f;
+#pragma unroll
+    for (int m = RCP_MAX_NDIM - 1; m >= 0; --m) {
+        if (m < kr.N && m != kr.n) {
+            const bool inner = m > kr.n;
+            const uint32_t x = inner ? b : a;
+            const uint32_t q = fast_udiv(x, kr.mul[m], kr.shr[m]);
+            const uint32_t d = x - q * (uint32_t)kr.l[m];
+            if (inner) b = q; else a = q;
+            p *= Fs[kr.foff[m] + (int)d * kr.R + c];
+        }
+    }
+    return p;
+}
+
+template <int NB, int MB, int WK, bool CB, int PR>
 __global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const float* Z,
                                                      uint64_t seed, uint32_t tag, float* part,
-                                                     double* sq_part) {
+                                                     double* sq_part, KrSpec kr) {
     constexpr int LPc = NB * 16;
     constexpr int IB = 64 * MB;
     extern __shared__ __align__(16) float smem[];
     float* Ts = smem;                       // IB x TS
     float* Ws = Ts + IB * TS;               // JT x LPc
+    float* Fs = Ws + JT * LPc;              // kWKr: the packed factors
     __shared__ double red[NWS];
+
+    if (WK == kWKr) {
+        if (kr.skip != nullptr && *kr.skip != 0) return;
+#pragma unroll
+        for (int m = 0; m < RCP_MAX_NDIM; ++m) {
+            if (m < kr.N && m != kr.n) {
+                const int cnt = kr.l[m] * kr.R;
+                for (int e = threadIdx.x; e < cnt; e += NTS) Fs[kr.foff[m] + e] = kr.fac[m][e];
+            }
+        }
+    }
 
     const int64_t row0 = (int64_t)blockIdx.y * IB;
     const int64_t rows_left = g.I - row0;
@@ -330,7 +376,26 @@ __global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const
         __syncthreads();
         if (CB) sq += load_tile(g, ti, row0, nrows, IB, Ts, want_sq);
         else sq += tile_commit<MB>(pf, Ts, want_sq);
-        if (GEN) {
+        if (WK == kWKr) {
+            const float inv_rr = 1.0f / (float)g.Rr;
+            for (int e = threadIdx.x; e < JT * LPc; e += NTS) {
+                const int jj = e / LPc, c = e % LPc;
+                float v = 0.0f;
+                if (jj < ti.width && c < kr.R) {
+                    uint32_t a, b;
+                    if (!g.caseB) {
+                        a = (uint32_t)ti.a0;
+                        b = (uint32_t)(ti.b0 + jj);
+                    } else {
+                        const int q = small_div(jj, (int)g.Rr, inv_rr);
+                        a = (uint32_t)(ti.a0 + q);
+                        b = (uint32_t)(jj - q * (int)g.Rr);
+                    }
+                    v = kr_entry(kr, Fs, a, b, c);
+                }
+                Ws[jj * LPc + c] = v;
+            }
+        } else if (WK == kWOmega) {
             constexpr int NG = LPc / 4;
             for (int e = threadIdx.x; e < JT * NG; e += NTS) {
                 const int jj = e / NG, gi = e % NG;
@@ -496,15 +561,15 @@ inline size_t contract_in_smem(int NB) {
     return (size_t)(IC * TS + IC * LPc + 4 * JT * LPc + JT * LPc) * sizeof(float);
 }
 
-template <int NB, int MB, bool GEN, int PR>
+template <int NB, int MB, int WK, int PR>
 static hipError_t launch_co(dim3 grid, size_t smem, hipStream_t s, const StreamGeom& g, int l,
                             const float* Z, uint64_t seed, uint32_t tag, float* part,
-                            double* sq) {
-    auto k = g.caseB ? k_contract_out<NB, MB, GEN, true, PR> : k_contract_out<NB, MB, GEN, false, PR>;
+                            double* sq, const KrSpec& kr = KrSpec{}) {
+    auto k = g.caseB ? k_contract_out<NB, MB, WK, true, PR> : k_contract_out<NB, MB, WK, false, PR>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)smem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, grid, dim3(NTS), smem, s, g, l, Z, seed, tag, part, sq);
+    hipLaunchKernelGGL(k, grid, dim3(NTS), smem, s, g, l, Z, seed, tag, part, sq, kr);
     return hipGetLastError();
 }
 
@@ -541,9 +606,9 @@ hipError_t launch_contract_out_t(const StreamGeom& g, int l, const float* Z, uin
     const dim3 grid((unsigned)P, nIB);
     hipError_t e = hipSuccess;
     if (Z == nullptr) {
-        RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_co<NB, MB, true, PR>(grid, smem, s, g, l, Z, seed, tag, part, sq_part))));
+        RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_co<NB, MB, kWOmega, PR>(grid, smem, s, g, l, Z, seed, tag, part, sq_part))));
     } else {
-        RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_co<NB, MB, false, PR>(grid, smem, s, g, l, Z, seed, tag, part, sq_part))));
+        RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_co<NB, MB, kWStored, PR>(grid, smem, s, g, l, Z, seed, tag, part, sq_part))));
     }
     return e;
 }

@@ -134,6 +134,34 @@ def test_als_matches_oracle(dims, R, iters):
     np.testing.assert_allclose(gl, ref.lam[perm], rtol=1e-4)
 
 
+# Cores larger than one workgroup's LDS take the grid-wide form (mode
+# products over the whole GPU, one-workgroup solves): 45^3 and 15^4 floats.
+@pytest.mark.parametrize("dims,R,iters,tol", [((60, 55, 50), 40, 15, 0.0),
+                                              ((30, 28, 26, 24), 10, 20, 0.0),
+                                              ((30, 28, 26, 24), 10, 200, 1e-6)])
+def test_als_grid_wide_matches_oracle(dims, R, iters, tol):
+    w, comp = _core_problem(dims, R, 0.05, 13, R, 5, 1)
+    core = comp.core.astype(np.float32)
+    assert core.size * 4 > 160 * 1024
+    normX2 = float(np.sum(w.X.astype(np.float64) ** 2))
+    plan = rcpgpu.Plan(dims, R, 5, 1, iters, tol, 13)
+    nx = torch.tensor([normX2], dtype=torch.float64, device="cuda")
+    At, lam, info = plan.als(_dev(core), nx)
+    info = rcpgpu.Plan.read_info(info)
+    ref = rcp.als(core.astype(np.float64), R, iters, tol=tol, normX2=normX2)
+    assert info["status"] == 0, info
+    assert info["iters"] == ref.iters, (info, ref.iters)
+    assert abs(info["rho"] - ref.rho) <= 1e-7, (info["rho"], ref.rho)
+    cong, cmin, perm = evaluate.congruence([_np(a) for a in At], ref.factors)
+    assert cmin >= 0.999, cmin
+    np.testing.assert_allclose(_np(lam), ref.lam[perm], rtol=1e-4)
+    # without ||X||^2 the fit is taken against ||core||^2
+    At2, lam2, info2 = plan.als(_dev(core))
+    info2 = rcpgpu.Plan.read_info(info2)
+    ref2 = rcp.als(core.astype(np.float64), R, iters, tol=tol)
+    assert abs(info2["rho"] - ref2.rho) <= 1e-6, (info2["rho"], ref2.rho)
+
+
 def test_expand_matches_oracle():
     dims, R = (50, 40, 30), 4
     w, comp = _core_problem(dims, R, 0.05, 12, R, 6, 1)
