@@ -545,6 +545,171 @@ __global__ __launch_bounds__(NTS) void k_contract_in(StreamGeom g, const float* 
     }
 }
 
+// ---------------------------------------------------------------------------
+// contract_in for tall modes (case A only): out[a, c, b] = sum_i Q[i, c]
+// T[a, i, b] with every row i streamed.  A workgroup owns groups of CW
+// consecutive columns (8 tiles, 1 KB runs per row) and walks their rows in
+// chunks of RC through a double-buffered LDS pipeline: while the matrix cores
+// consume chunk s, chunk s+1 is committed from registers into the other
+// buffer and chunk s+2 is in flight from HBM; one barrier per chunk.  The
+// (group, chunk) steps of a workgroup form one sequence, so the pipeline does
+// not drain between groups.  Each group's z^T (LP x CW) stays in the
+// accumulators and is written once: no partial outputs, no read-modify-write.
+// Wavefront w owns column blocks 2w, 2w+1 and all LP/16 blocks of c.
+
+constexpr int CW = 256;           // columns per group
+constexpr int RC = 32;            // rows per chunk
+constexpr int TSW = CW + 16;      // LDS row stride of a T chunk
+
+template <int NB, int PR>
+__global__ __launch_bounds__(NTS) void k_contract_in_tall(StreamGeom g, const float* Q, int lout,
+                                                         float* out) {
+    constexpr int LPc = NB * 16;
+    constexpr int LQ = LPc + 16;            // LDS row stride of a Q chunk
+    constexpr int TF4 = RC * CW / 4 / NTS;  // float4 of a T chunk per thread
+    constexpr int QF4 = RC * LPc / 4;       // float4 of a Q chunk
+    static_assert(RC * CW / 4 == TF4 * NTS, "T chunk split");
+    static_assert(QF4 <= NTS, "Q chunk split");
+    extern __shared__ __align__(16) float smem[];
+    float* Tb = smem;                       // [2][RC][TSW]
+    float* Qb = Tb + 2 * RC * TSW;          // [2][RC][LQ]
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int64_t gpa = (g.Rr + CW - 1) / CW;
+    const int64_t ngroups = g.L * gpa;
+    const int64_t I = g.I;
+    const int nch = (int)((I + RC - 1) / RC);
+    if ((int64_t)blockIdx.x >= ngroups) return;
+    const int64_t my_groups = (ngroups - blockIdx.x + gridDim.x - 1) / gridDim.x;
+    const int64_t nsteps = my_groups * nch;
+
+    float4 tr[TF4];
+    float4 qr = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto issue = [&](int64_t st) {
+        const int64_t grp = blockIdx.x + (st / nch) * gridDim.x;
+        const int64_t i0 = (st % nch) * RC;
+        const int64_t a = grp / gpa;
+        const int64_t b0 = (grp - a * gpa) * CW;
+        const int64_t wl = g.Rr - b0;
+        const int width = (int)(wl < CW ? wl : CW);
+        const int64_t rl = I - i0;
+        const int rows = (int)(rl < RC ? rl : RC);
+        const float* base = g.T + ((a * g.Is + i0) * g.Rr + b0);
+#pragma unroll
+        for (int s2 = 0; s2 < TF4; ++s2) {
+            const int f = tid + s2 * NTS;
+            const int r = f / (CW / 4), c0 = (f % (CW / 4)) * 4;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (r < rows && c0 < width) {
+                const float* p = base + (int64_t)r * g.Rr + c0;
+                if (g.vec4 && c0 + 4 <= width) {
+                    v = *reinterpret_cast<const float4*>(p);
+                } else {
+                    v.x = p[0];
+                    if (c0 + 1 < width) v.y = p[1];
+                    if (c0 + 2 < width) v.z = p[2];
+                    if (c0 + 3 < width) v.w = p[3];
+                }
+            }
+            tr[s2] = v;
+        }
+        if (tid < QF4) {
+            const int r = tid / (LPc / 4), c0 = (tid % (LPc / 4)) * 4;
+            qr = (i0 + r < I) ? *reinterpret_cast<const float4*>(Q + (i0 + r) * LPc + c0)
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto commit = [&](int buf) {
+        float* tb = Tb + buf * RC * TSW;
+#pragma unroll
+        for (int s2 = 0; s2 < TF4; ++s2) {
+            const int f = tid + s2 * NTS;
+            const int r = f / (CW / 4), c0 = (f % (CW / 4)) * 4;
+            *reinterpret_cast<float4*>(tb + r * TSW + c0) = tr[s2];
+        }
+        if (tid < QF4) {
+            const int r = tid / (LPc / 4), c0 = (tid % (LPc / 4)) * 4;
+            *reinterpret_cast<float4*>(Qb + buf * RC * LQ + r * LQ + c0) = qr;
+        }
+    };
+
+    f32x4 acc[2][NB];
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[jb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    issue(0);
+    commit(0);
+    if (nsteps > 1) issue(1);
+    __syncthreads();
+    for (int64_t st = 0; st < nsteps; ++st) {
+        const int buf = (int)(st & 1);
+        const float* tb = Tb + buf * RC * TSW + (2 * wave) * 16 + lr;
+        const float* qb = Qb + buf * RC * LQ + lr;
+        if constexpr (PR != kPrecFp32) {
+#pragma unroll
+            for (int k0 = 0; k0 < RC; k0 += 16) {
+                const int kr = k0 + 4 * lk;
+                s16x4 bt[2];
+#pragma unroll
+                for (int jb = 0; jb < 2; ++jb) {
+                    const float* tp = tb + kr * TSW + jb * 16;
+                    bt[jb] = to_lp<PR>(make_float4(tp[0], tp[TSW], tp[2 * TSW], tp[3 * TSW]));
+                }
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const float* qp = qb + kr * LQ + nb * 16;
+                    const s16x4 aq = to_lp<PR>(make_float4(qp[0], qp[LQ], qp[2 * LQ], qp[3 * LQ]));
+#pragma unroll
+                    for (int jb = 0; jb < 2; ++jb) acc[jb][nb] = mfma_lp<PR>(aq, bt[jb], acc[jb][nb]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k0 = 0; k0 < RC; k0 += 4) {
+                const int kr = k0 + lk;
+                const float b0v = tb[kr * TSW], b1v = tb[kr * TSW + 16];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const float aq = qb[kr * LQ + nb * 16];
+                    acc[0][nb] = mfma16x16x4(aq, b0v, acc[0][nb]);
+                    acc[1][nb] = mfma16x16x4(aq, b1v, acc[1][nb]);
+                }
+            }
+        }
+        if (st + 1 < nsteps) commit(buf ^ 1);
+        if (st + 2 < nsteps) issue(st + 2);
+        if ((int)(st % nch) == nch - 1) {
+            // the group is complete: z^T[c, j] -> out[a, c, b0 + j]
+            const int64_t grp = blockIdx.x + (st / nch) * gridDim.x;
+            const int64_t a = grp / gpa;
+            const int64_t b0 = (grp - a * gpa) * CW;
+            const int64_t wl = g.Rr - b0;
+            const int width = (int)(wl < CW ? wl : CW);
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb) {
+                const int j = (2 * wave + jb) * 16 + lr;
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int c = nb * 16 + 4 * lk + v;
+                        if (c < lout && j < width) out[(a * lout + c) * g.Rr + b0 + j] = acc[jb][nb][v];
+                    }
+                    acc[jb][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+inline size_t contract_in_tall_smem(int NB) {
+    return (size_t)(2 * RC * TSW + 2 * RC * (NB * 16 + 16)) * sizeof(float);
+}
+
 inline int lp_blocks(int l) { return (l + 15) / 16; }
 
 inline size_t contract_out_smem(int NB, int MB) {
@@ -660,9 +825,26 @@ hipError_t launch_contract_in_t(const StreamGeom& g, int l, const float* Qpadded
         RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_pf<NB, MB, false, PR>(P, smem, s, g, Qpadded, nullptr, lout, out))));
         return e;
     }
-    // Taller modes: slices of the rows whose basis rows fit in LDS, each a
-    // resident-basis pass over its rows that adds its share of T^T Q into
-    // the output (in slice order, so the sums are deterministic).
+    // Taller modes with runs of at least one tile per row: every row streamed
+    // through the double-buffered pipeline, the output written once.
+    if (!g.caseB) {
+        const int64_t ngroups = g.L * ((g.Rr + CW - 1) / CW);
+        const int P2 = (int)(ngroups < P ? ngroups : P);
+        const size_t smem = contract_in_tall_smem(NBv);
+        RCP_NB_SWITCH(NBv, {
+            auto k = k_contract_in_tall<NB, PR>;
+            e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)smem);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(k, dim3((unsigned)P2), dim3(NTS), smem, s, g, Qpadded, lout, out);
+                e = hipGetLastError();
+            }
+        });
+        return e;
+    }
+    // Otherwise (short a-slabs): slices of the rows whose basis rows fit in
+    // LDS, each a resident-basis pass over its rows that adds its share of
+    // T^T Q into the output (in slice order, so the sums are deterministic).
     int MBs = 8;
     while (MBs > 1 && power_fused_smem(NBv, MBs) > 160 * 1024) --MBs;
     if (power_fused_smem(NBv, MBs) <= 160 * 1024) {

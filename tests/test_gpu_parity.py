@@ -68,6 +68,7 @@ SKETCH_CASES = [
     ((45, 33), 0, 6, 4, 2),            # matrix (N = 2)
     ((16, 16, 16), 1, 10, 10, 1),      # l = I: square basis
     ((600, 20, 9), 0, 8, 8, 1),        # I > 512: two row blocks, two-pass power step
+    ((3, 530, 70), 1, 3, 9, 2),        # tall middle mode: 3 a-slabs, unaligned rows
 ]
 
 
@@ -87,7 +88,7 @@ def test_sketch_matches_oracle(shape, mode, k, p, q):
 
 @pytest.mark.parametrize("shape,mode", [((37, 50, 41), 0), ((37, 50, 41), 1), ((37, 50, 41), 2),
                                         ((64, 48, 5), 1), ((30, 11, 3, 7), 3), ((700, 9, 40), 0),
-                                        ((45, 33), 1)])
+                                        ((45, 33), 1), ((3, 530, 70), 1), ((520, 300), 0)])
 def test_compress_matches_oracle(shape, mode):
     T = _rand(shape, 7 + mode)
     I = shape[mode]
