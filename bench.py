@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=512, metavar="COUNT",
                     help="also time a batch of COUNT independent small problems (0 skips)")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--batch-autotune", type=int, default=1,
+                    help="time the batch again with the launch shape rcp_batch_autotune picks")
     ap.add_argument("--mixed-steps", type=int, default=10,
                     help="timed solves with bfloat16 and float16 operands (0 skips the comparison)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -141,19 +143,33 @@ def run_batch(args, torch, rcpgpu, dev):
         b.decompose(Xs)                       # records the graph and runs it once
     torch.cuda.synchronize()
     first = time.perf_counter() - t0
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(s):
-        e0.record(s)
-        for _ in range(args.batch_steps):
-            b.decompose(Xs)
-        e1.record(s)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.batch_steps
+    def timed_batches():
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(s):
+            e0.record(s)
+            for _ in range(args.batch_steps):
+                b.decompose(Xs)
+            e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.batch_steps
+
+    ms_default = timed_batches()
+    tune = None
+    if args.batch_autotune:
+        # the launch shape chosen by the library's autotuner, then timed again
+        with torch.cuda.stream(s):
+            tune = b.autotune(Xs)
+            b.decompose(Xs)                   # records the graph with the chosen shape
+        torch.cuda.synchronize()
+        ms = timed_batches()
+    else:
+        ms = ms_default
     infos = b.read_info()
     errs = [i["rel_err"] for i in infos]
     out = {"problems": args.batch, "elements": elems, "ms_per_batch": ms,
            "solves_per_s": args.batch * 1000.0 / ms, "first_call_s_with_graph_recording": first,
+           "ms_per_batch_default_shape": ms_default, "autotuned_shape": tune,
            "rel_err_mean": float(np.mean(errs)), "rel_err_max": float(np.max(errs)),
            "status_nonzero": int(sum(1 for i in infos if i["status"] != 0)),
            "workload": "3-way tensors, modes U{32..256}, R U{4..16}, noise 0.05, k=R, p=10, q=2, "

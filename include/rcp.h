@@ -243,6 +243,23 @@ rcp_status rcp_batch_init(rcp_batch* batch, const rcp_problem* probs, int32_t co
                           float* const* const* A, float* const* lambda, rcp_als_info* info,
                           void* workspace, size_t workspace_bytes, void* hip_stream);
 rcp_status rcp_batch_decompose(rcp_batch batch, const float* const* X);
+/* Autotuner of the batched launch shape (no counterpart in the paper, which
+ * has no batched form).  Times complete rcp_batch_decompose calls on the
+ * given inputs (so it also leaves their results in the outputs) for
+ * candidate shapes, searching one knob at a time with the others at their
+ * best so far:
+ *   shape[0] internal streams the compressions are spread over: 4, 8, 16;
+ *   shape[1] workgroups per streaming pass: 64, 128, one per compute unit;
+ *   shape[2] rows per row block of the sketch passes of modes with at most
+ *            512 rows, in units of 64: 1, 2, 4, 8.
+ * Each candidate is recorded once and timed over two replays with HIP events
+ * on the batch stream.  The fastest shape is kept for later calls of this
+ * batch (the graph is recorded again on the next call) and written to the
+ * host array shape[3]; *best_ms (host) receives its time per call.  Blocks
+ * until the timing is done.  Errors: RCP_ERR_INVALID_ARG for null arguments
+ * or misaligned inputs, RCP_ERR_HIP for a failed launch or event call. */
+rcp_status rcp_batch_autotune(rcp_batch batch, const float* const* X, int32_t* shape,
+                              double* best_ms);
 rcp_status rcp_batch_destroy(rcp_batch batch);
 
 /* Static description of a status code. */

@@ -296,6 +296,24 @@ class Batch:
                                                 _lib.ptr_array([X.data_ptr() for X in Xs])),
                    "rcp_batch_decompose")
 
+    def autotune(self, Xs) -> dict:
+        """Time the batch over candidate launch shapes (rcp_batch_autotune)
+        and keep the fastest; blocks.  Returns the chosen shape and its time."""
+        if len(Xs) != self.count:
+            raise ValueError(f"expected {self.count} tensors, got {len(Xs)}")
+        for X, dims in zip(Xs, self.dims):
+            _f32(X, "X")
+            if list(X.shape) != dims:
+                raise ValueError(f"tensor of shape {list(X.shape)} where {dims} was planned")
+        self._X = list(Xs)
+        shape = (ctypes.c_int32 * 3)()
+        ms = ctypes.c_double(0.0)
+        _lib.check(self.lib.rcp_batch_autotune(self.handle,
+                                               _lib.ptr_array([X.data_ptr() for X in Xs]),
+                                               shape, ctypes.byref(ms)), "rcp_batch_autotune")
+        return {"streams": shape[0], "workgroups": shape[1], "row_block_rows": 64 * shape[2],
+                "ms_per_batch": ms.value}
+
     def read_info(self):
         raw = bytes(self.info.cpu().numpy().tobytes())
         sz = ctypes.sizeof(_lib.AlsInfo)

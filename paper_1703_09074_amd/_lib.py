@@ -82,6 +82,8 @@ SIGNATURES = {
                              ctypes.POINTER(ctypes.POINTER(_vp)), ctypes.POINTER(_vp), _vp, _vp,
                              ctypes.c_size_t, _vp]),
     "rcp_batch_decompose": (_st, [_vp, ctypes.POINTER(_vp)]),
+    "rcp_batch_autotune": (_st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_double)]),
     "rcp_batch_destroy": (_st, [_vp]),
     "rcp_status_string": (ctypes.c_char_p, [_st]),
     "rcp_version": (ctypes.c_char_p, []),

@@ -109,7 +109,7 @@ Layout make_layout(const rcp_problem* p) {
     L.y64 = take((size_t)L.Imax * L.LPmax * sizeof(double));
     L.qt = take((size_t)L.Imax * L.LPmax * sizeof(float));
     int nib = 1;
-    for (int n = 0; n < L.N; ++n) nib = std::max(nib, contract_out_row_blocks(L.dims[n]));
+    for (int n = 0; n < L.N; ++n) nib = std::max(nib, contract_out_row_blocks(L.dims[n], 1));
     L.sq = take((size_t)kPmax * nib * sizeof(double));
     L.norm = take(64 * sizeof(double));
     for (int n = 0; n < L.N; ++n) L.qb[n] = take((size_t)L.dims[n] * L.l[n] * sizeof(float));
@@ -169,6 +169,7 @@ struct rcp_plan_t {
     char* ws;
     size_t ws_bytes;
     int P;                 // workgroups per streaming pass
+    int mb_cap = 8;        // row-block height of the sketch passes, in 64-row units
     size_t smem_limit;
     Profiler prof;
     template <class T>
@@ -246,7 +247,7 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
     float* Qt = pl->at<float>(pl->L.qt);
     double* sq = pl->at<double>(pl->L.sq);
     const uint32_t tag = omega_stream_tag(0, (uint32_t)mode);
-    const int nIB = contract_out_row_blocks(I);
+    const int nIB = contract_out_row_blocks(I, pl->mb_cap);
 
     const double S = (double)count_of(cur, N);
     const double J = S / (double)I;
@@ -256,7 +257,8 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
     const double qr_flops = 2.0 * 2.0 * (double)I * l * l;
     RCP_TRY(timed(pl, RCP_KERNEL_SKETCH, 4.0 * S + 4.0 * I * l, 2.0 * S * l, [&] {
         return launch_contract_out(g, l, nullptr, pl->prob.seed, tag, part, P,
-                                   norm_out ? sq : nullptr, pl->stream, pl->prob.precision);
+                                   norm_out ? sq : nullptr, pl->stream, pl->prob.precision,
+                                   pl->mb_cap);
     }));
     rcp_status st = reduce_y(pl, P, I, LP, norm_out ? sq : nullptr, P * nIB, norm_out);
     if (st != RCP_OK) return st;
@@ -272,7 +274,8 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
             RCP_TRY(timed(pl, RCP_KERNEL_CONTRACT_IN, 4.0 * S + 4.0 * J * LP, 2.0 * S * l,
                           [&] { return launch_contract_in(g, l, Qt, LP, Z, P, pl->stream, pl->prob.precision); }));
             RCP_TRY(timed(pl, RCP_KERNEL_CONTRACT_OUT, 4.0 * S + 4.0 * J * LP, 2.0 * S * l, [&] {
-                return launch_contract_out(g, l, Z, 0, 0, part, P, nullptr, pl->stream, pl->prob.precision);
+                return launch_contract_out(g, l, Z, 0, 0, part, P, nullptr, pl->stream,
+                                           pl->prob.precision, pl->mb_cap);
             }));
         }
         st = reduce_y(pl, P, I, LP, nullptr, 0, nullptr);
@@ -687,6 +690,11 @@ struct rcp_batch_t {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool use_graph = false;
+    // launch shape (rcp_batch_autotune): side streams in use, workgroups per
+    // streaming pass, row-block height of the sketch passes (64-row units)
+    int streams = kBatchStreams;
+    int workgroups = 0;
+    int mb_cap = 8;
 };
 
 namespace {
@@ -737,6 +745,16 @@ rcp_status batch_enqueue(rcp_batch_t* b, const float* const* X) {
     RCP_TRY(launch_als_batch(b->d_als, b->h_als.data(), b->count, b->stream));
     RCP_TRY(launch_expand_batch(b->d_exp, b->h_exp.data(), b->count, b->stream));
     return RCP_OK;
+}
+
+// Binds every problem's plan to the batch's current launch shape.
+void batch_apply_shape(rcp_batch_t* b) {
+    for (int i = 0; i < b->count; ++i) {
+        rcp_plan_t* pl = b->plans[i];
+        pl->stream = b->side[i % b->streams];
+        pl->P = b->workgroups;
+        pl->mb_cap = b->mb_cap;
+    }
 }
 
 void batch_drop_graph(rcp_batch_t* b) {
@@ -802,6 +820,7 @@ rcp_status rcp_batch_init(rcp_batch* batch, const rcp_problem* probs, int32_t co
         return RCP_ERR_HIP;
     }
     b->use_graph = hip_stream != nullptr;
+    b->workgroups = b->plans[0]->P;
     *batch = b;
     return RCP_OK;
 }
@@ -835,6 +854,75 @@ rcp_status rcp_batch_decompose(rcp_batch batch, const float* const* X) {
         batch->X.assign(X, X + batch->count);
     }
     RCP_TRY(hipGraphLaunch(batch->exec, batch->stream));
+    return RCP_OK;
+}
+
+// Coordinate search over the launch shape: each knob in turn takes every
+// candidate value with the others at their best so far; each candidate is
+// recorded (graph) once and timed over two replays.
+rcp_status rcp_batch_autotune(rcp_batch batch, const float* const* X, int32_t* shape,
+                              double* best_ms) {
+    if (batch == nullptr || X == nullptr || shape == nullptr || best_ms == nullptr)
+        return RCP_ERR_INVALID_ARG;
+    for (int i = 0; i < batch->count; ++i)
+        if (X[i] == nullptr || !aligned(X[i], 4)) return RCP_ERR_INVALID_ARG;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0 != nullptr) (void)hipEventDestroy(e0);
+        return RCP_ERR_HIP;
+    }
+    const int cus_default = batch->plans[0]->P;
+    int best[3] = {batch->streams, batch->workgroups, batch->mb_cap};
+    double best_t = -1.0;
+    rcp_status st = RCP_OK;
+    auto measure = [&](const int* c, double* ms) -> rcp_status {
+        batch->streams = c[0];
+        batch->workgroups = c[1];
+        batch->mb_cap = c[2];
+        batch_apply_shape(batch);
+        batch_drop_graph(batch);
+        rcp_status r = rcp_batch_decompose(batch, X);         // records the graph
+        if (r != RCP_OK) return r;
+        if (hipEventRecord(e0, batch->stream) != hipSuccess) return RCP_ERR_HIP;
+        for (int rep = 0; rep < 2 && r == RCP_OK; ++rep) r = rcp_batch_decompose(batch, X);
+        if (r != RCP_OK) return r;
+        if (hipEventRecord(e1, batch->stream) != hipSuccess ||
+            hipEventSynchronize(e1) != hipSuccess)
+            return RCP_ERR_HIP;
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) return RCP_ERR_HIP;
+        *ms = t / 2.0;
+        return RCP_OK;
+    };
+    st = measure(best, &best_t);
+    const int cand_s[] = {4, 8, kBatchStreams};
+    const int cand_p[] = {64, 128, cus_default};
+    const int cand_m[] = {1, 2, 4, 8};
+    const int* cands[3] = {cand_s, cand_p, cand_m};
+    const int ncand[3] = {3, 3, 4};
+    for (int knob = 0; knob < 3 && st == RCP_OK; ++knob) {
+        for (int c = 0; c < ncand[knob] && st == RCP_OK; ++c) {
+            int trial[3] = {best[0], best[1], best[2]};
+            if (trial[knob] == cands[knob][c]) continue;
+            trial[knob] = cands[knob][c];
+            double t = 0.0;
+            st = measure(trial, &t);
+            if (st == RCP_OK && t < best_t) {
+                best_t = t;
+                for (int k = 0; k < 3; ++k) best[k] = trial[k];
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    batch->streams = best[0];
+    batch->workgroups = best[1];
+    batch->mb_cap = best[2];
+    batch_apply_shape(batch);
+    batch_drop_graph(batch);
+    if (st != RCP_OK) return st;
+    for (int k = 0; k < 3; ++k) shape[k] = best[k];
+    *best_ms = best_t;
     return RCP_OK;
 }
 

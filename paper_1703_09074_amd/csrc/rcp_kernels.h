@@ -26,10 +26,13 @@ StreamGeom make_geom(const float* T, const int64_t* dims, int ndim, int mode);
 
 // streaming contractions (stream_kernels.hip)
 // precision: matrix-core operand type of the contraction (RCP_PREC_*)
+// mb_cap: at most 64 * mb_cap rows per row block for modes of at most 512
+// rows (a tile shape the batched form's autotuner chooses; taller modes
+// always take 512-row blocks)
 hipError_t launch_contract_out(const StreamGeom& g, int l, const float* Z, uint64_t seed,
                                uint32_t tag, float* part, int P, double* sq_part,
-                               hipStream_t s, int precision);
-int contract_out_row_blocks(int64_t I);
+                               hipStream_t s, int precision, int mb_cap = 8);
+int contract_out_row_blocks(int64_t I, int mb_cap = 8);
 bool power_fused_fits(int64_t I, int l, size_t smem_limit);
 hipError_t launch_power_fused(const StreamGeom& g, int l, const float* Qt, float* part, int P,
                               hipStream_t s, int precision);
@@ -38,7 +41,7 @@ hipError_t launch_contract_in(const StreamGeom& g, int l, const float* Qpadded, 
 // the 16-bit operand instantiations (stream_kernels_lp.hip)
 hipError_t launch_contract_out_lp(int precision, const StreamGeom& g, int l, const float* Z,
                                   uint64_t seed, uint32_t tag, float* part, int P, double* sq_part,
-                                  hipStream_t s);
+                                  hipStream_t s, int mb_cap);
 hipError_t launch_power_fused_lp(int precision, const StreamGeom& g, int l, const float* Qt,
                                  float* part, int P, hipStream_t s);
 hipError_t launch_contract_in_lp(int precision, const StreamGeom& g, int l, const float* Qpadded,

@@ -176,9 +176,11 @@ hipError_t launch_pad_q(const float* Q, int64_t I, int l, float* Qpad, int ldq, 
     return hipGetLastError();
 }
 
-int contract_out_row_blocks(int64_t I) {
+int contract_out_row_blocks(int64_t I, int mb_cap) {
     int MBv = (int)((I + 63) / 64);
+    if (I <= 512 && MBv > mb_cap) MBv = mb_cap;
     if (MBv > 8) MBv = 8;
+    if (MBv < 1) MBv = 1;
     const int IB = 64 * MBv;
     return (int)((I + IB - 1) / IB);
 }
@@ -191,9 +193,10 @@ bool power_fused_fits(int64_t I, int l, size_t smem_limit) {
 
 hipError_t launch_contract_out(const StreamGeom& g, int l, const float* Z, uint64_t seed,
                                uint32_t tag, float* part, int P, double* sq_part, hipStream_t s,
-                               int precision) {
-    if (precision == kPrecFp32) return launch_contract_out_t<kPrecFp32>(g, l, Z, seed, tag, part, P, sq_part, s);
-    return launch_contract_out_lp(precision, g, l, Z, seed, tag, part, P, sq_part, s);
+                               int precision, int mb_cap) {
+    if (precision == kPrecFp32)
+        return launch_contract_out_t<kPrecFp32>(g, l, Z, seed, tag, part, P, sq_part, s, mb_cap);
+    return launch_contract_out_lp(precision, g, l, Z, seed, tag, part, P, sq_part, s, mb_cap);
 }
 
 hipError_t launch_power_fused(const StreamGeom& g, int l, const float* Qt, float* part, int P,

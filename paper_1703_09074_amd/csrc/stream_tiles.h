@@ -761,10 +761,12 @@ static hipError_t launch_co(dim3 grid, size_t smem, hipStream_t s, const StreamG
 template <int PR>
 hipError_t launch_contract_out_t(const StreamGeom& g, int l, const float* Z, uint64_t seed,
                                  uint32_t tag, float* part, int P, double* sq_part,
-                                 hipStream_t s) {
+                                 hipStream_t s, int mb_cap) {
     const int NBv = lp_blocks(l);
     int MBv = (int)((g.I + 63) / 64);
+    if (g.I <= 512 && MBv > mb_cap) MBv = mb_cap;    // the cap applies to short modes only
     if (MBv > 8) MBv = 8;
+    if (MBv < 1) MBv = 1;
     const int IB = 64 * MBv;
     const unsigned nIB = (unsigned)((g.I + IB - 1) / IB);
     const size_t smem = contract_out_smem(NBv, MBv);

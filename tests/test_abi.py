@@ -140,6 +140,9 @@ def test_null_plan_rejected_everywhere(lib):
     assert lib.rcp_get_bases(None, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_get_core(None, None, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_destroy(None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_batch_decompose(None, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_batch_autotune(None, None, None, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_batch_destroy(None) == _lib.RCP_ERR_INVALID_ARG
 
 
 def test_status_strings(lib):

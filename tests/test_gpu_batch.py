@@ -86,3 +86,33 @@ def test_batch_graph_replays():
             for a in As:
                 a.fill_(3.0)
         torch.cuda.synchronize()
+
+
+def test_batch_autotune_keeps_a_valid_shape():
+    """The autotuner's chosen launch shape is one of its candidates, and the
+    batch solved with it still matches the oracle (graph replays included)."""
+    probs, tensors = _problems(8, 13, 24, 64, 25)
+    Xs = [torch.from_numpy(x).cuda() for x in tensors]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = rcpgpu.Batch(probs)
+        shape = b.autotune(Xs)
+    assert shape["streams"] in (4, 8, 16)
+    assert shape["workgroups"] >= 64
+    assert shape["row_block_rows"] in (64, 128, 256, 512)
+    assert shape["ms_per_batch"] > 0.0
+    got = []
+    for rep in range(2):
+        with torch.cuda.stream(s):
+            b.decompose(Xs)
+        torch.cuda.synchronize()
+        got.append([_np(t) for t in b.lam])
+    for i, (pr, x) in enumerate(zip(probs, tensors)):
+        np.testing.assert_array_equal(got[0][i], got[1][i])
+        ref = rcp.rcp_als(x.astype(np.float64), pr["k"], pr["p"], pr["q"], pr["max_iters"], 0.0,
+                          pr["seed"])
+        e_ref = evaluate.relative_error(x, ref.lam, ref.factors)
+        e_gpu = evaluate.relative_error(x, _np(b.lam[i]), [_np(a) for a in b.A[i]])
+        cong = evaluate.congruence([_np(a) for a in b.A[i]], ref.factors)[0]
+        assert abs(e_gpu - e_ref) <= 1e-4, (i, e_gpu, e_ref)
+        assert cong >= 0.999, (i, cong)
