@@ -607,6 +607,78 @@ __device__ __forceinline__ int block_gj(double* Aug, int ldx, int R, int Rp, int
     return *okp != 0.0;
 }
 
+// a double of lane `lane` (wave-uniform) to every lane
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// doubles of LDS the solvers need beside the augmented system (the blocked
+// one's pivot rows, columns and inverses; the one-wavefront one's flag)
+__host__ __device__ inline int gj_buf_doubles(int ldx, int Rp) {
+    return 2 * GB * (ldx + Rp) + 2 * GB * GB + 1;
+}
+
+// One-wavefront variant for small systems (Rp <= 32 rows, W <= 64 columns):
+// lane c holds column c in registers and the rows rotate through them so
+// that the pivot row is always register 0 (static indexing): at step k the
+// pivot column comes from lane k by readlane, the pivot row is scaled, the
+// other rows lose their multiples of it and the finished pivot row moves to
+// the back; after Rp steps the rows are in order again (the steps are
+// unrolled, so the rotation is register renaming).  No barriers.
+template <int RP>
+__device__ __forceinline__ int gj_wave(double* Aug, int ldx, int R, int W, double thr) {
+    const int c = threadIdx.x & 63;
+    const bool cv = c < W;
+    double col[RP];
+#pragma unroll
+    for (int i = 0; i < RP; ++i) col[i] = cv ? Aug[i * ldx + c] : 0.0;
+    int ok = 1;
+#pragma unroll
+    for (int k = 0; k < RP; ++k) {
+        const double piv = readlane_f64(col[0], k);
+        if (k < R && !(piv > thr)) ok = 0;
+        const double u = col[0] / piv;
+#pragma unroll
+        for (int i = 1; i < RP; ++i) col[i] -= readlane_f64(col[i], k) * u;
+#pragma unroll
+        for (int i = 0; i < RP - 1; ++i) col[i] = col[i + 1];
+        col[RP - 1] = u;
+    }
+    if (cv && c >= RP) {
+#pragma unroll
+        for (int i = 0; i < RP; ++i) Aug[i * ldx + c] = col[i];
+    }
+    return ok;
+}
+
+// V^{-1} Xt in place for Rp (a multiple of 4) rows and W columns; every
+// thread returns the ok flag.
+__device__ __forceinline__ int gj_solve(double* Aug, int ldx, int R, int Rp, int W, double thr,
+                                        double* fbuf) {
+    if (Rp <= 32 && W <= 64) {
+        if ((threadIdx.x >> 6) == 0) {
+            int ok = 0;
+            switch (Rp) {
+                case 4: ok = gj_wave<4>(Aug, ldx, R, W, thr); break;
+                case 8: ok = gj_wave<8>(Aug, ldx, R, W, thr); break;
+                case 12: ok = gj_wave<12>(Aug, ldx, R, W, thr); break;
+                case 16: ok = gj_wave<16>(Aug, ldx, R, W, thr); break;
+                case 20: ok = gj_wave<20>(Aug, ldx, R, W, thr); break;
+                case 24: ok = gj_wave<24>(Aug, ldx, R, W, thr); break;
+                case 28: ok = gj_wave<28>(Aug, ldx, R, W, thr); break;
+                default: ok = gj_wave<32>(Aug, ldx, R, W, thr); break;
+            }
+            if (threadIdx.x == 0) fbuf[0] = ok ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        return fbuf[0] != 0.0;
+    }
+    return block_gj(Aug, ldx, R, Rp, W - Rp, fbuf, thr);
+}
+
 // Left block of the augmented system: V = *_{m != n} G_m, identity padding up
 // to Rp, and zero padding rows in the right block.
 __device__ __forceinline__ void hadamard_grams(const AlsCtx& c, int n, const double* G, double* Aug,
@@ -676,7 +748,7 @@ __device__ __forceinline__ int solve_update(const AlsCtx& c, int n, double* G, c
     for (int r = 0; r < R; ++r) dmax = fmax(dmax, Aug[r * ldx + r]);
     const double thr = kPivotRtol * dmax;
     ALS_SUB(8);
-    const int ok = block_gj(Aug, ldx, R, Rp, ln, pb, thr);
+    const int ok = gj_solve(Aug, ldx, R, Rp, Rp + ln, thr, pb);
     ALS_SUB(9);
     if (!ok) {
         // Moore-Penrose pseudo-inverse through the eigen-decomposition
@@ -779,7 +851,7 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
     c.foff = sfoff;
 
     // dynamic LDS: [factors | ones | G | M | Aug = [V | Xt] | pivot buffers | P | big: E,V (init) then the core]
-    const int Rp = (R + GB - 1) / GB * GB;
+    const int Rp = (R + 3) / 4 * 4;
     const int ldx = Rp + lmax;
     unsigned char* p = als_smem;
     c.fbase = (float*)p;
@@ -787,7 +859,7 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
     float* ones = (float*)p; p += RCP_MAX_RANK * sizeof(float);
     double* G = (double*)p;  p += (size_t)N * R * R * sizeof(double);
     double* Aug = (double*)p; p += (size_t)Rp * ldx * sizeof(double);
-    double* pb = (double*)p; p += (size_t)(2 * GB * (ldx + Rp) + 2 * GB * GB + 1) * sizeof(double);
+    double* pb = (double*)p; p += (size_t)gj_buf_doubles(ldx, Rp) * sizeof(double);
     float* P = (float*)p;    p += (size_t)als_part_floats(N, a.l, R) * sizeof(float);
     double* M = a.Ebuf + 2 * kEigLd * kEigLd;            // l_n x R, global (read by the fit and the fallback)
     double* E = EIG_IN_LDS ? (double*)p : a.Ebuf;
@@ -972,11 +1044,11 @@ __global__ __launch_bounds__(ANT) void k_als_wide_step(AlsArgs a, int n) {
     const int N = a.N, R = a.R, ln = a.l[n];
     int lmax = 0;
     for (int m = 0; m < N; ++m) lmax = max(lmax, a.l[m]);
-    const int Rp = (R + GB - 1) / GB * GB;
+    const int Rp = (R + 3) / 4 * 4;
     const int ldx = Rp + lmax;
     double* Aug = (double*)als_smem;
     double* pb = Aug + Rp * ldx;
-    float* fbase = (float*)(pb + 2 * GB * (ldx + Rp) + 2 * GB * GB + 1);
+    float* fbase = (float*)(pb + gj_buf_doubles(ldx, Rp));
     AlsCtx c;
     wide_ctx(a, c, sl, sfoff, fbase, red, sh);
     double* G = a.state + kStG;
@@ -1047,12 +1119,12 @@ static size_t als_lds_fixed(int N, const int* l, int R) {
         b += ((size_t)l[n] * R * sizeof(float) + 15) & ~(size_t)15;
         lmax = lmax > l[n] ? lmax : l[n];
     }
-    const int Rp = (R + GB - 1) / GB * GB;
+    const int Rp = (R + 3) / 4 * 4;
     const int ldx = Rp + lmax;
     b += RCP_MAX_RANK * sizeof(float);                        // ones
     b += (size_t)N * R * R * sizeof(double);                  // G
     b += (size_t)Rp * ldx * sizeof(double);                   // augmented system [V | M^T]
-    b += (size_t)(2 * GB * (ldx + Rp) + 2 * GB * GB + 1) * sizeof(double);  // pivot buffers
+    b += (size_t)gj_buf_doubles(ldx, Rp) * sizeof(double);   // pivot buffers
     b += (size_t)als_part_floats(N, l, R) * sizeof(float);    // partial products
     return b;
 }
@@ -1075,9 +1147,9 @@ bool als_core_in_lds(int N, const int* l, int R) {
 static size_t wide_step_lds(const AlsArgs& a) {
     int lmax = 0;
     for (int m = 0; m < a.N; ++m) lmax = lmax > a.l[m] ? lmax : a.l[m];
-    const int Rp = (a.R + GB - 1) / GB * GB;
+    const int Rp = (a.R + 3) / 4 * 4;
     const int ldx = Rp + lmax;
-    return (size_t)(Rp * ldx + 2 * GB * (ldx + Rp) + 2 * GB * GB + 1) * sizeof(double) +
+    return (size_t)(Rp * ldx + gj_buf_doubles(ldx, Rp)) * sizeof(double) +
            (size_t)lmax * a.R * sizeof(float);
 }
 
