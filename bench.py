@@ -365,7 +365,10 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-KERNEL_SOURCES = {"als": "als_kernel.hip", "qr": "qr_kernel.hip", "expand": "expand_kernel.hip"}
+# the sources each kernel class is compiled from (besides the shared headers)
+STREAM_SOURCES = ("stream_kernels.hip", "stream_tiles.h")
+KERNEL_SOURCES = {"als": ("als_kernel.hip",), "qr": ("qr_kernel.hip",),
+                  "expand": ("expand_kernel.hip",)}
 
 
 def _source_hash(kernel_class):
@@ -374,7 +377,7 @@ def _source_hash(kernel_class):
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "paper_1703_09074_amd", "csrc")
-    for f in (KERNEL_SOURCES.get(kernel_class, "stream_kernels.hip"), "rcp_device.h", "rcp_kernels.h"):
+    for f in KERNEL_SOURCES.get(kernel_class, STREAM_SOURCES) + ("rcp_device.h", "rcp_kernels.h"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
