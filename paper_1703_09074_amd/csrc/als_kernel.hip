@@ -78,11 +78,17 @@ struct AlsCtx {
 // Parallel cyclic Jacobi eigen-decomposition of the symmetric n x n matrix
 // A (row stride kEigLd, overwritten; eigenvalues end on the diagonal), with
 // the eigenvectors accumulated in the columns of V.  Round-robin (circle
-// method) ordering: each round rotates n/2 disjoint (p, q) pairs.  Returns
-// false if the off-diagonal mass did not fall below 1e-30 of the diagonal's.
+// method) ordering: each round rotates n/2 disjoint (p, q) pairs.  A round
+// is two phases: the rotation angles of the pairs, then one update in which
+// a thread owns a 2 x 2 block of A at (pair u, pair v) and replaces it by
+// G_u A_uv G_v^T (G = [[c, -s], [s, c]] of each pair, i.e. the row and the
+// column rotation at once, in place since no other thread touches the block)
+// or two entries of V's row (V <- V G^T).  Returns false if the off-diagonal
+// mass did not fall below 1e-30 of the diagonal's.
 __device__ __forceinline__ bool jacobi_eig(double* A, double* V, int n, double* red, double* sh) {
     const int tid = threadIdx.x;
     const int np = (n + 1) & ~1;
+    const int half = np / 2;
     double* cs = sh;
     double* sn = sh + 32;
     int* pp = (int*)(sh + 64);
@@ -102,7 +108,7 @@ __device__ __forceinline__ bool jacobi_eig(double* A, double* V, int n, double* 
         dia = block_sum(dia, red);
         if (off <= 1e-30 * dia || off == 0.0) { converged = true; break; }
         for (int round = 0; round < np - 1; ++round) {
-            if (tid < np / 2) {
+            if (tid < half) {
                 const int k = tid;
                 int a = (k == 0) ? 0 : ((k - 1 + round) % (np - 1)) + 1;
                 int b = ((np - 2 - k + round) % (np - 1)) + 1;
@@ -121,32 +127,37 @@ __device__ __forceinline__ bool jacobi_eig(double* A, double* V, int n, double* 
                 cs[k] = c; sn[k] = s; pp[k] = a; qq[k] = b;
             }
             __syncthreads();
-            // rows: A <- J^T A   (thread = (pair k, column j))
-            for (int k = tid / 64; k < np / 2; k += ANW) {
-                const int p = pp[k], q = qq[k];
-                if (q < n && sn[k] != 0.0) {
-                    const double c = cs[k], s = sn[k];
-                    for (int j = tid % 64; j < n; j += 64) {
-                        const double ap = A[p * kEigLd + j], aq = A[q * kEigLd + j];
-                        A[p * kEigLd + j] = c * ap - s * aq;
-                        A[q * kEigLd + j] = s * ap + c * aq;
-                    }
-                }
-            }
-            __syncthreads();
-            // columns: A <- A J, V <- V J   (thread = (pair k, row i))
-            for (int k = tid / 64; k < np / 2; k += ANW) {
-                const int p = pp[k], q = qq[k];
-                if (q < n && sn[k] != 0.0) {
-                    const double c = cs[k], s = sn[k];
-                    for (int i = tid % 64; i < n; i += 64) {
-                        const double ap = A[i * kEigLd + p], aq = A[i * kEigLd + q];
-                        A[i * kEigLd + p] = c * ap - s * aq;
-                        A[i * kEigLd + q] = s * ap + c * aq;
-                        const double vp = V[i * kEigLd + p], vq = V[i * kEigLd + q];
-                        V[i * kEigLd + p] = c * vp - s * vq;
-                        V[i * kEigLd + q] = s * vp + c * vq;
-                    }
+            // A: blocks (u, v); V: (row i, pair v)
+            const int nblk = half * half;
+            for (int e = tid; e < nblk + n * half; e += ANT) {
+                if (e < nblk) {
+                    const int u = e / half, v = e - (e / half) * half;
+                    const double cu = cs[u], su = sn[u], cv = cs[v], sv = sn[v];
+                    if (su == 0.0 && sv == 0.0) continue;
+                    const int p = pp[u], q = qq[u], r = pp[v], t = qq[v];
+                    const bool qv = q < n, tv = t < n;
+                    const double a00 = A[p * kEigLd + r];
+                    const double a01 = tv ? A[p * kEigLd + t] : 0.0;
+                    const double a10 = qv ? A[q * kEigLd + r] : 0.0;
+                    const double a11 = (qv && tv) ? A[q * kEigLd + t] : 0.0;
+                    // rows: [b0; b1] = G_u [a0; a1]
+                    const double b00 = cu * a00 - su * a10, b01 = cu * a01 - su * a11;
+                    const double b10 = su * a00 + cu * a10, b11 = su * a01 + cu * a11;
+                    // columns: [d0 d1] = [b0 b1] G_v^T
+                    A[p * kEigLd + r] = cv * b00 - sv * b01;
+                    if (tv) A[p * kEigLd + t] = sv * b00 + cv * b01;
+                    if (qv) A[q * kEigLd + r] = cv * b10 - sv * b11;
+                    if (qv && tv) A[q * kEigLd + t] = sv * b10 + cv * b11;
+                } else {
+                    const int e2 = e - nblk;
+                    const int i = e2 / half, v = e2 - (e2 / half) * half;
+                    const double sv = sn[v];
+                    if (sv == 0.0) continue;
+                    const double cv = cs[v];
+                    const int r = pp[v], t = qq[v];
+                    const double vr = V[i * kEigLd + r], vt = V[i * kEigLd + t];
+                    V[i * kEigLd + r] = cv * vr - sv * vt;
+                    V[i * kEigLd + t] = sv * vr + cv * vt;
                 }
             }
             __syncthreads();
