@@ -66,6 +66,8 @@ def parse():
                     help="time the batch again with the launch shape rcp_batch_autotune picks")
     ap.add_argument("--mixed-steps", type=int, default=10,
                     help="timed solves with bfloat16 and float16 operands (0 skips the comparison)")
+    ap.add_argument("--mixed-large-steps", type=int, default=2,
+                    help="timed solves per precision of the large mixed-precision workloads (0 skips)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU oracle sample budget (0 disables the cpu_baseline leg)")
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
@@ -190,6 +192,49 @@ def run_batch(args, torch, rcpgpu, dev):
                                "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
                                "sample": f"the first {n} problems of the batch in float64 ({dt:.1f} s)",
                                "max_abs_rel_err_diff_vs_gpu": float(max(diffs))}
+    return out
+
+
+# The mixed-precision configurations: 2048 x 2048 x 512 with a bfloat16 range
+# finder, 256 x 256 x 256 x 64 with a float16 one, each against float32 on the
+# same tensor (built on the GPU from the seeded recipe).
+MIXED_LARGE = (("rcp2048", "bf16"), ("rcp4way", "fp16"))
+
+
+def mixed_large(args, torch, rcpgpu, dev):
+    from paper_1703_09074_amd import synth
+    out = {}
+    for name, prec in MIXED_LARGE:
+        cfg = dict(synth.WORKLOADS[name])
+        dims = list(cfg["dims"])
+        X, _, _, _ = synth.low_rank_device(dims, cfg["R"], cfg["noise"], cfg["data_seed"],
+                                           kind=cfg["kind"], device=dev)
+        res = {}
+        for p in ("fp32", prec):
+            plan = rcpgpu.Plan(dims, cfg["k"], cfg["p"], cfg["q"], cfg["iters"], 0.0, cfg["seed"],
+                               device=dev, precision=p)
+            A = [torch.empty((d, cfg["k"]), dtype=torch.float32, device=dev) for d in dims]
+            lam = torch.empty((cfg["k"],), dtype=torch.float32, device=dev)
+            info = plan._info_buffer()
+            plan.decompose_into(X, A, lam, info)
+            torch.cuda.synchronize()
+            stream = torch.cuda.current_stream(dev)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.mixed_large_steps):
+                plan.decompose_into(X, A, lam, info)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res[p] = (e0.elapsed_time(e1) / args.mixed_large_steps, rcpgpu.Plan.read_info(info)["rel_err"])
+            del plan, A, lam, info
+        (t32, e32), (tlp, elp) = res["fp32"], res[prec]
+        out[name] = {"precision": prec, "ms_per_solve_fp32": t32, "ms_per_solve_mixed": tlp,
+                     "speedup_vs_fp32": t32 / tlp, "rel_err_fp32": e32, "rel_err_mixed": elp,
+                     "equal_error": abs(elp - e32) <= 1e-4,
+                     "note": "float32 run's parity with the oracle: tests/test_gpu_fullsize.py"}
+        del X
+        torch.cuda.empty_cache()
     return out
 
 
@@ -318,6 +363,7 @@ def main():
                 "timing": "host wall clock around the issue of all solves and a device sync"}
 
     batched = run_batch(args, torch, rcpgpu, dev) if args.batch > 0 else None
+    mixed_big = mixed_large(args, torch, rcpgpu, dev) if args.mixed_large_steps > 0 else None
 
     mixed = {}
     if args.mixed_steps > 0:
@@ -350,6 +396,7 @@ def main():
         "sketch_ttm": sketch_ttm,
         "kernels": kern,
         "mixed_vs_fp32": mixed or None,
+        "mixed_vs_fp32_large": mixed_big,
         "concurrent_streams": conc,
         "batched": batched,
         "cpu_baseline": None,
