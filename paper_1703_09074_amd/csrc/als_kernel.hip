@@ -726,13 +726,19 @@ __device__ __forceinline__ void gram_mfma(const float* F, int ln, int R, double*
         while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
         const int bj = bi + rem;
         const int c1 = bi * 16 + li, c2 = bj * 16 + li;
-        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < ln; k0 += 4) {
-            const int k = k0 + lk;
+        // two independent accumulation chains (even and odd steps of 4 rows)
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < ln; k0 += 8) {
+            const int k = k0 + lk, kb = k + 4;
             const double a = (k < ln && c1 < R) ? (double)F[k * R + c1] : 0.0;
             const double b = (k < ln && c2 < R) ? (double)F[k * R + c2] : 0.0;
+            const double a2 = (kb < ln && c1 < R) ? (double)F[kb * R + c1] : 0.0;
+            const double b2 = (kb < ln && c2 < R) ? (double)F[kb * R + c2] : 0.0;
             acc = mfma64(a, b, acc);
+            acc2 = mfma64(a2, b2, acc2);
         }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] += acc2[v];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = bi * 16 + lk + 4 * v, s = bj * 16 + li;
