@@ -253,7 +253,8 @@ rcp_status rcp_batch_decompose(rcp_batch batch, const float* const* X);
  *   shape[2] rows per row block of the sketch passes of modes with at most
  *            512 rows, in units of 64: 1, 2, 4, 8.
  * Each candidate is recorded once and timed over two replays with HIP events
- * on the batch stream.  The fastest shape is kept for later calls of this
+ * on the batch stream; it replaces the best so far only if at least 3%
+ * faster (the timing noise).  The chosen shape is kept for later calls of this
  * batch (the graph is recorded again on the next call) and written to the
  * host array shape[3]; *best_ms (host) receives its time per call.  Blocks
  * until the timing is done.  Errors: RCP_ERR_INVALID_ARG for null arguments

@@ -857,6 +857,8 @@ rcp_status rcp_batch_decompose(rcp_batch batch, const float* const* X) {
     return RCP_OK;
 }
 
+constexpr double kAutotuneGain = 0.97;
+
 // Coordinate search over the launch shape: each knob in turn takes every
 // candidate value with the others at their best so far; each candidate is
 // recorded (graph) once and timed over two replays.
@@ -907,7 +909,8 @@ rcp_status rcp_batch_autotune(rcp_batch batch, const float* const* X, int32_t* s
             trial[knob] = cands[knob][c];
             double t = 0.0;
             st = measure(trial, &t);
-            if (st == RCP_OK && t < best_t) {
+            // two replays time a candidate to a few percent: only a clear gain moves the shape
+            if (st == RCP_OK && t < kAutotuneGain * best_t) {
                 best_t = t;
                 for (int k = 0; k < 3; ++k) best[k] = trial[k];
             }
