@@ -151,7 +151,11 @@ rcp_status rcp_norm2(rcp_plan plan, const float* X, int64_t count, double* out);
  * 1..N-1 (Algorithm 2 step 2).  Sweeps: for n = 0..N-1, Ã_n = B_(n)
  * KR(Ã_{m!=n}) (*_{m!=n} Ã_m^T Ã_m)^+, column-normalised, lambda from the
  * last mode (steps 4-10).  Stops after max_iters sweeps, or earlier when
- * tol > 0 and the fit changes by less than tol (step 11). */
+ * tol > 0 and the fit changes by less than tol (step 11).  A core that fits
+ * in one workgroup's LDS runs the whole sweep loop in one launch; a larger
+ * one runs its mode products over the whole GPU with a one-workgroup solve
+ * per mode (every max_iters sweep is enqueued; after the stopping rule fires
+ * the remaining launches return at once).  Results agree to rounding. */
 rcp_status rcp_als(rcp_plan plan, const float* core, float* const* At,
                    float* lambda, const double* normX2, rcp_als_info* info);
 
