@@ -83,6 +83,19 @@ __device__ __forceinline__ void tile_issue(const StreamGeom& g, const TileInfo& 
                                            int nrows, TileRegs<MB>& pf) {
     const int tid = threadIdx.x;
     const float* base = g.T + ((ti.a0 * g.Is + i_lo) * g.Rr + ti.b0);
+    if (g.vec4 && ti.width == JT) {
+        // full, aligned tile: straight-line 16-byte loads; rows past the end
+        // read the last valid row and are zeroed afterwards
+#pragma unroll
+        for (int s = 0; s < MB; ++s) {
+            const int f = tid + s * NTS;
+            const int r = f >> 3, c0 = (f & 7) * 4;
+            const int rr = (r < nrows) ? r : nrows - 1;
+            const float4 v = *reinterpret_cast<const float4*>(base + (int64_t)rr * g.Rr + c0);
+            pf.v[s] = (r < nrows) ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        return;
+    }
 #pragma unroll
     for (int s = 0; s < MB; ++s) {
         const int f = tid + s * NTS;
