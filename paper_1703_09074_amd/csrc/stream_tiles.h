@@ -420,6 +420,17 @@ __global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const
                     Ws[jj * LPc + c] = (c < l) ? z[v] : 0.0f;
                 }
             }
+        } else if (!g.caseB && g.vec4 && ti.width == JT) {
+            // full, aligned tile: 16-byte loads of four consecutive rows j
+            for (int e = threadIdx.x; e < (JT / 4) * LPc; e += NTS) {
+                const int j4 = (e % (JT / 4)) * 4, c = e / (JT / 4);
+                const float4 v = *reinterpret_cast<const float4*>(
+                    Z + (ti.a0 * LPc + c) * g.Rr + ti.b0 + j4);
+                Ws[(j4 + 0) * LPc + c] = v.x;
+                Ws[(j4 + 1) * LPc + c] = v.y;
+                Ws[(j4 + 2) * LPc + c] = v.z;
+                Ws[(j4 + 3) * LPc + c] = v.w;
+            }
         } else {
             for (int e = threadIdx.x; e < JT * LPc; e += NTS) {
                 const int jj = e % JT, c = e / JT;
