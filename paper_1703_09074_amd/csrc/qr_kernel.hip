@@ -63,12 +63,12 @@ __device__ __forceinline__ double qr_block_max(double v, double* red) {
 // B operand [k][j] in lane j + 16 k, result element v of lane l is
 // [l / 16 + 4 v][l % 16].
 __device__ __forceinline__ void gram64(const double* A, int lda, int m, int n, int np, double* G,
-                                       double* part) {
+                                       double* part, int max_units) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int nb = np >> 4;
     const int U = nb * (nb + 1) / 2;
-    const int kp = (QNW / U) > 0 ? QNW / U : 1;
+    const int kp = (max_units / U) > 0 ? max_units / U : 1;
     const int per = (((m + kp - 1) / kp) + 3) & ~3;
     for (int u = wave; u < U * kp; u += QNW) {
         const int blk = u % U, p = u / U;
@@ -77,14 +77,28 @@ __device__ __forceinline__ void gram64(const double* A, int lda, int m, int n, i
         const int bj = bi + rem;
         const int c1 = bi * 16 + li, c2 = bj * 16 + li;
         const int r0 = p * per, r1 = min(m, r0 + per);
-        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int k0 = r0; k0 < r1; k0 += 4) {
-            const int r = k0 + lk;
-            const bool rv = r < r1;
-            const double a = (rv && c1 < n) ? A[r * lda + c1] : 0.0;
-            const double b = (rv && c2 < n) ? A[r * lda + c2] : 0.0;
-            acc = mfma64(a, b, acc);
+        // four steps of 4 rows per iteration, loads first (independent of
+        // the accumulators), over two accumulation chains
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = r0; k0 < r1; k0 += 16) {
+            double a[4], b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int r = k0 + 4 * t + lk;
+                const bool rv = r < r1;
+                const int rc = rv ? r : r0;
+                a[t] = A[rc * lda + (c1 < n ? c1 : 0)];
+                b[t] = A[rc * lda + (c2 < n ? c2 : 0)];
+                if (!rv || c1 >= n) a[t] = 0.0;
+                if (!rv || c2 >= n) b[t] = 0.0;
+            }
+            acc = mfma64(a[0], b[0], acc);
+            acc2 = mfma64(a[1], b[1], acc2);
+            acc = mfma64(a[2], b[2], acc);
+            acc2 = mfma64(a[3], b[3], acc2);
         }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] += acc2[v];
         double* dst = part + u * 256;
 #pragma unroll
         for (int v = 0; v < 4; ++v) dst[(lk + 4 * v) * 16 + li] = acc[v];
@@ -186,14 +200,27 @@ __device__ __forceinline__ void apply_upper(double* A, int lda, int m, int n, co
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb) acc[cb] = f64x4{0.0, 0.0, 0.0, 0.0};
         const int r = rb * 16 + li;
-        for (int k0 = 0; k0 < n; k0 += 4) {
-            const int kk = k0 + lk;
-            const double a = (r < m && kk < n) ? A[r * lda + kk] : 0.0;
+        const int rc = (r < m) ? r : 0;
+        // four steps of 4 columns per iteration, the row loads first
+        for (int k0 = 0; k0 < n; k0 += 16) {
+            double a[4];
 #pragma unroll
-            for (int cb = 0; cb < NB; ++cb) {
-                const int c = cb * 16 + li;
-                const double b = (kk < n && c < n) ? X[kk * np + c] : 0.0;
-                acc[cb] = mfma64(a, b, acc[cb]);
+            for (int t = 0; t < 4; ++t) {
+                const int kk = k0 + 4 * t + lk;
+                a[t] = A[rc * lda + (kk < n ? kk : 0)];
+                if (r >= m || kk >= n) a[t] = 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (k0 + 4 * t < n) {
+                    const int kk = k0 + 4 * t + lk;
+#pragma unroll
+                    for (int cb = 0; cb < NB; ++cb) {
+                        const int c = cb * 16 + li;
+                        const double b = (kk < n && c < n) ? X[kk * np + c] : 0.0;
+                        acc[cb] = mfma64(a[t], b, acc[cb]);
+                    }
+                }
             }
         }
 #pragma unroll
@@ -314,7 +341,7 @@ __global__ __launch_bounds__(QNT) void k_qr(double* Yg, int m, int n, int ldy, f
     const double shift_coef = 11.0 * ((double)m * n + (double)n * (n + 1)) * kUnitRoundoff;
     const int passes = second_pass ? 3 : 2;
     for (int pass = 0; pass < passes; ++pass) {
-        gram64(A, lda, m, n, np, G, scratch);
+        gram64(A, lda, m, n, np, G, scratch, USE_LDS ? QNW : 2 * QNW);
         bool first_order = false;
         if (pass == 2) {
             double e = 0.0;
@@ -394,7 +421,7 @@ hipError_t launch_qr(double* Y, int64_t m, int n, int ldy, float* Qpad, int ldq,
     const size_t lds = qr_lds_bytes(m, n);
     if (lds <= kQrLds - 4096)
         return launch_qr_l<true>(Y, (int)m, n, ldy, Qpad, ldq, Qout, sp, lds, s);
-    const size_t small = (2 * (size_t)np * np + kQrScratch) * sizeof(double);
+    const size_t small = (2 * (size_t)np * np + 2 * kQrScratch) * sizeof(double);
     return launch_qr_l<false>(Y, (int)m, n, ldy, Qpad, ldq, Qout, sp, small, s);
 }
 
