@@ -921,7 +921,16 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
                                    (n == N - 1) ? lam : lam_tmp, inv_norm, it_dbg);
             ALS_STAMP(3 + 2 * n);
         }
-        // ---- fit (Section 3.3): rho = 1 - (||X||^2 + ||Xhat||^2 - 2 <Xhat, X>) / ||X||^2
+        // ---- fit (Section 3.3): rho = 1 - (||X||^2 + ||Xhat||^2 - 2 <Xhat, X>) / ||X||^2,
+        // needed by the stopping rule (tol > 0), after the last sweep, and to
+        // report a non-finite model (seen first in lambda)
+        bool need_fit = a.tol > 0.0 || it == a.max_iters;
+        if (!need_fit) {
+            bool fin = true;
+            for (int r = 0; r < R; ++r) fin = fin && isfinite(lam[r]);
+            need_fit = !fin;
+        }
+        if (!need_fit) continue;
         double pi = 0.0;
         const float* AN = c.fac(N - 1);
         for (int e = tid; e < c.lN * R; e += ANT) pi += lam[e % R] * M[e] * (double)AN[e];
@@ -1087,7 +1096,25 @@ __global__ __launch_bounds__(ANT) void k_als_wide_step(AlsArgs a, int n) {
         if (tid == 0 && status != 0) fl[2] |= status;
         return;
     }
-    // fit (Section 3.3) on the core, as in the persistent kernel
+    // fit (Section 3.3) on the core, as in the persistent kernel, when the
+    // stopping rule, the last sweep or a non-finite lambda needs it
+    const int it = fl[1] + 1;
+    bool need_fit = a.tol > 0.0 || it >= a.max_iters;
+    if (!need_fit) {
+        bool fin = true;
+        for (int r = 0; r < R; ++r) fin = fin && isfinite(lam[r]);
+        need_fit = !fin;
+    }
+    if (!need_fit) {
+        for (int r = tid; r < R; r += ANT) a.state[kStG + (size_t)N * R * R + r] = lam[r];
+        __syncthreads();
+        if (tid == 0) {
+            fl[2] |= status;
+            fl[1] = it;
+            a.info->iters = it;
+        }
+        return;
+    }
     double pi = 0.0;
     const float* AN = c.fac(N - 1);
     for (int e = tid; e < c.lN * R; e += ANT) pi += lam[e % R] * M[e] * (double)AN[e];
@@ -1102,7 +1129,6 @@ __global__ __launch_bounds__(ANT) void k_als_wide_step(AlsArgs a, int n) {
     const double normX2 = *a.normX2;
     const double err2 = normX2 - 2.0 * inner + model;
     const double rho = (normX2 > 0.0) ? 1.0 - err2 / normX2 : 0.0;
-    const int it = fl[1] + 1;
     bool stop = it >= a.max_iters;
     if (!isfinite(rho)) {
         status |= RCP_INFO_NONFINITE;
