@@ -618,13 +618,6 @@ __device__ __forceinline__ int block_gj(double* Aug, int ldx, int R, int Rp, int
     return *okp != 0.0;
 }
 
-// a double of lane `lane` (wave-uniform) to every lane
-__device__ __forceinline__ double readlane_f64(double x, int lane) {
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
 
 // doubles of LDS the solvers need beside the augmented system (the blocked
 // one's pivot rows, columns and inverses; the one-wavefront one's flag)

@@ -30,8 +30,15 @@
 
 namespace rcp {
 
-constexpr int QNT = 1024;
+constexpr int QNT = 1024;                      // threads of the largest QR workgroup
 constexpr int QNW = QNT / 64;
+// threads and wavefronts of the running workgroup: 512 for bases of at most
+// 32 columns (their Cholesky runs in one wavefront's registers, which needs
+// more than the 128 VGPRs of a 1024-thread workgroup), 1024 otherwise
+__device__ __forceinline__ int qnt() { return (int)blockDim.x; }
+__device__ __forceinline__ int qnw() { return (int)(blockDim.x >> 6); }
+template <int NB>
+constexpr int qr_threads() { return NB <= 2 ? 512 : QNT; }
 constexpr size_t kQrLds = 160 * 1024;
 constexpr int kQrScratch = QNW * 256;         // doubles: Gram partials / Householder partial dots
 constexpr double kCqrPivot = 1e-15;           // relative pivot floor of the unshifted passes
@@ -52,7 +59,7 @@ __device__ __forceinline__ double qr_block_max(double v, double* red) {
     if (lane == 0) red[w] = v;
     __syncthreads();
     double t = red[0];
-    for (int i = 1; i < QNW; ++i) t = fmax(t, red[i]);
+    for (int i = 1; i < qnw(); ++i) t = fmax(t, red[i]);
     return t;
 }
 
@@ -70,7 +77,7 @@ __device__ __forceinline__ void gram64(const double* A, int lda, int m, int n, i
     const int U = nb * (nb + 1) / 2;
     const int kp = (max_units / U) > 0 ? max_units / U : 1;
     const int per = (((m + kp - 1) / kp) + 3) & ~3;
-    for (int u = wave; u < U * kp; u += QNW) {
+    for (int u = wave; u < U * kp; u += qnw()) {
         const int blk = u % U, p = u / U;
         int bi = 0, rem = blk;
         while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
@@ -104,7 +111,7 @@ __device__ __forceinline__ void gram64(const double* A, int lda, int m, int n, i
         for (int v = 0; v < 4; ++v) dst[(lk + 4 * v) * 16 + li] = acc[v];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < np * np; e += QNT) {
+    for (int e = threadIdx.x; e < np * np; e += qnt()) {
         int i = e / np, j = e - (e / np) * np;
         if ((i >> 4) > (j >> 4)) { const int t = i; i = j; j = t; }
         const int bi = i >> 4, bj = j >> 4;
@@ -132,13 +139,13 @@ __device__ __forceinline__ int chol_inverse(double* G, double* X, double* B, dou
                                             double* red, int n, int np, double shift_coef) {
     const int tid = threadIdx.x;
     double gm = 0.0, tr = 0.0;
-    for (int j = tid; j < n; j += QNT) { gm = fmax(gm, G[j * np + j]); tr += G[j * np + j]; }
+    for (int j = tid; j < n; j += qnt()) { gm = fmax(gm, G[j * np + j]); tr += G[j * np + j]; }
     tr = block_sum(tr, red);
     gm = qr_block_max(gm, red);
     const double shift = shift_coef * tr;
     const double thr = kCqrPivot * (gm + shift);
-    for (int j = tid; j < n; j += QNT) G[j * np + j] += shift;
-    for (int e = tid; e < np * np; e += QNT) {
+    for (int j = tid; j < n; j += qnt()) G[j * np + j] += shift;
+    for (int e = tid; e < np * np; e += qnt()) {
         const int i = e / np, c = e - (e / np) * np;
         X[e] = 0.0;
         B[e] = (i == c) ? 1.0 : 0.0;
@@ -154,7 +161,7 @@ __device__ __forceinline__ int chol_inverse(double* G, double* X, double* B, dou
         const int w = n - j - 1;
         if (w > 0) {
             const float inv_w = __builtin_amdgcn_rcpf((float)w);
-            for (int e = tid; e < w * w; e += QNT) {
+            for (int e = tid; e < w * w; e += qnt()) {
                 const int ii = small_div(e, w, inv_w), kk = e - ii * w;
                 if (kk < ii) continue;
                 const int i = j + 1 + ii, k = j + 1 + kk;
@@ -166,9 +173,9 @@ __device__ __forceinline__ int chol_inverse(double* G, double* X, double* B, dou
         __syncthreads();
     }
     // R_jj = sqrt(d_j), R_jk = g_jk / sqrt(d_j); keep 1 / R_jj in pinv
-    for (int j = tid; j < n; j += QNT) pinv[j] = 1.0 / sqrt(fmax(G[j * np + j], thr));
+    for (int j = tid; j < n; j += qnt()) pinv[j] = 1.0 / sqrt(fmax(G[j * np + j], thr));
     __syncthreads();
-    for (int e = tid; e < n * n; e += QNT) {
+    for (int e = tid; e < n * n; e += qnt()) {
         const int i = e / n, k = e - (e / n) * n;
         if (k > i) G[i * np + k] *= pinv[i];
     }
@@ -176,12 +183,75 @@ __device__ __forceinline__ int chol_inverse(double* G, double* X, double* B, dou
     // back substitution for R^{-1}, rows from the last
     for (int j = n - 1; j >= 0; --j) {
         const double ir = pinv[j];
-        for (int e = tid; e < (j + 1) * (n - j); e += QNT) {
+        for (int e = tid; e < (j + 1) * (n - j); e += qnt()) {
             const int i = e / (n - j), c = j + (e - (e / (n - j)) * (n - j));
             if (i == j) X[j * np + c] = B[j * np + c] * ir;
             else B[i * np + c] -= G[i * np + j] * B[j * np + c] * ir;
         }
         __syncthreads();
+    }
+    return ok;
+}
+
+// The same result for n <= NP <= 32 in one wavefront, from registers: lane c
+// holds column c of [G + shift I | I] (2 NP <= 64 columns, identity beyond
+// n), and the rows rotate through the registers so that the pivot row is
+// always register 0 (steps unrolled: static indices).  Step k subtracts
+// multiples of the pivot row from the rows below it (their entries in the
+// pivot column come from lane k by readlane) and moves it to the back; after
+// NP steps the rows read [U | L^{-1}] with G + shift I = L U, U = D L^T.  Then
+// R = D^{1/2} L^T, so R^{-1}[i][j] = L^{-1}[j][i] / sqrt(d_j): lane NP + i
+// holds column i of L^{-1} and writes row i of X.  Wavefront 0 runs it; it
+// returns 0 when a pivot is not above kCqrPivot times the largest diagonal
+// entry (shift included).  Callers synchronise the workgroup before using X.
+template <int NP>
+__device__ __forceinline__ int chol_inverse_wave(const double* G, double* X, int n,
+                                                 double shift_coef, double* isd) {
+    const int lane = threadIdx.x & 63;
+    double gm = 0.0, tr = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double d = G[j * NP + j];
+        gm = fmax(gm, d);
+        tr += d;
+    }
+    const double shift = shift_coef * tr;
+    const double thr = kCqrPivot * (gm + shift);
+    double col[NP];
+    const int c = lane;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        double v;
+        if (c < NP) {
+            v = (i < n && c < n) ? G[i * NP + c] : 0.0;
+            if (i == c) v = (i < n) ? v + shift : 1.0;
+        } else {
+            v = (i == c - NP) ? 1.0 : 0.0;
+        }
+        col[i] = v;
+    }
+    int ok = 1;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const double piv = readlane_f64(col[0], k);
+        if (k < n && !(piv > thr)) ok = 0;
+        if (lane == 0) isd[k] = 1.0 / sqrt(fmax(piv, thr));     // d_k = U[k][k]
+        const double u = col[0] / piv;
+#pragma unroll
+        for (int i = 1; i < NP - k; ++i) col[i] -= readlane_f64(col[i], k) * u;
+        const double p0 = col[0];
+#pragma unroll
+        for (int i = 0; i < NP - 1; ++i) col[i] = col[i + 1];
+        col[NP - 1] = p0;
+    }
+    // lane 0's isd stores before the other lanes' reads (one wavefront)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (c >= NP && c < 2 * NP) {
+        const int i = c - NP;
+#pragma unroll
+        for (int j = 0; j < NP; ++j)
+            X[i * NP + j] = (i < n && j < n && j >= i) ? col[j] * isd[j] : 0.0;
     }
     return ok;
 }
@@ -195,7 +265,7 @@ __device__ __forceinline__ void apply_upper(double* A, int lda, int m, int n, co
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int mb = (m + 15) >> 4;
-    for (int rb = wave; rb < mb; rb += QNW) {
+    for (int rb = wave; rb < mb; rb += qnw()) {
         f64x4 acc[NB];
 #pragma unroll
         for (int cb = 0; cb < NB; ++cb) acc[cb] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -270,10 +340,10 @@ __device__ __forceinline__ void householder_q(double* A, int lda, int m, int n, 
                                               double* taus, double* betas, double* red) {
     const int tid = threadIdx.x;
     const int CL = (n <= 32) ? 32 : 64;
-    const int G = QNT / CL;
+    const int G = qnt() / CL;
     for (int k = 0; k < n; ++k) {
         double s = 0.0;
-        for (int i = k + 1 + tid; i < m; i += QNT) {
+        for (int i = k + 1 + tid; i < m; i += qnt()) {
             const double v = A[i * lda + k];
             s += v * v;
         }
@@ -287,7 +357,7 @@ __device__ __forceinline__ void householder_q(double* A, int lda, int m, int n, 
             scale = 1.0 / (alpha - beta);
         }
         if (tau != 0.0)
-            for (int i = k + 1 + tid; i < m; i += QNT) A[i * lda + k] *= scale;
+            for (int i = k + 1 + tid; i < m; i += qnt()) A[i * lda + k] *= scale;
         if (tid == 0) { taus[k] = tau; betas[k] = beta; }
         __syncthreads();
         if (tau != 0.0 && k + 1 < n) apply_reflector(A, lda, m, n, k, tau, wp, CL, G);
@@ -295,7 +365,7 @@ __device__ __forceinline__ void householder_q(double* A, int lda, int m, int n, 
     for (int k = n - 1; k >= 0; --k) {
         const double tau = taus[k];
         if (k + 1 < n && tau != 0.0) apply_reflector(A, lda, m, n, k, tau, wp, CL, G);
-        for (int i = tid; i < m; i += QNT) {
+        for (int i = tid; i < m; i += qnt()) {
             double* p = A + i * lda + k;
             if (i > k) *p = -tau * (*p);
             else if (i == k) *p = 1.0 - tau;
@@ -304,7 +374,7 @@ __device__ __forceinline__ void householder_q(double* A, int lda, int m, int n, 
         __syncthreads();
     }
     // diag(R) >= 0: R_kk = beta_k, so negate column k where beta_k < 0
-    for (int e = tid; e < m * n; e += QNT) {
+    for (int e = tid; e < m * n; e += qnt()) {
         const int i = e / n, c = e - (e / n) * n;
         if (betas[c] < 0.0) A[i * lda + c] = -A[i * lda + c];
     }
@@ -312,7 +382,7 @@ __device__ __forceinline__ void householder_q(double* A, int lda, int m, int n, 
 }
 
 template <bool USE_LDS, int NB>
-__global__ __launch_bounds__(QNT) void k_qr(double* Yg, int m, int n, int ldy, float* Qpad, int ldq,
+__global__ __launch_bounds__(qr_threads<NB>()) void k_qr(double* Yg, int m, int n, int ldy, float* Qpad, int ldq,
                                             float* Qout, int second_pass) {
     extern __shared__ double qsm[];
     __shared__ double taus[64];
@@ -330,7 +400,7 @@ __global__ __launch_bounds__(QNT) void k_qr(double* Yg, int m, int n, int ldy, f
     double* X = G + np * np;
     double* scratch = X + np * np;
     if (USE_LDS) {
-        for (int e = tid; e < m * np; e += QNT) {
+        for (int e = tid; e < m * np; e += qnt()) {
             const int i = e / np, c = e - (e / np) * np;
             A[i * lda + c] = (c < n) ? Yg[(size_t)i * ldy + c] : 0.0;
         }
@@ -345,7 +415,7 @@ __global__ __launch_bounds__(QNT) void k_qr(double* Yg, int m, int n, int ldy, f
         bool first_order = false;
         if (pass == 2) {
             double e = 0.0;
-            for (int t = tid; t < n * n; t += QNT) {
+            for (int t = tid; t < n * n; t += qnt()) {
                 const int i = t / n, j = t - (t / n) * n;
                 e = fmax(e, fabs(G[i * np + j] - (i == j ? 1.0 : 0.0)));
             }
@@ -353,7 +423,7 @@ __global__ __launch_bounds__(QNT) void k_qr(double* Yg, int m, int n, int ldy, f
         }
         if (first_order) {
             // R3^{-1} = I - F to first order, F = triu(G - I) with the diagonal halved
-            for (int t = tid; t < np * np; t += QNT) {
+            for (int t = tid; t < np * np; t += qnt()) {
                 const int i = t / np, j = t - (t / np) * np;
                 double v = 0.0;
                 if (i < n && j < n && i <= j) {
@@ -365,7 +435,19 @@ __global__ __launch_bounds__(QNT) void k_qr(double* Yg, int m, int n, int ldy, f
             __syncthreads();
             apply_upper<NB>(A, lda, m, n, X);
         } else {
-            flag = chol_inverse(G, X, scratch, dinv, red, n, np, pass == 0 ? shift_coef : 0.0);
+            const double sc = pass == 0 ? shift_coef : 0.0;
+            if (np <= 32) {
+                if (tid < 64) {
+                    const int okw = (np == 16) ? chol_inverse_wave<16>(G, X, n, sc, dinv)
+                                               : chol_inverse_wave<32>(G, X, n, sc, dinv);
+                    if (tid == 0) red[0] = okw ? 1.0 : 0.0;
+                }
+                __syncthreads();
+                flag = red[0] != 0.0;
+                __syncthreads();
+            } else {
+                flag = chol_inverse(G, X, scratch, dinv, red, n, np, sc);
+            }
             if (!flag) {
                 householder_q(A, lda, m, n, scratch, taus, betas, red);
                 break;
@@ -376,7 +458,7 @@ __global__ __launch_bounds__(QNT) void k_qr(double* Yg, int m, int n, int ldy, f
     }
 
     // float32 outputs, zero padding columns
-    for (int e = tid; e < m * ldq; e += QNT) {
+    for (int e = tid; e < m * ldq; e += qnt()) {
         const int i = e / ldq, c = e - (e / ldq) * ldq;
         float v = 0.0f;
         if (c < n) {
@@ -398,7 +480,8 @@ static hipError_t launch_qr_t(double* Y, int m, int n, int ldy, float* Qpad, int
     hipError_t e = hipFuncSetAttribute((const void*)k_qr<L, NB>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_qr<L, NB>), dim3(1), dim3(QNT), lds, s, Y, m, n, ldy, Qpad, ldq, Qout, sp);
+    hipLaunchKernelGGL((k_qr<L, NB>), dim3(1), dim3(qr_threads<NB>()), lds, s, Y, m, n, ldy, Qpad, ldq,
+                       Qout, sp);
     return hipGetLastError();
 }
 

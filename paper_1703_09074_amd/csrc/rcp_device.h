@@ -110,6 +110,14 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return t;
 }
 
+// a double of lane `lane` (wave-uniform) to every lane of the wavefront
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Exact-ish integer quotient of small non-negative values (< 2^22) by a
 // positive divisor, using a float reciprocal plus one correction step.
 __device__ __forceinline__ int small_div(int a, int d, float inv_d) {
