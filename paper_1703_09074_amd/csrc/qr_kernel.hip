@@ -400,9 +400,26 @@ __global__ __launch_bounds__(qr_threads<NB>()) void k_qr(double* Yg, int m, int 
     double* X = G + np * np;
     double* scratch = X + np * np;
     if (USE_LDS) {
-        for (int e = tid; e < m * np; e += qnt()) {
-            const int i = e / np, c = e - (e / np) * np;
-            A[i * lda + c] = (c < n) ? Yg[(size_t)i * ldy + c] : 0.0;
+        // eight loads in flight per thread before their stores
+        const int total = m * np, nt = qnt();
+        for (int e0 = tid; e0 < total; e0 += 8 * nt) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * nt;
+                const int i = e / np, c = e - (e / np) * np;
+                const bool ok = e < total && c < n;
+                v[u] = Yg[ok ? (size_t)i * ldy + c : 0];
+                if (!ok) v[u] = 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * nt;
+                if (e < total) {
+                    const int i = e / np, c = e - (e / np) * np;
+                    A[i * lda + c] = v[u];
+                }
+            }
         }
     }
     __syncthreads();
@@ -457,15 +474,30 @@ __global__ __launch_bounds__(qr_threads<NB>()) void k_qr(double* Yg, int m, int 
         __syncthreads();
     }
 
-    // float32 outputs, zero padding columns
-    for (int e = tid; e < m * ldq; e += qnt()) {
-        const int i = e / ldq, c = e - (e / ldq) * ldq;
-        float v = 0.0f;
-        if (c < n) {
-            v = (float)A[i * lda + c];
-            if (Qout != nullptr) Qout[(int64_t)i * n + c] = v;
+    // float32 outputs, zero padding columns; eight reads in flight per thread
+    {
+        const int total = m * ldq, nt = qnt();
+        for (int e0 = tid; e0 < total; e0 += 8 * nt) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * nt;
+                const int i = e / ldq, c = e - (e / ldq) * ldq;
+                const bool ok = e < total && c < n;
+                v[u] = A[ok ? i * lda + c : 0];
+                if (!ok) v[u] = 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + u * nt;
+                if (e < total) {
+                    const int i = e / ldq, c = e - (e / ldq) * ldq;
+                    const float f = (float)v[u];
+                    if (Qout != nullptr && c < n) Qout[(int64_t)i * n + c] = f;
+                    Qpad[(int64_t)i * ldq + c] = f;
+                }
+            }
         }
-        Qpad[(int64_t)i * ldq + c] = v;
     }
 }
 
