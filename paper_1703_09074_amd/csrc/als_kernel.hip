@@ -619,6 +619,10 @@ __device__ __forceinline__ int block_gj(double* Aug, int ldx, int R, int Rp, int
 }
 
 
+// Row stride (doubles) of the augmented system [V | Xt]: odd, so that the 16
+// rows one matrix-core operand reads at a time fall in distinct LDS banks.
+__host__ __device__ inline int aug_ld(int Rp, int lmax) { return (Rp + lmax) | 1; }
+
 // doubles of LDS the solvers need beside the augmented system (the blocked
 // one's pivot rows, columns and inverses; the one-wavefront one's flag)
 __host__ __device__ inline int gj_buf_doubles(int ldx, int Rp) {
@@ -642,11 +646,18 @@ __device__ __forceinline__ int gj_wave(double* Aug, int ldx, int R, int W, doubl
     int ok = 1;
 #pragma unroll
     for (int k = 0; k < RP; ++k) {
-        const double piv = readlane_f64(col[0], k);
-        if (k < R && !(piv > thr)) ok = 0;
-        const double u = col[0] / piv;
+        // the whole pivot column is read before the first update: readlanes
+        // into distinct scalar registers issue back to back, where one
+        // broadcast per update serialises on a single register pair
+        double s[RP];
+        s[0] = readlane_f64(col[0], k);
+        const double u = col[0] / s[0];
 #pragma unroll
-        for (int i = 1; i < RP; ++i) col[i] -= readlane_f64(col[i], k) * u;
+        for (int i = 1; i < RP; ++i) s[i] = readlane_f64(col[i], k);
+        __builtin_amdgcn_sched_barrier(0);
+        if (k < R && !(s[0] > thr)) ok = 0;
+#pragma unroll
+        for (int i = 1; i < RP; ++i) col[i] -= s[i] * u;
 #pragma unroll
         for (int i = 0; i < RP - 1; ++i) col[i] = col[i + 1];
         col[RP - 1] = u;
@@ -743,18 +754,83 @@ __device__ __forceinline__ void gram_mfma(const float* F, int ln, int R, double*
     }
 }
 
+// Unit columns of the solution and their Gram in one pass: Xt holds the
+// solution transposed (R rows of length l_n, float64, stride ldx).  Every
+// wavefront takes 16 x 16 blocks (bi, bj) of the upper triangle of
+// G_n = F^T F, F the float32 factor with columns Xt_r / ||Xt_r||; it first
+// forms the norms of its own rows (each lane sums a quarter of the row, the
+// four quarters meet by shuffles), then feeds the matrix cores with exactly
+// the float32 values of F, so G_n is the float64 Gram of the stored factor.
+// The wavefronts of diagonal blocks also store F (l_n x R) and
+// lambda_r = ||Xt_r||.
+__device__ __forceinline__ void unit_factor_gram(const double* Xt, int ldx, int ln, int R, float* F,
+                                                 double* G, double* lam) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nb = (R + 15) >> 4;
+    const int U = nb * (nb + 1) / 2;
+    for (int u = wave; u < U; u += ANW) {
+        int bi = 0, rem = u;
+        while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
+        const int bj = bi + rem;
+        const bool diag = bi == bj;
+        const int c1 = bi * 16 + li, c2 = bj * 16 + li;
+        const bool v1 = c1 < R, v2 = c2 < R;
+        const double* x1 = Xt + (v1 ? c1 : 0) * ldx;
+        const double* x2 = Xt + (v2 ? c2 : 0) * ldx;
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
+        for (int k = lk; k < ln; k += 4) {
+            const double p = x1[k], q = x2[k];
+            s1 += p * p;
+            s2 += q * q;
+        }
+        s1 += __shfl_xor(s1, 16, 64);
+        s1 += __shfl_xor(s1, 32, 64);
+        s2 += __shfl_xor(s2, 16, 64);
+        s2 += __shfl_xor(s2, 32, 64);
+        const double nu1 = sqrt(s1), nu2 = sqrt(s2);
+        const double i1 = (nu1 > 0.0) ? 1.0 / nu1 : 1.0, i2 = (nu2 > 0.0) ? 1.0 / nu2 : 1.0;
+        if (diag && lk == 0 && v1) lam[c1] = nu1;
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < ln; k0 += 8) {
+            const int k = k0 + lk, kb = k + 4;
+            const bool ka = k < ln, kbv = kb < ln;
+            const float fa = (float)(x1[ka ? k : 0] * i1), fb = (float)(x2[ka ? k : 0] * i2);
+            const float fa2 = (float)(x1[kbv ? kb : 0] * i1), fb2 = (float)(x2[kbv ? kb : 0] * i2);
+            if (diag && v1) {
+                if (ka) F[k * R + c1] = fa;
+                if (kbv) F[kb * R + c1] = fa2;
+            }
+            acc = mfma64((ka && v1) ? (double)fa : 0.0, (ka && v2) ? (double)fb : 0.0, acc);
+            acc2 = mfma64((kbv && v1) ? (double)fa2 : 0.0, (kbv && v2) ? (double)fb2 : 0.0, acc2);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] += acc2[v];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = bi * 16 + lk + 4 * v, t = bj * 16 + li;
+            if (r < R && t < R) {
+                G[r * R + t] = acc[v];
+                if (!diag) G[t * R + r] = acc[v];
+            }
+        }
+    }
+}
+
 // Ã_n = M V^+ (V and M^T already in the augmented system), then unit
 // columns: lambda_r = ||column r||, the float32 factor in c.fac(n) and
 // G_n = Ã_n^T Ã_n of exactly that float32 factor (matrix cores).  Returns
 // RCP_INFO_* bits.
 __device__ __forceinline__ int solve_update(const AlsCtx& c, int n, double* G, const double* M,
                                             double* Aug, int ldx, int Rp, double* pb, double* E,
-                                            double* Ev, double* lam, double* inv_norm, int dbg_it) {
+                                            double* Ev, double* lam, int dbg_it) {
     (void)dbg_it;
     const int tid = threadIdx.x, R = c.R, ln = c.l[n];
     double* Xt = Aug + Rp;
     int status = 0;
     double dmax = 0.0;
+#pragma unroll 8
     for (int r = 0; r < R; ++r) dmax = fmax(dmax, Aug[r * ldx + r]);
     const double thr = kPivotRtol * dmax;
     ALS_SUB(8);
@@ -792,31 +868,9 @@ __device__ __forceinline__ int solve_update(const AlsCtx& c, int n, double* G, c
         }
         __syncthreads();
     }
-    // column norms of the solution (rows of Xt), wavefront w takes r = w, w + 8, ...
-    {
-        const int lane = tid & 63, wave = tid >> 6;
-        for (int r = wave; r < R; r += ANW) {
-            double ss = 0.0;
-            for (int i = lane; i < ln; i += 64) { const double x = Xt[r * ldx + i]; ss += x * x; }
-            ss = warp_sum(ss);
-            if (lane == 0) {
-                const double nu = sqrt(ss);
-                lam[r] = nu;
-                inv_norm[r] = (nu > 0.0) ? 1.0 / nu : 1.0;
-            }
-        }
-    }
+    unit_factor_gram(Xt, ldx, ln, R, c.fac(n), G + n * R * R, lam);
     __syncthreads();
-    {
-        float* fn = c.fac(n);
-        for (int e = tid; e < ln * R; e += ANT) {
-            const int i = e / R, r = e - (e / R) * R;
-            fn[e] = (float)(Xt[r * ldx + i] * inv_norm[r]);
-        }
-    }
-    __syncthreads();
-    gram_mfma(c.fac(n), ln, R, G + n * R * R);
-    __syncthreads();
+    ALS_SUB(10);
     return status;
 }
 
@@ -827,7 +881,6 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
     __shared__ double sh[128];
     __shared__ double lam[RCP_MAX_RANK];
     __shared__ double lam_tmp[RCP_MAX_RANK];
-    __shared__ double inv_norm[RCP_MAX_RANK];
     __shared__ int sl[RCP_MAX_NDIM];
     __shared__ int sfoff[RCP_MAX_NDIM];
     __shared__ int sst[RCP_MAX_NDIM];
@@ -862,7 +915,7 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
 
     // dynamic LDS: [factors | ones | G | M | Aug = [V | Xt] | pivot buffers | P | big: E,V (init) then the core]
     const int Rp = (R + 3) / 4 * 4;
-    const int ldx = Rp + lmax;
+    const int ldx = aug_ld(Rp, lmax);
     unsigned char* p = als_smem;
     c.fbase = (float*)p;
     p += fbytes;
@@ -911,7 +964,7 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
             __syncthreads();
             ALS_STAMP(2 + 2 * n);
             status |= solve_update(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs,
-                                   (n == N - 1) ? lam : lam_tmp, inv_norm, it_dbg);
+                                   (n == N - 1) ? lam : lam_tmp, it_dbg);
             ALS_STAMP(3 + 2 * n);
         }
         // ---- fit (Section 3.3): rho = 1 - (||X||^2 + ||Xhat||^2 - 2 <Xhat, X>) / ||X||^2,
@@ -1054,7 +1107,6 @@ __global__ __launch_bounds__(ANT) void k_als_wide_step(AlsArgs a, int n) {
     __shared__ double red[ANW];
     __shared__ double sh[128];
     __shared__ double lam[RCP_MAX_RANK];
-    __shared__ double inv_norm[RCP_MAX_RANK];
     __shared__ int sl[RCP_MAX_NDIM];
     __shared__ int sfoff[RCP_MAX_NDIM];
     int* fl = (int*)a.state;
@@ -1064,7 +1116,7 @@ __global__ __launch_bounds__(ANT) void k_als_wide_step(AlsArgs a, int n) {
     int lmax = 0;
     for (int m = 0; m < N; ++m) lmax = max(lmax, a.l[m]);
     const int Rp = (R + 3) / 4 * 4;
-    const int ldx = Rp + lmax;
+    const int ldx = aug_ld(Rp, lmax);
     double* Aug = (double*)als_smem;
     double* pb = Aug + Rp * ldx;
     float* fbase = (float*)(pb + gj_buf_doubles(ldx, Rp));
@@ -1083,7 +1135,7 @@ __global__ __launch_bounds__(ANT) void k_als_wide_step(AlsArgs a, int n) {
         Aug[r * ldx + Rp + i] = v;
     }
     __syncthreads();
-    int status = solve_update(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs, lam, inv_norm, 0);
+    int status = solve_update(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs, lam, 0);
     for (int e = tid; e < ln * R; e += ANT) a.At[n][e] = c.fac(n)[e];
     if (n < N - 1) {
         if (tid == 0 && status != 0) fl[2] |= status;
@@ -1156,7 +1208,7 @@ static size_t als_lds_fixed(int N, const int* l, int R) {
         lmax = lmax > l[n] ? lmax : l[n];
     }
     const int Rp = (R + 3) / 4 * 4;
-    const int ldx = Rp + lmax;
+    const int ldx = aug_ld(Rp, lmax);
     b += RCP_MAX_RANK * sizeof(float);                        // ones
     b += (size_t)N * R * R * sizeof(double);                  // G
     b += (size_t)Rp * ldx * sizeof(double);                   // augmented system [V | M^T]
@@ -1184,7 +1236,7 @@ static size_t wide_step_lds(const AlsArgs& a) {
     int lmax = 0;
     for (int m = 0; m < a.N; ++m) lmax = lmax > a.l[m] ? lmax : a.l[m];
     const int Rp = (a.R + 3) / 4 * 4;
-    const int ldx = Rp + lmax;
+    const int ldx = aug_ld(Rp, lmax);
     return (size_t)(Rp * ldx + gj_buf_doubles(ldx, Rp)) * sizeof(double) +
            (size_t)lmax * a.R * sizeof(float);
 }

@@ -232,12 +232,18 @@ __device__ __forceinline__ int chol_inverse_wave(const double* G, double* X, int
     int ok = 1;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        const double piv = readlane_f64(col[0], k);
+        // pivot column first, into distinct scalar registers, then the updates
+        double s[NP];
+        s[0] = readlane_f64(col[0], k);
+        const double u = col[0] / s[0];
+#pragma unroll
+        for (int i = 1; i < NP - k; ++i) s[i] = readlane_f64(col[i], k);
+        __builtin_amdgcn_sched_barrier(0);
+        const double piv = s[0];
         if (k < n && !(piv > thr)) ok = 0;
         if (lane == 0) isd[k] = 1.0 / sqrt(fmax(piv, thr));     // d_k = U[k][k]
-        const double u = col[0] / piv;
 #pragma unroll
-        for (int i = 1; i < NP - k; ++i) col[i] -= readlane_f64(col[i], k) * u;
+        for (int i = 1; i < NP - k; ++i) col[i] -= s[i] * u;
         const double p0 = col[0];
 #pragma unroll
         for (int i = 0; i < NP - 1; ++i) col[i] = col[i + 1];
