@@ -637,13 +637,18 @@ __host__ __device__ inline int gj_buf_doubles(int ldx, int Rp) {
 // the back; after Rp steps the rows are in order again (the steps are
 // unrolled, so the rotation is register renaming).  No barriers.
 template <int RP>
-__device__ __forceinline__ int gj_wave(double* Aug, int ldx, int R, int W, double thr) {
+__device__ __forceinline__ int gj_wave(double* Aug, int ldx, int R, int W, double rtol) {
     const int c = threadIdx.x & 63;
     const bool cv = c < W;
     double col[RP];
 #pragma unroll
     for (int i = 0; i < RP; ++i) col[i] = cv ? Aug[i * ldx + c] : 0.0;
-    int ok = 1;
+    const double dg = (c < RP) ? Aug[c * ldx + c] : 0.0;     // V_cc (V itself is not written)
+    // The pivot test does not steer the elimination, so it is taken once at
+    // the end: every pivot of the first R rows must exceed
+    // rtol * max_{r < R} V_rr, i.e. none is NaN and the smallest does.
+    double pmin = __builtin_huge_val();
+    bool pnan = false;
 #pragma unroll
     for (int k = 0; k < RP; ++k) {
         // the whole pivot column is read before the first update: readlanes
@@ -655,7 +660,10 @@ __device__ __forceinline__ int gj_wave(double* Aug, int ldx, int R, int W, doubl
 #pragma unroll
         for (int i = 1; i < RP; ++i) s[i] = readlane_f64(col[i], k);
         __builtin_amdgcn_sched_barrier(0);
-        if (k < R && !(s[0] > thr)) ok = 0;
+        if (k < R) {
+            pmin = fmin(pmin, s[0]);
+            pnan = pnan || (s[0] != s[0]);
+        }
 #pragma unroll
         for (int i = 1; i < RP; ++i) col[i] -= s[i] * u;
 #pragma unroll
@@ -666,32 +674,41 @@ __device__ __forceinline__ int gj_wave(double* Aug, int ldx, int R, int W, doubl
 #pragma unroll
         for (int i = 0; i < RP; ++i) Aug[i * ldx + c] = col[i];
     }
-    return ok;
+    double dmax = 0.0;
+#pragma unroll
+    for (int k = 0; k < RP; ++k) {
+        const double v = readlane_f64(dg, k);
+        if (k < R) dmax = fmax(dmax, v);
+    }
+    return (!pnan && pmin > rtol * dmax) ? 1 : 0;
 }
 
 // V^{-1} Xt in place for Rp (a multiple of 4) rows and W columns; every
-// thread returns the ok flag.
-__device__ __forceinline__ int gj_solve(double* Aug, int ldx, int R, int Rp, int W, double thr,
+// thread returns the ok flag (0 when a pivot of the first R rows is not above
+// rtol * max_{r < R} V_rr).
+__device__ __forceinline__ int gj_solve(double* Aug, int ldx, int R, int Rp, int W, double rtol,
                                         double* fbuf) {
     if (Rp <= 32 && W <= 64) {
         if ((threadIdx.x >> 6) == 0) {
             int ok = 0;
             switch (Rp) {
-                case 4: ok = gj_wave<4>(Aug, ldx, R, W, thr); break;
-                case 8: ok = gj_wave<8>(Aug, ldx, R, W, thr); break;
-                case 12: ok = gj_wave<12>(Aug, ldx, R, W, thr); break;
-                case 16: ok = gj_wave<16>(Aug, ldx, R, W, thr); break;
-                case 20: ok = gj_wave<20>(Aug, ldx, R, W, thr); break;
-                case 24: ok = gj_wave<24>(Aug, ldx, R, W, thr); break;
-                case 28: ok = gj_wave<28>(Aug, ldx, R, W, thr); break;
-                default: ok = gj_wave<32>(Aug, ldx, R, W, thr); break;
+                case 4: ok = gj_wave<4>(Aug, ldx, R, W, rtol); break;
+                case 8: ok = gj_wave<8>(Aug, ldx, R, W, rtol); break;
+                case 12: ok = gj_wave<12>(Aug, ldx, R, W, rtol); break;
+                case 16: ok = gj_wave<16>(Aug, ldx, R, W, rtol); break;
+                case 20: ok = gj_wave<20>(Aug, ldx, R, W, rtol); break;
+                case 24: ok = gj_wave<24>(Aug, ldx, R, W, rtol); break;
+                case 28: ok = gj_wave<28>(Aug, ldx, R, W, rtol); break;
+                default: ok = gj_wave<32>(Aug, ldx, R, W, rtol); break;
             }
             if (threadIdx.x == 0) fbuf[0] = ok ? 1.0 : 0.0;
         }
         __syncthreads();
         return fbuf[0] != 0.0;
     }
-    return block_gj(Aug, ldx, R, Rp, W - Rp, fbuf, thr);
+    double dmax = 0.0;
+    for (int r = 0; r < R; ++r) dmax = fmax(dmax, Aug[r * ldx + r]);
+    return block_gj(Aug, ldx, R, Rp, W - Rp, fbuf, rtol * dmax);
 }
 
 // Left block of the augmented system: V = *_{m != n} G_m, identity padding up
@@ -829,12 +846,8 @@ __device__ __forceinline__ int solve_update(const AlsCtx& c, int n, double* G, c
     const int tid = threadIdx.x, R = c.R, ln = c.l[n];
     double* Xt = Aug + Rp;
     int status = 0;
-    double dmax = 0.0;
-#pragma unroll 8
-    for (int r = 0; r < R; ++r) dmax = fmax(dmax, Aug[r * ldx + r]);
-    const double thr = kPivotRtol * dmax;
     ALS_SUB(8);
-    const int ok = gj_solve(Aug, ldx, R, Rp, Rp + ln, thr, pb);
+    const int ok = gj_solve(Aug, ldx, R, Rp, Rp + ln, kPivotRtol, pb);
     ALS_SUB(9);
     if (!ok) {
         // Moore-Penrose pseudo-inverse through the eigen-decomposition

@@ -230,6 +230,7 @@ __device__ __forceinline__ int chol_inverse_wave(const double* G, double* X, int
         col[i] = v;
     }
     int ok = 1;
+    double mypiv = 1.0;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         // pivot column first, into distinct scalar registers, then the updates
@@ -241,7 +242,7 @@ __device__ __forceinline__ int chol_inverse_wave(const double* G, double* X, int
         __builtin_amdgcn_sched_barrier(0);
         const double piv = s[0];
         if (k < n && !(piv > thr)) ok = 0;
-        if (lane == 0) isd[k] = 1.0 / sqrt(fmax(piv, thr));     // d_k = U[k][k]
+        mypiv = (lane == k) ? piv : mypiv;                       // d_k = U[k][k], kept by lane k
 #pragma unroll
         for (int i = 1; i < NP - k; ++i) col[i] -= s[i] * u;
         const double p0 = col[0];
@@ -249,7 +250,8 @@ __device__ __forceinline__ int chol_inverse_wave(const double* G, double* X, int
         for (int i = 0; i < NP - 1; ++i) col[i] = col[i + 1];
         col[NP - 1] = p0;
     }
-    // lane 0's isd stores before the other lanes' reads (one wavefront)
+    if (lane < NP) isd[lane] = 1.0 / sqrt(fmax(mypiv, thr));
+    // the isd stores before the other lanes' reads (one wavefront)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

@@ -135,6 +135,28 @@ def test_als_matches_oracle(dims, R, iters):
     np.testing.assert_allclose(gl, ref.lam[perm], rtol=1e-4)
 
 
+# An all-zero core: the first update makes A_0 zero, so every later V is the
+# zero matrix, the elimination meets zero pivots and the pseudo-inverse (of
+# zero) takes over (Definition 2), as in the oracle.  Three solver paths: one
+# wavefront (R = 3), blocked elimination (R = 36 > 32 rows) and the grid-wide
+# form (a 45^3 core exceeds one workgroup's LDS).
+@pytest.mark.parametrize("dims,R", [((9, 8, 7), 3), ((60, 50), 36), ((45, 45, 45), 4)])
+def test_als_zero_core_takes_pseudo_inverse(dims, R):
+    iters = 3
+    core = np.zeros(dims, dtype=np.float32)
+    plan = rcpgpu.Plan(dims, R, max(dims) - R, 0, iters, 0.0, 11)
+    nx = torch.tensor([1.0], dtype=torch.float64, device="cuda")
+    At, lam, info = plan.als(_dev(core), nx)
+    info = rcpgpu.Plan.read_info(info)
+    ref = rcp.als(core.astype(np.float64), R, iters, normX2=1.0)
+    assert info["status"] & 1, info
+    assert info["iters"] == iters
+    assert info["rho"] == ref.rho == 0.0
+    assert np.all(_np(lam) == 0.0) and np.all(ref.lam == 0.0)
+    for a, b in zip(At, ref.factors):
+        assert np.all(_np(a) == 0.0) and np.all(b == 0.0)
+
+
 # Cores larger than one workgroup's LDS take the grid-wide form (mode
 # products over the whole GPU, one-workgroup solves): 45^3 and 15^4 floats.
 @pytest.mark.parametrize("dims,R,iters,tol", [((60, 55, 50), 40, 15, 0.0),
