@@ -19,6 +19,8 @@
 #include "rcp_device.h"
 #include "rcp_kernels.h"
 
+#include <type_traits>
+
 namespace rcp {
 
 #ifdef RCP_ALS_TIMING
@@ -250,7 +252,8 @@ __device__ __forceinline__ bool eig_init(const AlsCtx& c, const float* Bg, int n
 template <int NN>
 __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, const int* st,
                                        const float* ones, float* P, double* M, double* Xt,
-                                       int ldx) {
+                                       int ldx, int dbg_it) {
+    (void)dbg_it;
     constexpr int D = NN - 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
@@ -317,7 +320,10 @@ __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, c
                 d[s] = 0;
             }
         };
-        if (nq <= kMtQuads) {
+        // NQ = 0: quad count nq at run time; NQ = kMtQuads: all quads, so the
+        // loop body has no branches
+        auto pipelined = [&](auto nq_const) {
+            constexpr int NQ = decltype(nq_const)::value;
             // software pipelined in half steps of four quads: the operands of
             // the next half are in flight while the matrix cores work on the
             // current one (at most nine LDS reads outstanding, within what the
@@ -339,7 +345,7 @@ __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, c
             auto compute = [&](const float* av, const float* bv, float w, int q0) {
 #pragma unroll
                 for (int q = 0; q < HQ; ++q) {
-                    if (q0 + q < nq) {
+                    if (q0 + q < (NQ ? NQ : nq)) {
                         const bool kv = lk + 4 * (q0 + q) < Kl;
                         const float x = kv ? av[q] : 0.0f;
                         const float y = kv ? w * bv[q] : 0.0f;
@@ -353,17 +359,22 @@ __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, c
                 fetch(alo, blo, boff, 0);
             }
             for (int o = o_lo; o < o_hi; ++o) {
-                if (nq > HQ) fetch(ahi, bhi, boff, HQ);
+                if ((NQ ? NQ : nq) > HQ) fetch(ahi, bhi, boff, HQ);
                 compute(alo, blo, ob, 0);
                 const bool more = o + 1 < o_hi;
                 if (more) {
                     outer(boff_next, ob_next);
                     fetch(alo, blo, boff_next, 0);
                 }
-                if (nq > HQ) compute(ahi, bhi, ob, HQ);
+                if ((NQ ? NQ : nq) > HQ) compute(ahi, bhi, ob, HQ);
                 ob = ob_next;
                 boff = boff_next;
             }
+        };
+        if (nq == kMtQuads) {
+            pipelined(std::integral_constant<int, kMtQuads>{});
+        } else if (nq <= kMtQuads) {
+            pipelined(std::integral_constant<int, 0>{});
         } else {
             for (int o = o_lo; o < o_hi; ++o) {
                 int boff;
@@ -411,6 +422,7 @@ __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, c
         }
     }
     __syncthreads();
+    ALS_SUB(13);
     if (keep_blk >= 0) {
         const int ib = keep_blk / ncb, cb = keep_blk - (keep_blk / ncb) * ncb;
         const int col = cb * 16 + lr;
@@ -973,7 +985,12 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
         ALS_STAMP(0);
         for (int n = 0; n < N; ++n) {
             hadamard_grams(c, n, G, Aug, ldx, Rp, c.l[n]);
-            mttkrp<NN>(c, n, Bs, sst, ones, P, M, Aug + Rp, ldx);
+            {
+                const int dbg_it = it_dbg;
+                (void)dbg_it;
+                ALS_SUB(12);
+            }
+            mttkrp<NN>(c, n, Bs, sst, ones, P, M, Aug + Rp, ldx, it_dbg);
             __syncthreads();
             ALS_STAMP(2 + 2 * n);
             status |= solve_update(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs,
