@@ -320,8 +320,9 @@ __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, c
                 d[s] = 0;
             }
         };
-        // NQ = 0: quad count nq at run time; NQ = kMtQuads: all quads, so the
-        // loop body has no branches
+        // NQ = 0: quad count nq at run time; otherwise a compile-time count
+        // NQ >= nq, so the loop body has no branches (the quads past nq read
+        // a clamped in-bounds element and feed zeros to the matrix cores)
         auto pipelined = [&](auto nq_const) {
             constexpr int NQ = decltype(nq_const)::value;
             // software pipelined in half steps of four quads: the operands of
@@ -371,8 +372,12 @@ __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, c
                 boff = boff_next;
             }
         };
-        if (nq == kMtQuads) {
-            pipelined(std::integral_constant<int, kMtQuads>{});
+        if (nq <= kMtQuads && nq >= 7) {
+            pipelined(std::integral_constant<int, 8>{});
+        } else if (nq == 5 || nq == 6) {
+            pipelined(std::integral_constant<int, 6>{});
+        } else if (nq == 3 || nq == 4) {
+            pipelined(std::integral_constant<int, 4>{});
         } else if (nq <= kMtQuads) {
             pipelined(std::integral_constant<int, 0>{});
         } else {
