@@ -108,6 +108,13 @@ __device__ __forceinline__ bool jacobi_eig(double* A, double* V, int n, double* 
             }
         off = block_sum(off, red);
         dia = block_sum(dia, red);
+#ifdef RCP_ALS_TIMING
+        if (tid == 0) {
+            const unsigned long long slot = atomicAdd(&g_als_ns[47], 1ull);
+            if (slot < 16) g_als_ns[48 + slot] = (unsigned long long)sweep * 1000000ull +
+                                                 (unsigned long long)fmin(999999.0, -10.0 * log10(off / dia + 1e-300));
+        }
+#endif
         if (off <= 1e-30 * dia || off == 0.0) { converged = true; break; }
         for (int round = 0; round < np - 1; ++round) {
             if (tid < half) {
@@ -225,6 +232,9 @@ __device__ __forceinline__ bool eig_init(const AlsCtx& c, const float* Bg, int n
         E[i2 * kEigLd + i] = s;
     }
     __syncthreads();
+#ifdef RCP_ALS_TIMING
+    if (tid == 0 && n == 1) g_als_stamps[1] = wall_clock64();
+#endif
     return eig_leading(c, n, E, V);
 }
 
@@ -969,9 +979,21 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
     const double normX2 = (a.normX2 != nullptr) ? *a.normX2 : normB2;
 
     int status = 0;
+#ifdef RCP_ALS_TIMING
+    {
+        const int it_dbg = 0;
+        ALS_STAMP(14);
+    }
+#endif
     for (int n = 1; n < N; ++n) {
         if (!eig_init(c, a.B, n, E, Ev)) status |= RCP_INFO_EIG_NOT_CONVERGED;
         gram_mfma(c.fac(n), c.l[n], R, G + n * R * R);   // Gram of the unit-norm eigenvectors
+#ifdef RCP_ALS_TIMING
+        if (n == 1) {
+            const int it_dbg = 0;
+            ALS_STAMP(11);
+        }
+#endif
     }
     __syncthreads();
     if (B_IN_LDS)
