@@ -118,9 +118,15 @@ __device__ __forceinline__ bool jacobi_eig(double* A, double* V, int n, double* 
         if (off <= 1e-30 * dia || off == 0.0) { converged = true; break; }
         for (int round = 0; round < np - 1; ++round) {
             if (tid < half) {
-                const int k = tid;
-                int a = (k == 0) ? 0 : ((k - 1 + round) % (np - 1)) + 1;
-                int b = ((np - 2 - k + round) % (np - 1)) + 1;
+                // round-robin pairing: a = (k - 1 + round) mod (np - 1) + 1 for
+                // k > 0, b = (np - 2 - k + round) mod (np - 1) + 1; both
+                // arguments lie in [0, 2 (np - 1)), so one subtraction reduces them
+                const int k = tid, m = np - 1;
+                int xa = k - 1 + round, xb = np - 2 - k + round;
+                if (xa >= m) xa -= m;
+                if (xb >= m) xb -= m;
+                int a = (k == 0) ? 0 : xa + 1;
+                int b = xb + 1;
                 if (a > b) { const int t = a; a = b; b = t; }
                 double c = 1.0, s = 0.0;
                 if (b < n) {
