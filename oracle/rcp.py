@@ -38,7 +38,12 @@ Parity: every function here is pinned by the oracle self-tests (brute-force
 loops on tiny tensors, exact recovery of noise-free low-rank tensors,
 orthonormality, the Halko matrix special case, equivalence with
 deterministic CP-ALS when l_n = I_n, the Khatri-Rao pseudo-inverse identity,
-monotone ALS residuals and the fit identity).
+monotone ALS residuals and the fit identity).  The q power iterations are
+pinned exactly: span(Q_n) equals span(U S^(2q+1) V^T Omega_n) from an SVD
+of T_(n) (eq. IMPsampleMatrix) and differs from the q - 1 span.  The
+sequential scheme is pinned by a brute-force loop: mode n sketches the tensor
+compressed in modes < n, with J_n rows of Omega_n (Algorithm 1 step 13).
+The warm start of ``als`` is pinned by continuing an interrupted run.
 """
 from __future__ import annotations
 

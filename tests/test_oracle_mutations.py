@@ -105,3 +105,70 @@ def test_lost_sign_compensation_is_caught(monkeypatch):
     monkeypatch.setattr(rcp, "finalize", fin)
     with pytest.raises(AssertionError):
         trcp.test_finalize_order_and_signs()
+
+
+def test_dropped_power_iteration_is_caught(monkeypatch):
+    """range_finder running q - 1 normalised power iterations instead of q."""
+    from tests import test_oracle_power_sequential as tps
+
+    def rf_short(T, n, l, q, seed, batch=0, normalizer="qr"):
+        Tn = rcp.unfold(T, n)
+        Om = philox.omega(seed, n, batch, 0, Tn.shape[1], l)
+        Y = Tn @ Om
+        y0 = Y.copy()
+        for _ in range(max(0, int(q) - 1)):
+            Qt = rcp._normalize(Y, normalizer)
+            Z = rcp._normalize(Tn.T @ Qt, normalizer)
+            Y = Tn @ Z
+        return rcp.ModeStage(mode=n, shape_in=T.shape, omega=Om, y0=y0, y_final=Y,
+                             Q=rcp.qr_pos(Y))
+    monkeypatch.setattr(rcp, "range_finder", rf_short)
+    with pytest.raises(AssertionError):
+        tps.test_power_iterations_span_closed_form(2, "qr")
+    with pytest.raises(AssertionError):
+        tps.test_power_iterations_span_through_compress()
+
+
+def test_sequential_scheme_sketching_x_is_caught(monkeypatch):
+    """The sequential scheme taking every sketch from X instead of the tensor
+    already compressed in the earlier modes (Algorithm 1 step 13)."""
+    from tests import test_oracle_power_sequential as tps
+    orig = rcp.compress
+
+    def compress_bad(X, k, p=10, q=2, seed=0, batch=0, scheme="sequential", normalizer="qr"):
+        if scheme != "sequential":
+            return orig(X, k, p, q, seed, batch, scheme, normalizer)
+        X = np.asarray(X, dtype=np.float64)
+        T, Qs, stages = X, [], []
+        for n in range(X.ndim):
+            st = rcp.range_finder(X, n, rcp.sketch_width(k, p, X.shape[n]), q, seed, batch,
+                                  normalizer)
+            stages.append(st)
+            Qs.append(st.Q)
+            T = rcp.mode_product(T, st.Q.T, n)
+        return rcp.Compression(core=T, Q=Qs, stages=stages)
+    monkeypatch.setattr(rcp, "compress", compress_bad)
+    with pytest.raises(AssertionError):
+        tps.test_sequential_scheme_sketches_partly_compressed_tensor((6, 5, 4), 2, 1)
+    with pytest.raises(AssertionError):
+        tps.test_sequential_and_independent_schemes_differ()
+
+
+def test_missing_column_normalisation_is_caught(monkeypatch):
+    """ALS and the renormalisation leaving the factor columns unscaled
+    (Algorithm 2 steps 5/7/9 and 13)."""
+    monkeypatch.setattr(rcp, "_scale_columns", lambda A, nu: A)
+    with pytest.raises(AssertionError):
+        trcp.test_exact_recovery_noise_free()
+
+
+def test_wrong_fit_sign_is_caught(monkeypatch):
+    """The model term of the Section 3.3 fit entering with the wrong sign."""
+    orig = rcp.gram_hadamard
+
+    def gh(factors, skip):
+        V = orig(factors, skip)
+        return -V if skip is None else V
+    monkeypatch.setattr(rcp, "gram_hadamard", gh)
+    with pytest.raises(AssertionError):
+        trcp.test_fit_identity_matches_brute_force()

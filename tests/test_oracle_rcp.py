@@ -217,3 +217,23 @@ def test_congruence_invariances():
     mean, mn, p = evaluate.congruence(F, G)
     assert abs(mean - 1.0) < 1e-14 and abs(mn - 1.0) < 1e-14
     assert list(p) == [1, 3, 0, 2]
+
+
+def test_warm_start_continues_the_sweeps():
+    """CP-ALS started from given factors (the warm start / resume of the
+    boundary): a sweep updates mode 1 first from the factors of modes 2..N,
+    so continuing from the factors after j sweeps reproduces sweeps j+1..
+    of the uninterrupted run exactly, and starting from the true factors of
+    a noise-free low-rank tensor fits it in one sweep."""
+    w = synth.low_rank((14, 12, 11), 3, 0.2, 25, dtype=np.float64)
+    full = rcp.als(w.X, 3, max_iters=7)
+    head = rcp.als(w.X, 3, max_iters=3)
+    tail = rcp.als(w.X, 3, max_iters=4, init=head.factors)
+    np.testing.assert_allclose(tail.rho_history, full.rho_history[3:], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(tail.lam, full.lam, rtol=1e-11)
+    for a, b in zip(tail.factors, full.factors):
+        np.testing.assert_allclose(a, b, atol=1e-10)
+    e = _exact((10, 9, 8), 3, 26)
+    true = [f / np.linalg.norm(f, axis=0) for f in e.factors]
+    one = rcp.als(e.X, 3, max_iters=1, init=true)
+    assert abs(one.rho - 1.0) < 1e-13, one.rho
