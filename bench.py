@@ -5,14 +5,18 @@ finder on every mode with in-kernel Gaussian test matrices, q power
 iterations, the chained mode products down to the core, CP-ALS on the core
 and the back-projection, from X resident in HBM to (lambda, A_n) in HBM.
 
-Default workload (rcp400): a dense 400 x 400 x 400 float32 tensor, rank 20
-with mode-0 column norms log-uniform in [1, 100], noise 0.05 rms; k = 20,
-p = 10, q = 2, 100 ALS sweeps.
+Default workload (rcp2048, the largest single-GPU configuration): a dense
+2048 x 2048 x 512 float32 tensor (8 GiB), rank 50 with factors N(0,1), noise
+0.1 rms; k = 50, p = 10, q = 2, 100 ALS sweeps.  Secondary lines: the
+400 x 400 x 400 workload (rank 20, log-uniform weights, noise 0.05, k = 20,
+p = 10, q = 2, 100 sweeps), the bfloat16 range finder on the same tensor,
+the 4-way float16 configuration and the batch of 512 small problems.
 
 Prints one JSON line.  Besides the throughput it reports, for the kernel
 class that takes the most time, the achieved algorithmic rate against the
 MI355X peak (HIP events around that kernel's launches on the plan's stream),
-every kernel class's totals, and the CPU oracle timed on this host.
+every kernel class's totals, and the CPU oracle timed on this host on a
+bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -55,7 +59,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rcp400")
+    ap.add_argument("--workload", default="rcp2048")
+    ap.add_argument("--secondary", default="rcp400",
+                    help="a second workload timed after the headline one ('' skips)")
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--concurrent", type=int, default=6, metavar="S",
                     help="also time independent solves on S streams (0 skips)")
@@ -90,12 +96,16 @@ def calibrate_copy(mib):
           flush=True)
 
 
+def _cores():
+    threads = os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS")
+    cores = len(os.sched_getaffinity(0))
+    return int(threads) if threads and threads.isdigit() else cores
+
+
 def cpu_baseline(X, cfg, budget_s):
     """The float64 oracle, unmodified, on this host: whole solves of the same
     workload until the budget is spent (at least one)."""
-    import numpy as np
     from oracle import rcp
-    cores = len(os.sched_getaffinity(0))
     X64 = X.astype(np.float64)
     n = 0
     rel_err = None
@@ -108,12 +118,40 @@ def cpu_baseline(X, cfg, budget_s):
         if time.perf_counter() - t0 >= budget_s or n >= 20:
             break
     dt = time.perf_counter() - t0
-    threads = os.environ.get("OMP_NUM_THREADS") or os.environ.get("OPENBLAS_NUM_THREADS")
-    return ({"value": n / dt, "unit": "solves/s",
-             "cores": int(threads) if threads and threads.isdigit() else cores,
-             "kind": "oracle",
+    return ({"value": n / dt, "unit": "solves/s", "cores": _cores(), "kind": "oracle",
              "sample": f"{n} whole solve(s) of the same workload in float64 NumPy/SciPy ({dt:.1f} s)"},
             rel_err)
+
+
+def cpu_baseline_sampled(X_dev, cfg, slices):
+    """The float64 oracle, unmodified, on a bounded sample of a tensor too
+    large to solve on the host within the bench: the sub-tensor of the first
+    ``slices`` indices of the last mode (same leading modes, same k, p, q,
+    sweeps and seed).  Its compression (Algorithm 1) is timed and scaled by
+    the element-count ratio to the whole tensor, since every pass streams the
+    tensor once; CP-ALS on its core (the same core size as the whole tensor's
+    while slices >= k + p) is timed as it is."""
+    from oracle import rcp
+    sub = X_dev[..., :slices].contiguous().cpu().numpy()
+    S_full = float(np.prod(cfg["dims"]))
+    S_sub = float(sub.size)
+    t0 = time.perf_counter()
+    X64 = sub.astype(np.float64)
+    normX2 = float(np.dot(X64.ravel(), X64.ravel()))
+    comp = rcp.compress(X64, cfg["k"], cfg["p"], cfg["q"], cfg["seed"])
+    t_comp = time.perf_counter() - t0
+    del X64
+    t1 = time.perf_counter()
+    res = rcp.als(comp.core, cfg["k"], cfg["iters"], 0.0, normX2=normX2)
+    rcp.expand(comp.Q, res.factors, res.lam)
+    t_als = time.perf_counter() - t1
+    t_solve = t_comp * S_full / S_sub + t_als
+    dims = list(cfg["dims"])
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": _cores(), "kind": "oracle",
+            "sample": (f"oracle rcp_als stages on the sub-tensor {dims[:-1] + [slices]} "
+                       f"(first {slices} of {dims[-1]} last-mode slices): compression "
+                       f"{t_comp:.2f} s scaled by {S_full / S_sub:.0f} (element ratio) + ALS and "
+                       f"expand on its core {t_als:.2f} s = {t_solve:.1f} s per solve")}
 
 
 def batch_workload(count, seed=20170331):
@@ -201,10 +239,12 @@ def run_batch(args, torch, rcpgpu, dev):
 MIXED_LARGE = (("rcp2048", "bf16"), ("rcp4way", "fp16"))
 
 
-def mixed_large(args, torch, rcpgpu, dev):
+def mixed_large(args, torch, rcpgpu, dev, skip=None):
     from paper_1703_09074_amd import synth
     out = {}
     for name, prec in MIXED_LARGE:
+        if name == skip:
+            continue
         cfg = dict(synth.WORKLOADS[name])
         dims = list(cfg["dims"])
         X, _, _, _ = synth.low_rank_device(dims, cfg["R"], cfg["noise"], cfg["data_seed"],
@@ -238,6 +278,112 @@ def mixed_large(args, torch, rcpgpu, dev):
     return out
 
 
+def measure(torch, rcpgpu, dev, name, X, precision, steps, warmup, profile_steps, traffic_json):
+    """Timed solves of one workload: throughput, per-kernel-class totals, the
+    dominant class's roofline line and the streaming passes' rates."""
+    from paper_1703_09074_amd import synth
+    cfg = dict(synth.WORKLOADS[name])
+    dims = list(cfg["dims"])
+    plan = rcpgpu.Plan(dims, cfg["k"], cfg["p"], cfg["q"], cfg["iters"], 0.0, cfg["seed"],
+                       device=dev, precision=precision)
+    A = [torch.empty((d, cfg["k"]), dtype=torch.float32, device=dev) for d in dims]
+    lam = torch.empty((cfg["k"],), dtype=torch.float32, device=dev)
+    info = plan._info_buffer()
+    for _ in range(warmup):
+        plan.decompose_into(X, A, lam, info)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.decompose_into(X, A, lam, info)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    res = rcpgpu.Plan.read_info(info)
+    out = {"ms_per_step": ms, "value": 1000.0 / ms, "wall_s": wall, "rel_err": res["rel_err"],
+           "status": res["status"], "iters": res["iters"]}
+    if profile_steps <= 0:
+        return out, plan
+    # per-kernel timing (separate pass with an event pair around every launch)
+    plan.profile(True)
+    for _ in range(profile_steps):
+        plan.decompose_into(X, A, lam, info)
+    torch.cuda.synchronize()
+    kern = plan.profile_read()
+    plan.profile(False)
+    for v in kern.values():
+        v["ms_per_launch"] = v["ms"] / v["launches"]
+        v["bytes_per_launch"] = v["bytes"] / v["launches"]
+        v["flops_per_launch"] = v["flops"] / v["launches"]
+        v["ms_per_step"] = v["ms"] / profile_steps
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    d = kern[dom]
+    bound, peak, unit, qty, kname, wgs = ROOFLINES.get(
+        dom, ("hbm", PEAK_HBM_GBS, "GB/s", "bytes", dom, None))
+    if dom in STREAMING:
+        # a contraction is bound by HBM or by the matrix cores, whichever its
+        # arithmetic intensity (flops per byte) against the machine balance says
+        ai = d["flops"] / d["bytes"]
+        mpeak = PEAK_FP32_MFMA_TFLOPS if precision == "fp32" else 2500.0
+        if ai > mpeak * 1e12 / (PEAK_HBM_GBS * 1e9):
+            bound, peak, unit, qty = "mfma", mpeak, "TFLOP/s", "flops"
+    scale = 1e9 if unit == "GB/s" else 1e12
+    per_launch = d[qty] / d["launches"]
+    ach = per_launch / (d["ms_per_launch"] * 1e-3) / scale
+    roof = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+            "kernel_class": dom, "kernel": kname, "ms_per_launch": d["ms_per_launch"],
+            ("flops" if qty == "flops" else "bytes") + "_per_launch": per_launch}
+    if wgs == 1:
+        # a single-workgroup kernel can use one compute unit's share of the peak
+        roof["frac_of_one_cu"] = ach / (peak / N_CU)
+    roof["traffic"] = None
+    if traffic_json and os.path.exists(traffic_json):
+        try:
+            tj = json.load(open(traffic_json))
+            ent = tj.get(name, {}).get(dom)
+            if ent and ent.get("source_hash") == _source_hash(dom):
+                roof["traffic"] = ent["bytes_per_launch"]
+        except (ValueError, OSError):
+            pass
+    sb = sum(kern[k]["bytes"] for k in STREAMING if k in kern)
+    sf = sum(kern[k]["flops"] for k in STREAMING if k in kern)
+    sm = sum(kern[k]["ms"] for k in STREAMING if k in kern)
+    mpeak = PEAK_FP32_MFMA_TFLOPS if precision == "fp32" else 2500.0
+    out["roofline"] = roof
+    out["sketch_ttm"] = {"gbps": sb / (sm * 1e-3) / 1e9, "tflops": sf / (sm * 1e-3) / 1e12,
+                         "frac_hbm": sb / (sm * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                         "frac_mfma": sf / (sm * 1e-3) / 1e12 / mpeak,
+                         "mfma_peak_tflops": mpeak,
+                         "ms_per_step": sm / profile_steps} if sm > 0 else None
+    out["kernels"] = kern
+    return out, plan
+
+
+def make_input(torch, name, dev):
+    from paper_1703_09074_amd import synth
+    cfg = dict(synth.WORKLOADS[name])
+    dims = list(cfg["dims"])
+    if int(np.prod(dims)) <= 100_000_000:
+        w_X = synth.make(name).X
+        return torch.from_numpy(w_X).to(dev), w_X
+    # too large to build on the host quickly: the same recipe assembled on the GPU
+    X, _, _, _ = synth.low_rank_device(dims, cfg["R"], cfg["noise"], cfg["data_seed"],
+                                       kind=cfg["kind"], device=dev)
+    return X, None
+
+
+def config_of(name):
+    from paper_1703_09074_amd import synth
+    cfg = dict(synth.WORKLOADS[name])
+    return {"workload": name, "dims": list(cfg["dims"]), "R": cfg["R"], "k": cfg["k"],
+            "p": cfg["p"], "q": cfg["q"], "als_iters": cfg["iters"], "noise": cfg["noise"],
+            "factors": cfg["kind"], "scheme": "sequential", "precision": "fp32"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -252,164 +398,142 @@ def main():
     import paper_1703_09074_amd as rcpgpu
     from paper_1703_09074_amd import synth
 
-    cfg = dict(synth.WORKLOADS[args.workload])
+    name = args.workload
+    cfg = dict(synth.WORKLOADS[name])
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    dims = list(cfg["dims"])
-    if int(np.prod(dims)) <= 100_000_000:
-        w_X = synth.make(args.workload).X
-        X = torch.from_numpy(w_X).to(dev)
-    else:
-        # too large to build on the host quickly: the same recipe assembled on the GPU
-        X, _, _, _ = synth.low_rank_device(dims, cfg["R"], cfg["noise"], cfg["data_seed"],
-                                           kind=cfg["kind"], device=dev)
-        w_X = None
-    def run(precision, steps, warmup):
-        plan = rcpgpu.Plan(dims, cfg["k"], cfg["p"], cfg["q"], cfg["iters"], 0.0, cfg["seed"],
-                           device=dev, precision=precision)
-        A = [torch.empty((d, cfg["k"]), dtype=torch.float32, device=dev) for d in dims]
-        lam = torch.empty((cfg["k"],), dtype=torch.float32, device=dev)
-        info = plan._info_buffer()
-        for _ in range(warmup):
-            plan.decompose_into(X, A, lam, info)
-        torch.cuda.synchronize()
-        stream = torch.cuda.current_stream(dev)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record(stream)
-        for _ in range(steps):
-            plan.decompose_into(X, A, lam, info)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms = e0.elapsed_time(e1) / steps
-        return plan, (A, lam, info), ms, wall, rcpgpu.Plan.read_info(info)
+    X, w_X = make_input(torch, name, dev)
+    head, plan = measure(torch, rcpgpu, dev, name, X, "fp32", args.steps, args.warmup,
+                         args.profile_steps, args.traffic_json)
+    del plan
 
-    plan, (A, lam, info), ms_per_step, wall, res = run("fp32", args.steps, args.warmup)
-    value = 1000.0 / ms_per_step
-
-    # per-kernel timing (separate pass with an event pair around every launch)
-    plan.profile(True)
-    for _ in range(args.profile_steps):
-        plan.decompose_into(X, A, lam, info)
-    torch.cuda.synchronize()
-    kern = plan.profile_read()
-    plan.profile(False)
-    for v in kern.values():
-        v["ms_per_launch"] = v["ms"] / v["launches"]
-        v["bytes_per_launch"] = v["bytes"] / v["launches"]
-        v["flops_per_launch"] = v["flops"] / v["launches"]
-        v["ms_per_step"] = v["ms"] / args.profile_steps
-    dom = max(kern, key=lambda k: kern[k]["ms"])
-    d = kern[dom]
-    bound, peak, unit, qty, kname, wgs = ROOFLINES.get(
-        dom, ("hbm", PEAK_HBM_GBS, "GB/s", "bytes", dom, None))
-    scale = 1e9 if unit == "GB/s" else 1e12
-    per_launch = d[qty] / d["launches"]
-    ach = per_launch / (d["ms_per_launch"] * 1e-3) / scale
-    roof = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
-            "kernel_class": dom, "kernel": kname, "ms_per_launch": d["ms_per_launch"],
-            ("flops" if qty == "flops" else "bytes") + "_per_launch": per_launch}
-    if wgs == 1:
-        # a single-workgroup kernel can use one compute unit's share of the peak
-        roof["frac_of_one_cu"] = ach / (peak / N_CU)
-    roof["traffic"] = None
-    if os.path.exists(args.traffic_json):
-        try:
-            tj = json.load(open(args.traffic_json))
-            ent = tj.get(args.workload, {}).get(dom)
-            if ent and ent.get("source_hash") == _source_hash(dom):
-                roof["traffic"] = ent["bytes_per_launch"]
-        except (ValueError, OSError):
-            pass
-    sb = sum(kern[k]["bytes"] for k in STREAMING if k in kern)
-    sf = sum(kern[k]["flops"] for k in STREAMING if k in kern)
-    sm = sum(kern[k]["ms"] for k in STREAMING if k in kern)
-    sketch_ttm = {"gbps": sb / (sm * 1e-3) / 1e9, "tflops": sf / (sm * 1e-3) / 1e12,
-                  "frac_hbm": sb / (sm * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                  "frac_fp32_mfma": sf / (sm * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS,
-                  "ms_per_step": sm / args.profile_steps} if sm > 0 else None
-
-    conc = None
-    if args.concurrent > 1:
-        # S independent plans, each bound to its own stream: one solve's single-CU ALS
-        # overlaps the next solves' grid-wide streaming passes
-        S = args.concurrent
-        streams = [torch.cuda.Stream(device=dev) for _ in range(S)]
-        slots = []
-        for st in streams:
-            with torch.cuda.stream(st):
-                pl = rcpgpu.Plan(dims, cfg["k"], cfg["p"], cfg["q"], cfg["iters"], 0.0, cfg["seed"],
-                                 device=dev)
-                As = [torch.empty((d, cfg["k"]), dtype=torch.float32, device=dev) for d in dims]
-                ls = torch.empty((cfg["k"],), dtype=torch.float32, device=dev)
-                slots.append((pl, As, ls, pl._info_buffer()))
-        torch.cuda.synchronize()
-        for pl, As, ls, inf in slots:
-            pl.decompose_into(X, As, ls, inf)
-        torch.cuda.synchronize()
-        total = S * max(2, args.steps // S)
-        t0 = time.perf_counter()
-        for i in range(total):
-            pl, As, ls, inf = slots[i % S]
-            pl.decompose_into(X, As, ls, inf)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        errs = [rcpgpu.Plan.read_info(inf)["rel_err"] for _, _, _, inf in slots]
-        conc = {"streams": S, "solves": total, "solves_per_s": total / dt,
-                "speedup_vs_one_stream": (total / dt) / value,
-                "rel_err_max_abs_diff": max(abs(e - res["rel_err"]) for e in errs),
-                "timing": "host wall clock around the issue of all solves and a device sync"}
-
-    batched = run_batch(args, torch, rcpgpu, dev) if args.batch > 0 else None
-    mixed_big = mixed_large(args, torch, rcpgpu, dev) if args.mixed_large_steps > 0 else None
-
+    # the mixed-precision form of the same workload, at equal error
     mixed = {}
     if args.mixed_steps > 0:
-        for prec in ("bf16", "fp16"):
-            _, _, mms, _, mres = run(prec, args.mixed_steps, 1)
-            mixed[prec] = {"ms_per_step": mms, "solves_per_s": 1000.0 / mms,
-                           "speedup_vs_fp32": ms_per_step / mms, "rel_err": mres["rel_err"],
-                           "rel_err_minus_fp32": mres["rel_err"] - res["rel_err"]}
+        precs = ("bf16", "fp16") if name in ("rcp100", "rcp400") else \
+            (("fp16",) if name.startswith("rcp4way") else ("bf16",))
+        for prec in precs:
+            m, pl = measure(torch, rcpgpu, dev, name, X, prec, args.mixed_steps, 1,
+                            args.profile_steps, None)
+            del pl
+            mixed[prec] = {"ms_per_step": m["ms_per_step"], "solves_per_s": m["value"],
+                           "speedup_vs_fp32": head["ms_per_step"] / m["ms_per_step"],
+                           "rel_err": m["rel_err"],
+                           "rel_err_minus_fp32": m["rel_err"] - head["rel_err"],
+                           "equal_error": abs(m["rel_err"] - head["rel_err"]) <= 1e-4,
+                           "sketch_ttm": m.get("sketch_ttm")}
+
+    cpu = None
+    oracle_err = None
+    if args.cpu_seconds > 0:
+        if w_X is not None:
+            cpu, oracle_err = cpu_baseline(w_X, cfg, args.cpu_seconds)
+        else:
+            # a bounded sample: 1/8 of the last mode for the 2048 x 2048 x 512 tensor
+            slices = max(cfg["k"] + cfg["p"], cfg["dims"][-1] // 8)
+            cpu = cpu_baseline_sampled(X, cfg, slices)
+    del X
+    torch.cuda.empty_cache()
+
+    secondary = None
+    if args.secondary and args.secondary != name:
+        sname = args.secondary
+        scfg = dict(synth.WORKLOADS[sname])
+        X2, w_X2 = make_input(torch, sname, dev)
+        sec, splan = measure(torch, rcpgpu, dev, sname, X2, "fp32", args.steps, args.warmup,
+                             args.profile_steps, args.traffic_json)
+        del splan
+        sec["config"] = config_of(sname)
+        if args.cpu_seconds > 0 and w_X2 is not None:
+            scpu, s_oracle = cpu_baseline(w_X2, scfg, args.cpu_seconds)
+            sec["cpu_baseline"] = scpu
+            sec["oracle_rel_err"] = s_oracle
+            sec["rel_err_minus_oracle"] = sec["rel_err"] - s_oracle
+        if args.concurrent > 1:
+            sec["concurrent_streams"] = concurrent(args, torch, rcpgpu, dev, sname, X2, sec)
+        if args.mixed_steps > 0:
+            sm = {}
+            for prec in ("bf16", "fp16"):
+                m, pl = measure(torch, rcpgpu, dev, sname, X2, prec, args.mixed_steps, 1, 0, None)
+                del pl
+                sm[prec] = {"ms_per_step": m["ms_per_step"],
+                            "speedup_vs_fp32": sec["ms_per_step"] / m["ms_per_step"],
+                            "rel_err": m["rel_err"], "rel_err_minus_fp32": m["rel_err"] - sec["rel_err"]}
+                if "oracle_rel_err" in sec:
+                    sm[prec]["valid_at_equal_error"] = bool(
+                        abs(sec["rel_err"] - sec["oracle_rel_err"]) <= 1e-4 and
+                        abs(m["rel_err"] - sec["oracle_rel_err"]) <= 1e-4)
+            sec["mixed_vs_fp32"] = sm
+        secondary = {sname: sec}
+        del X2
+        torch.cuda.empty_cache()
+
+    batched = run_batch(args, torch, rcpgpu, dev) if args.batch > 0 else None
+    mixed_big = mixed_large(args, torch, rcpgpu, dev, skip=name) if args.mixed_large_steps > 0 else None
 
     out = {
         "metric": "rCP solves/sec + sketch/TTM TFLOP/s (% peak), mixed vs FP32 at equal rel. error",
-        "value": value,
+        "value": head["value"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "dims": dims, "R": cfg["R"], "k": cfg["k"],
-                   "p": cfg["p"], "q": cfg["q"], "als_iters": cfg["iters"],
-                   "noise": cfg["noise"], "factors": cfg["kind"], "scheme": "sequential",
-                   "precision": "fp32"},
-        "rel_err": res["rel_err"],
-        "wall_s": wall,
-        "roofline": roof,
-        "sketch_ttm": sketch_ttm,
-        "kernels": kern,
+        "config": config_of(name),
+        "rel_err": head["rel_err"],
+        "wall_s": head["wall_s"],
+        "roofline": head.get("roofline"),
+        "sketch_ttm": head.get("sketch_ttm"),
+        "kernels": head.get("kernels"),
         "mixed_vs_fp32": mixed or None,
+        "cpu_baseline": cpu,
+        "secondary": secondary,
         "mixed_vs_fp32_large": mixed_big,
-        "concurrent_streams": conc,
         "batched": batched,
-        "cpu_baseline": None,
     }
-    if args.cpu_seconds > 0 and w_X is not None:
-        cb, oracle_err = cpu_baseline(w_X, cfg, args.cpu_seconds)
-        out["cpu_baseline"] = cb
+    if oracle_err is not None:
         out["oracle_rel_err"] = oracle_err
-        # mixed precision counts only at equal error: both within 1e-4 of the oracle's
-        fp32_ok = abs(res["rel_err"] - oracle_err) <= 1e-4
-        for m in mixed.values():
-            m["valid_at_equal_error"] = bool(fp32_ok and abs(m["rel_err"] - oracle_err) <= 1e-4)
+        out["rel_err_minus_oracle"] = head["rel_err"] - oracle_err
     print(json.dumps(out), flush=True)
+
+
+def concurrent(args, torch, rcpgpu, dev, name, X, base):
+    """S independent plans, each bound to its own stream: one solve's ALS
+    overlaps the next solves' grid-wide streaming passes."""
+    from paper_1703_09074_amd import synth
+    cfg = dict(synth.WORKLOADS[name])
+    dims = list(cfg["dims"])
+    S = args.concurrent
+    streams = [torch.cuda.Stream(device=dev) for _ in range(S)]
+    slots = []
+    for st in streams:
+        with torch.cuda.stream(st):
+            pl = rcpgpu.Plan(dims, cfg["k"], cfg["p"], cfg["q"], cfg["iters"], 0.0, cfg["seed"],
+                             device=dev)
+            As = [torch.empty((d, cfg["k"]), dtype=torch.float32, device=dev) for d in dims]
+            ls = torch.empty((cfg["k"],), dtype=torch.float32, device=dev)
+            slots.append((pl, As, ls, pl._info_buffer()))
+    torch.cuda.synchronize()
+    for pl, As, ls, inf in slots:
+        pl.decompose_into(X, As, ls, inf)
+    torch.cuda.synchronize()
+    total = S * max(2, args.steps // S)
+    t0 = time.perf_counter()
+    for i in range(total):
+        pl, As, ls, inf = slots[i % S]
+        pl.decompose_into(X, As, ls, inf)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    errs = [rcpgpu.Plan.read_info(inf)["rel_err"] for _, _, _, inf in slots]
+    return {"streams": S, "solves": total, "solves_per_s": total / dt,
+            "speedup_vs_one_stream": (total / dt) / base["value"],
+            "rel_err_max_abs_diff": max(abs(e - base["rel_err"]) for e in errs),
+            "timing": "host wall clock around the issue of all solves and a device sync"}
 
 
 # the sources each kernel class is compiled from (besides the shared headers)

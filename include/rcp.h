@@ -63,11 +63,15 @@ enum { RCP_PREC_FP32 = 0, RCP_PREC_BF16 = 1, RCP_PREC_FP16 = 2 };
  * forms the core by chained mode products afterwards. */
 enum { RCP_SCHEME_SEQUENTIAL = 0, RCP_SCHEME_INDEPENDENT = 1 };
 
-/* Device-side status bits in rcp_als_info.status. */
+/* Device-side status bits: rcp_als_info.status holds those of one CP-ALS
+ * run (the first three); the plan's status word (rcp_read_status) collects
+ * every bit any call on the plan has raised since it was last read. */
 enum {
-    RCP_INFO_PINV_FALLBACK = 1,  /* a Gram matrix was singular: pseudo-inverse used */
+    RCP_INFO_PINV_FALLBACK = 1,  /* a Gram matrix was singular: pseudo-inverse used (Definition 2) */
     RCP_INFO_NONFINITE = 2,      /* the fit became NaN/Inf */
-    RCP_INFO_EIG_NOT_CONVERGED = 4
+    RCP_INFO_EIG_NOT_CONVERGED = 4, /* the eigenvector start's Jacobi sweeps did not converge */
+    RCP_INFO_QR_HOUSEHOLDER = 8  /* a sketch was numerically rank deficient: its QR
+                                    (Algorithm 1 steps 8/12) fell back to Householder */
 };
 
 #define RCP_MAX_NDIM 8     /* tensor order N in [2, 8] */
@@ -122,6 +126,13 @@ rcp_status rcp_init(rcp_plan* plan, const rcp_problem* prob, void* workspace,
 /* Frees the host-side plan.  Does not touch the workspace. */
 rcp_status rcp_destroy(rcp_plan plan);
 
+/* Reads the plan's device status word (RCP_INFO_* bits raised by every call
+ * on the plan since rcp_init or the previous read) into *status (host) and
+ * clears it.  Blocks: the read is ordered after all work enqueued on the
+ * plan's stream.  RCP_ERR_INVALID_ARG for null arguments, RCP_ERR_HIP if the
+ * copy fails. */
+rcp_status rcp_read_status(rcp_plan plan, int32_t* status);
+
 /* Randomised range finder of one mode (Algorithm 1 steps 3-12).
  * T: current tensor with dims cur_dims[0..N-1] (host array); mode n; the
  * sketch width is l = min(k + p, cur_dims[n]).  Writes the orthonormal
@@ -148,7 +159,10 @@ rcp_status rcp_norm2(rcp_plan plan, const float* X, int64_t count, double* out);
  * R outputs; info: device rcp_als_info.  normX2: device pointer to ||X||^2
  * of the uncompressed tensor for the fit (NULL: use ||core||^2).
  * Initialisation: leading R eigenvectors of B_(n) B_(n)^T for modes
- * 1..N-1 (Algorithm 2 step 2).  Sweeps: for n = 0..N-1, Ã_n = B_(n)
+ * 1..N-1 (Algorithm 2 step 2); with use_given_init != 0 the sweeps start
+ * instead from the factors the caller left in At[1..N-1] (a warm start, the
+ * way to resume an interrupted run: At[0] is computed first and not read).
+ * Sweeps: for n = 0..N-1, Ã_n = B_(n)
  * KR(Ã_{m!=n}) (*_{m!=n} Ã_m^T Ã_m)^+, column-normalised, lambda from the
  * last mode (steps 4-10).  Stops after max_iters sweeps, or earlier when
  * tol > 0 and the fit changes by less than tol (step 11).  A core that fits
@@ -157,7 +171,8 @@ rcp_status rcp_norm2(rcp_plan plan, const float* X, int64_t count, double* out);
  * per mode (every max_iters sweep is enqueued; after the stopping rule fires
  * the remaining launches return at once).  Results agree to rounding. */
 rcp_status rcp_als(rcp_plan plan, const float* core, float* const* At,
-                   float* lambda, const double* normX2, rcp_als_info* info);
+                   float* lambda, const double* normX2, rcp_als_info* info,
+                   int32_t use_given_init);
 
 /* Back-projection A_n = Q_n Ã_n (eq. qbs, Algorithm 2 step 12) and the
  * renormalisation of step 13: unit columns, norms folded into lambda,
@@ -188,6 +203,14 @@ rcp_status rcp_get_core(rcp_plan plan, float** core, int64_t* core_dims);
  * uniforms ((x >> 8) + 1) 2^-24, Box-Muller on the pairs (u0,u1), (u2,u3). */
 rcp_status rcp_debug_omega(rcp_plan plan, int32_t mode, int64_t row0, int64_t nrows,
                            int32_t l, float* omega);
+
+/* The raw Philox4x32-10 output behind the same rows: for row j = row0 + r
+ * and column group g < ngroups (columns 4g..4g+3), words[(r * ngroups + g) * 4
+ * + i] (device, uint32) is word i of the generator applied to the counter
+ * (j mod 2^32, j >> 32, g, mode) under the key (seed mod 2^32, seed >> 32).
+ * ngroups in [1, 16]. */
+rcp_status rcp_debug_philox(rcp_plan plan, int32_t mode, int64_t row0, int64_t nrows,
+                            int32_t ngroups, uint32_t* words);
 
 /* Per-kernel timing of a plan's launches (for roofline reporting).
  * rcp_profile(plan, 1) starts recording a HIP event pair around every kernel
@@ -222,34 +245,43 @@ rcp_status rcp_profile_read(rcp_plan plan, int32_t kernel_class, int64_t* launch
  * the compression passes of the problems are spread over a few internal
  * streams forked from and joined back into the batch stream (so small
  * problems' kernels run side by side), then one launch runs CP-ALS for all
- * of them (one workgroup per problem) and one launch the back-projection.  The paper treats one tensor at a time; this is
- * the throughput form for many small ones.  Each problem gives exactly the
- * result rcp_decompose gives it alone.
+ * of them (one workgroup per problem) and one launch the back-projection.
+ * The paper treats one tensor at a time; this is the throughput form for
+ * many small ones.  Each problem gives exactly the result rcp_decompose
+ * gives it alone.
  *
  * rcp_batch_workspace_size: bytes of device workspace for probs[0..count).
  *   RCP_ERR_INVALID_ARG / RCP_ERR_UNSUPPORTED as rcp_init for any problem.
- * rcp_batch_init: binds the workspace (device, 256-byte aligned) and the
- *   stream, and fixes the outputs: A[i][n] (device, I_n x k_i float32,
- *   row-major), lambda[i] (device, k_i float32) and info[i] (device array of
- *   count rcp_als_info).  A and lambda are host arrays of device pointers,
- *   read during the call only.  The device argument tables of the batched
- *   launches are written into the workspace with a synchronous copy.
+ * rcp_batch_init: binds the workspace (device, 256-byte aligned, at least
+ *   rcp_batch_workspace_size bytes) and the stream (hipStream_t as void*,
+ *   NULL = the null stream); RCP_ERR_WORKSPACE / RCP_ERR_INVALID_ARG as
+ *   rcp_init.
  * rcp_batch_decompose: X[i] (host array of count device pointers to the
- *   C-order float32 tensors).  On a non-null stream the first call records
- *   the whole sequence in a HIP graph and launches it; later calls with the
- *   same X pointers relaunch the graph (other pointers re-record it).  On
- *   the null stream the kernels are enqueued directly.  Asynchronous like
- *   every other call; numeric outcomes land in info[i].
- * rcp_batch_destroy: frees the host-side state (the graph included). */
+ *   C-order float32 tensors), outputs A[i][n] (device, I_n x k_i float32,
+ *   row-major; A and A[i] are host arrays), lambda[i] (device, k_i float32)
+ *   and info (device array of count rcp_als_info).  The output pointers go
+ *   into device argument tables: when they differ from the previous call's,
+ *   the call first waits for the batch stream to drain and uploads new
+ *   tables in stream order (host blocking only then).  On a non-null stream
+ *   the first call records the whole sequence in a HIP graph and launches
+ *   it; later calls with the same X pointers relaunch the graph (other X
+ *   pointers re-record it).  On the null stream the kernels are enqueued
+ *   directly.  Asynchronous otherwise, like every other call; numeric
+ *   outcomes land in info[i].  RCP_ERR_INVALID_ARG: a null or misaligned
+ *   pointer.
+ * rcp_batch_read_status: the status word (rcp_read_status) of problem index.
+ * rcp_batch_destroy: waits for the batch stream, frees the host-side state
+ *   (the graph included). */
 typedef struct rcp_batch_t* rcp_batch;
 rcp_status rcp_batch_workspace_size(const rcp_problem* probs, int32_t count, size_t* bytes);
 rcp_status rcp_batch_init(rcp_batch* batch, const rcp_problem* probs, int32_t count,
-                          float* const* const* A, float* const* lambda, rcp_als_info* info,
                           void* workspace, size_t workspace_bytes, void* hip_stream);
-rcp_status rcp_batch_decompose(rcp_batch batch, const float* const* X);
+rcp_status rcp_batch_decompose(rcp_batch batch, const float* const* X, float* const* const* A,
+                               float* const* lambda, rcp_als_info* info);
+rcp_status rcp_batch_read_status(rcp_batch batch, int32_t index, int32_t* status);
 /* Autotuner of the batched launch shape (no counterpart in the paper, which
- * has no batched form).  Times complete rcp_batch_decompose calls on the
- * given inputs (so it also leaves their results in the outputs) for
+ * has no batched form).  Times complete batch decompositions of the given
+ * inputs into the given outputs (so it also leaves their results there) for
  * candidate shapes, searching one knob at a time with the others at their
  * best so far:
  *   shape[0] internal streams the compressions are spread over: 4, 8, 16;
@@ -261,9 +293,10 @@ rcp_status rcp_batch_decompose(rcp_batch batch, const float* const* X);
  * faster (the timing noise).  The chosen shape is kept for later calls of this
  * batch (the graph is recorded again on the next call) and written to the
  * host array shape[3]; *best_ms (host) receives its time per call.  Blocks
- * until the timing is done.  Errors: RCP_ERR_INVALID_ARG for null arguments
- * or misaligned inputs, RCP_ERR_HIP for a failed launch or event call. */
-rcp_status rcp_batch_autotune(rcp_batch batch, const float* const* X, int32_t* shape,
+ * until the timing is done.  Errors: RCP_ERR_INVALID_ARG as
+ * rcp_batch_decompose, RCP_ERR_HIP for a failed launch or event call. */
+rcp_status rcp_batch_autotune(rcp_batch batch, const float* const* X, float* const* const* A,
+                              float* const* lambda, rcp_als_info* info, int32_t* shape,
                               double* best_ms);
 rcp_status rcp_batch_destroy(rcp_batch batch);
 

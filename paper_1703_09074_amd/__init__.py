@@ -135,18 +135,42 @@ class Plan:
                                       ctypes.c_void_p(out.data_ptr())), "rcp_norm2")
         return out
 
-    def als(self, core, normX2=None):
-        """CP-ALS on the core (Algorithm 2 steps 2-11): (factors, lambda, info buffer)."""
+    def als(self, core, normX2=None, init: Optional[List] = None):
+        """CP-ALS on the core (Algorithm 2 steps 2-11): (factors, lambda, info buffer).
+
+        init: starting factors (l_n x R float32 CUDA tensors, one per mode; the
+        first is not read) instead of the eigenvector start (warm start)."""
         _f32(core, "core")
+        if list(core.shape) != self.l:
+            raise ValueError(f"core has shape {list(core.shape)}, plan expects {self.l}")
         At = [self._empty((self.l[n], self.R)) for n in range(self.N)]
+        if init is not None:
+            if len(init) != self.N:
+                raise ValueError(f"init needs {self.N} factors")
+            for n in range(1, self.N):
+                _f32(init[n], f"init[{n}]")
+                if list(init[n].shape) != [self.l[n], self.R]:
+                    raise ValueError(f"init[{n}] has shape {list(init[n].shape)}, "
+                                     f"expected {[self.l[n], self.R]}")
+                At[n].copy_(init[n])
         lam = self._empty((self.R,))
         info = self._info_buffer()
+        if normX2 is not None and (normX2.dtype != _torch().float64 or not normX2.is_cuda):
+            raise TypeError("normX2 must be a float64 CUDA tensor")
         nptr = ctypes.c_void_p(normX2.data_ptr()) if normX2 is not None else ctypes.c_void_p(0)
         _lib.check(self.lib.rcp_als(self.handle, ctypes.c_void_p(core.data_ptr()),
                                     _lib.ptr_array([a.data_ptr() for a in At]),
                                     ctypes.c_void_p(lam.data_ptr()), nptr,
-                                    ctypes.c_void_p(info.data_ptr())), "rcp_als")
+                                    ctypes.c_void_p(info.data_ptr()),
+                                    1 if init is not None else 0), "rcp_als")
         return At, lam, info
+
+    def read_status(self) -> int:
+        """The plan's device status word (RCP_INFO_* bits raised since the last
+        read), cleared by the read; waits for the plan's stream."""
+        v = ctypes.c_int32(0)
+        _lib.check(self.lib.rcp_read_status(self.handle, ctypes.byref(v)), "rcp_read_status")
+        return int(v.value)
 
     def expand(self, Q: List, At: List, lam):
         """A_n = Q_n Ã_n and the final renormalisation (eq. qbs, Algorithm 2 steps 12-13)."""
@@ -161,6 +185,22 @@ class Plan:
 
     def decompose_into(self, X, A: List, lam, info) -> None:
         """The whole path into preallocated outputs (no allocation)."""
+        _f32(X, "X")
+        if list(X.shape) != self.dims:
+            raise ValueError(f"X has shape {list(X.shape)}, plan expects {self.dims}")
+        if len(A) != self.N:
+            raise ValueError(f"expected {self.N} factor outputs, got {len(A)}")
+        for n, a in enumerate(A):
+            _f32(a, f"A[{n}]")
+            if list(a.shape) != [self.dims[n], self.R]:
+                raise ValueError(f"A[{n}] has shape {list(a.shape)}, expected {[self.dims[n], self.R]}")
+        _f32(lam, "lam")
+        if lam.numel() < self.R:
+            raise ValueError("lam is too small")
+        if not info.is_cuda or not info.is_contiguous() or \
+                info.numel() * info.element_size() < ctypes.sizeof(_lib.AlsInfo):
+            raise ValueError("info must be a contiguous CUDA buffer of at least "
+                             f"{ctypes.sizeof(_lib.AlsInfo)} bytes")
         _lib.check(self.lib.rcp_decompose(self.handle, ctypes.c_void_p(X.data_ptr()),
                                           _lib.ptr_array([a.data_ptr() for a in A]),
                                           ctypes.c_void_p(lam.data_ptr()),
@@ -225,10 +265,19 @@ class Plan:
                                             ctypes.c_void_p(out.data_ptr())), "rcp_debug_omega")
         return out
 
+    def philox_words(self, mode: int, row0: int, nrows: int, ngroups: int):
+        """Raw Philox4x32-10 words (nrows x ngroups x 4, int32 bit patterns of
+        the uint32 words) behind rows [row0, row0 + nrows) of Omega_mode."""
+        out = self._empty((nrows, ngroups, 4), dtype=_torch().int32)
+        _lib.check(self.lib.rcp_debug_philox(self.handle, int(mode), int(row0), int(nrows),
+                                             int(ngroups), ctypes.c_void_p(out.data_ptr())),
+                   "rcp_debug_philox")
+        return out
+
 
 class Batch:
-    """Independent problems decomposed as one unit (rcp_batch_*): the outputs
-    (factors, lambda, info) are allocated here and bound at creation; the
+    """Independent problems decomposed as one unit (rcp_batch_*).  The outputs
+    (factors, lambda, info) are allocated here and passed on every call; the
     batch runs on the current HIP stream of ``device`` at creation (a
     non-default stream records the work in a HIP graph on the first call).
 
@@ -262,15 +311,9 @@ class Batch:
         self.lam = [torch.empty((k,), dtype=torch.float32, device=self.device) for k in self.k]
         self.info = torch.zeros(self.count * ctypes.sizeof(_lib.AlsInfo), dtype=torch.uint8,
                                 device=self.device)
-        rows = [_lib.ptr_array([a.data_ptr() for a in As]) for As in self.A]
-        self._rows = rows
-        A_arg = (ctypes.POINTER(ctypes.c_void_p) * self.count)(
-            *[ctypes.cast(r, ctypes.POINTER(ctypes.c_void_p)) for r in rows])
-        lam_arg = _lib.ptr_array([t.data_ptr() for t in self.lam])
         self.stream = _stream_handle(torch, self.device)
         handle = ctypes.c_void_p(0)
-        _lib.check(self.lib.rcp_batch_init(ctypes.byref(handle), arr, self.count, A_arg, lam_arg,
-                                           ctypes.c_void_p(self.info.data_ptr()),
+        _lib.check(self.lib.rcp_batch_init(ctypes.byref(handle), arr, self.count,
                                            ctypes.c_void_p(self.workspace.data_ptr()),
                                            ctypes.c_size_t(self.workspace.numel()), self.stream),
                    "rcp_batch_init")
@@ -282,9 +325,7 @@ class Batch:
             self.lib.rcp_batch_destroy(h)
             self.handle = None
 
-    def decompose(self, Xs) -> None:
-        """Enqueue the decomposition of every tensor (float32 CUDA, shapes as
-        given at creation); results land in .A, .lam and .info."""
+    def _io(self, Xs):
         if len(Xs) != self.count:
             raise ValueError(f"expected {self.count} tensors, got {len(Xs)}")
         for X, dims in zip(Xs, self.dims):
@@ -292,27 +333,38 @@ class Batch:
             if list(X.shape) != dims:
                 raise ValueError(f"tensor of shape {list(X.shape)} where {dims} was planned")
         self._X = list(Xs)
-        _lib.check(self.lib.rcp_batch_decompose(self.handle,
-                                                _lib.ptr_array([X.data_ptr() for X in Xs])),
+        rows = [_lib.ptr_array([a.data_ptr() for a in As]) for As in self.A]
+        self._rows = rows
+        A_arg = (ctypes.POINTER(ctypes.c_void_p) * self.count)(
+            *[ctypes.cast(r, ctypes.POINTER(ctypes.c_void_p)) for r in rows])
+        lam_arg = _lib.ptr_array([t.data_ptr() for t in self.lam])
+        return (_lib.ptr_array([X.data_ptr() for X in Xs]), A_arg, lam_arg,
+                ctypes.c_void_p(self.info.data_ptr()))
+
+    def decompose(self, Xs) -> None:
+        """Enqueue the decomposition of every tensor (float32 CUDA, shapes as
+        given at creation); results land in .A, .lam and .info."""
+        X_arg, A_arg, lam_arg, info_arg = self._io(Xs)
+        _lib.check(self.lib.rcp_batch_decompose(self.handle, X_arg, A_arg, lam_arg, info_arg),
                    "rcp_batch_decompose")
 
     def autotune(self, Xs) -> dict:
         """Time the batch over candidate launch shapes (rcp_batch_autotune)
         and keep the fastest; blocks.  Returns the chosen shape and its time."""
-        if len(Xs) != self.count:
-            raise ValueError(f"expected {self.count} tensors, got {len(Xs)}")
-        for X, dims in zip(Xs, self.dims):
-            _f32(X, "X")
-            if list(X.shape) != dims:
-                raise ValueError(f"tensor of shape {list(X.shape)} where {dims} was planned")
-        self._X = list(Xs)
+        X_arg, A_arg, lam_arg, info_arg = self._io(Xs)
         shape = (ctypes.c_int32 * 3)()
         ms = ctypes.c_double(0.0)
-        _lib.check(self.lib.rcp_batch_autotune(self.handle,
-                                               _lib.ptr_array([X.data_ptr() for X in Xs]),
+        _lib.check(self.lib.rcp_batch_autotune(self.handle, X_arg, A_arg, lam_arg, info_arg,
                                                shape, ctypes.byref(ms)), "rcp_batch_autotune")
         return {"streams": shape[0], "workgroups": shape[1], "row_block_rows": 64 * shape[2],
                 "ms_per_batch": ms.value}
+
+    def read_status(self, index: int) -> int:
+        """Status word of problem ``index`` (rcp_batch_read_status); blocks."""
+        v = ctypes.c_int32(0)
+        _lib.check(self.lib.rcp_batch_read_status(self.handle, int(index), ctypes.byref(v)),
+                   "rcp_batch_read_status")
+        return int(v.value)
 
     def read_info(self):
         raw = bytes(self.info.cpu().numpy().tobytes())

@@ -22,6 +22,11 @@ RCP_ERR_HIP = 3
 RCP_ERR_NUMERIC = 4
 RCP_ERR_UNSUPPORTED = 5
 
+RCP_INFO_PINV_FALLBACK = 1
+RCP_INFO_NONFINITE = 2
+RCP_INFO_EIG_NOT_CONVERGED = 4
+RCP_INFO_QR_HOUSEHOLDER = 8
+
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 KERNEL_CLASSES = ["sketch", "power", "contract_in", "contract_out", "reduce", "qr", "als",
                   "expand", "other"]
@@ -66,23 +71,27 @@ SIGNATURES = {
     "rcp_sketch": (_st, [_vp, _vp, _i64p, ctypes.c_int32, _vp]),
     "rcp_compress": (_st, [_vp, _vp, _i64p, ctypes.c_int32, _vp, _vp]),
     "rcp_norm2": (_st, [_vp, _vp, ctypes.c_int64, _vp]),
-    "rcp_als": (_st, [_vp, _vp, ctypes.POINTER(_vp), _vp, _vp, _vp]),
+    "rcp_als": (_st, [_vp, _vp, ctypes.POINTER(_vp), _vp, _vp, _vp, ctypes.c_int32]),
+    "rcp_read_status": (_st, [_vp, ctypes.POINTER(ctypes.c_int32)]),
     "rcp_expand": (_st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, ctypes.POINTER(_vp), _vp]),
     "rcp_decompose": (_st, [_vp, _vp, ctypes.POINTER(_vp), _vp, _vp]),
     "rcp_get_bases": (_st, [_vp, ctypes.POINTER(_vp)]),
     "rcp_get_core": (_st, [_vp, ctypes.POINTER(_vp), _i64p]),
     "rcp_debug_omega": (_st, [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _vp]),
+    "rcp_debug_philox": (_st, [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _vp]),
     "rcp_profile": (_st, [_vp, ctypes.c_int32]),
     "rcp_profile_read": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_double)]),
     "rcp_batch_workspace_size": (_st, [ctypes.POINTER(Problem), ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_size_t)]),
-    "rcp_batch_init": (_st, [ctypes.POINTER(_vp), ctypes.POINTER(Problem), ctypes.c_int32,
-                             ctypes.POINTER(ctypes.POINTER(_vp)), ctypes.POINTER(_vp), _vp, _vp,
+    "rcp_batch_init": (_st, [ctypes.POINTER(_vp), ctypes.POINTER(Problem), ctypes.c_int32, _vp,
                              ctypes.c_size_t, _vp]),
-    "rcp_batch_decompose": (_st, [_vp, ctypes.POINTER(_vp)]),
-    "rcp_batch_autotune": (_st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int32),
+    "rcp_batch_decompose": (_st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.POINTER(_vp)),
+                                  ctypes.POINTER(_vp), _vp]),
+    "rcp_batch_read_status": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "rcp_batch_autotune": (_st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.POINTER(_vp)),
+                                 ctypes.POINTER(_vp), _vp, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_double)]),
     "rcp_batch_destroy": (_st, [_vp]),
     "rcp_status_string": (ctypes.c_char_p, [_st]),

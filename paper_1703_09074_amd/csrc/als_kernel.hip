@@ -23,24 +23,6 @@
 
 namespace rcp {
 
-#ifdef RCP_ALS_TIMING
-__device__ unsigned long long g_als_stamps[64];
-#define ALS_STAMP(slot)                                                                    \
-    do {                                                                                   \
-        __syncthreads();                                                                   \
-        if (threadIdx.x == 0 && it_dbg < 3) g_als_stamps[it_dbg * 16 + (slot)] = wall_clock64(); \
-    } while (0)
-__device__ unsigned long long g_als_ns[64];
-#define ALS_SUB(slot)                                                                      \
-    do {                                                                                   \
-        __syncthreads();                                                                   \
-        if (threadIdx.x == 0 && n == 0 && dbg_it < 3)                                      \
-            g_als_stamps[dbg_it * 16 + (slot)] = wall_clock64();                           \
-    } while (0)
-#else
-#define ALS_STAMP(slot) do {} while (0)
-#define ALS_SUB(slot) do {} while (0)
-#endif
 
 constexpr int ANT = 512;
 constexpr int ANW = ANT / 64;
@@ -108,13 +90,6 @@ __device__ __forceinline__ bool jacobi_eig(double* A, double* V, int n, double* 
             }
         off = block_sum(off, red);
         dia = block_sum(dia, red);
-#ifdef RCP_ALS_TIMING
-        if (tid == 0) {
-            const unsigned long long slot = atomicAdd(&g_als_ns[47], 1ull);
-            if (slot < 16) g_als_ns[48 + slot] = (unsigned long long)sweep * 1000000ull +
-                                                 (unsigned long long)fmin(999999.0, -10.0 * log10(off / dia + 1e-300));
-        }
-#endif
         if (off <= 1e-30 * dia || off == 0.0) { converged = true; break; }
         for (int round = 0; round < np - 1; ++round) {
             if (tid < half) {
@@ -258,9 +233,6 @@ __device__ __forceinline__ bool eig_init(const AlsCtx& c, const float* Bg, int n
         E[i2 * kEigLd + i] = s;
     }
     __syncthreads();
-#ifdef RCP_ALS_TIMING
-    if (tid == 0 && n <= 2) g_als_stamps[16 * (n - 1) + 1] = wall_clock64();
-#endif
     return eig_leading(c, n, E, V);
 }
 
@@ -288,8 +260,7 @@ __device__ __forceinline__ bool eig_init(const AlsCtx& c, const float* Bg, int n
 template <int NN>
 __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, const int* st,
                                        const float* ones, float* P, double* M, double* Xt,
-                                       int ldx, int dbg_it) {
-    (void)dbg_it;
+                                       int ldx) {
     constexpr int D = NN - 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
@@ -463,7 +434,6 @@ __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, c
         }
     }
     __syncthreads();
-    ALS_SUB(13);
     if (keep_blk >= 0) {
         const int ib = keep_blk / ncb, cb = keep_blk - (keep_blk / ncb) * ncb;
         const int col = cb * 16 + lr;
@@ -894,14 +864,11 @@ __device__ __forceinline__ void unit_factor_gram(const double* Xt, int ldx, int 
 // RCP_INFO_* bits.
 __device__ __forceinline__ int solve_update(const AlsCtx& c, int n, double* G, const double* M,
                                             double* Aug, int ldx, int Rp, double* pb, double* E,
-                                            double* Ev, double* lam, int dbg_it) {
-    (void)dbg_it;
+                                            double* Ev, double* lam) {
     const int tid = threadIdx.x, R = c.R, ln = c.l[n];
     double* Xt = Aug + Rp;
     int status = 0;
-    ALS_SUB(8);
     const int ok = gj_solve(Aug, ldx, R, Rp, Rp + ln, kPivotRtol, pb);
-    ALS_SUB(9);
     if (!ok) {
         // Moore-Penrose pseudo-inverse through the eigen-decomposition
         status |= RCP_INFO_PINV_FALLBACK;
@@ -936,7 +903,6 @@ __device__ __forceinline__ int solve_update(const AlsCtx& c, int n, double* G, c
     }
     unit_factor_gram(Xt, ldx, ln, R, c.fac(n), G + n * R * R, lam);
     __syncthreads();
-    ALS_SUB(10);
     return status;
 }
 
@@ -1005,21 +971,15 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
     const double normX2 = (a.normX2 != nullptr) ? *a.normX2 : normB2;
 
     int status = 0;
-#ifdef RCP_ALS_TIMING
-    {
-        const int it_dbg = 0;
-        ALS_STAMP(14);
-    }
-#endif
     for (int n = 1; n < N; ++n) {
-        if (!eig_init(c, a.B, n, E, Ev)) status |= RCP_INFO_EIG_NOT_CONVERGED;
-        gram_mfma(c.fac(n), c.l[n], R, G + n * R * R);   // Gram of the unit-norm eigenvectors
-#ifdef RCP_ALS_TIMING
-        if (n == 1) {
-            const int it_dbg = 0;
-            ALS_STAMP(11);
+        if (a.warm) {
+            // the caller's starting factors (warm start)
+            for (int e = tid; e < c.l[n] * R; e += ANT) c.fac(n)[e] = a.At[n][e];
+            __syncthreads();
+        } else if (!eig_init(c, a.B, n, E, Ev)) {
+            status |= RCP_INFO_EIG_NOT_CONVERGED;
         }
-#endif
+        gram_mfma(c.fac(n), c.l[n], R, G + n * R * R);
     }
     __syncthreads();
     if (B_IN_LDS)
@@ -1030,25 +990,12 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
     double rho = 0.0, rho_prev = 0.0;
     int it;
     for (it = 1; it <= a.max_iters; ++it) {
-#ifdef RCP_ALS_TIMING
-        const int it_dbg = it - 1;
-#else
-        const int it_dbg = 0;
-#endif
-        ALS_STAMP(0);
         for (int n = 0; n < N; ++n) {
             hadamard_grams(c, n, G, Aug, ldx, Rp, c.l[n]);
-            {
-                const int dbg_it = it_dbg;
-                (void)dbg_it;
-                ALS_SUB(12);
-            }
-            mttkrp<NN>(c, n, Bs, sst, ones, P, M, Aug + Rp, ldx, it_dbg);
+            mttkrp<NN>(c, n, Bs, sst, ones, P, M, Aug + Rp, ldx);
             __syncthreads();
-            ALS_STAMP(2 + 2 * n);
             status |= solve_update(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs,
-                                   (n == N - 1) ? lam : lam_tmp, it_dbg);
-            ALS_STAMP(3 + 2 * n);
+                                   (n == N - 1) ? lam : lam_tmp);
         }
         // ---- fit (Section 3.3): rho = 1 - (||X||^2 + ||Xhat||^2 - 2 <Xhat, X>) / ||X||^2,
         // needed by the stopping rule (tol > 0), after the last sweep, and to
@@ -1073,7 +1020,6 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
         const double model = block_sum(pm, red);
         const double err2 = normX2 - 2.0 * inner + model;
         rho = (normX2 > 0.0) ? 1.0 - err2 / normX2 : 0.0;
-        ALS_STAMP(15);
         if (!isfinite(rho)) { status |= RCP_INFO_NONFINITE; break; }
         if (a.tol > 0.0 && it >= 2 && fabs(rho - rho_prev) < a.tol) break;
         rho_prev = rho;
@@ -1091,6 +1037,7 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
         a.info->rho = rho;
         a.info->rel_err = sqrt(fmax(0.0, 1.0 - rho));
         a.info->normX2 = normX2;
+        if (a.status_word != nullptr && status != 0) *a.status_word |= status;
     }
 }
 
@@ -1218,7 +1165,7 @@ __global__ __launch_bounds__(ANT) void k_als_wide_step(AlsArgs a, int n) {
         Aug[r * ldx + Rp + i] = v;
     }
     __syncthreads();
-    int status = solve_update(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs, lam, 0);
+    int status = solve_update(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs, lam);
     for (int e = tid; e < ln * R; e += ANT) a.At[n][e] = c.fac(n)[e];
     if (n < N - 1) {
         if (tid == 0 && status != 0) fl[2] |= status;
@@ -1279,7 +1226,33 @@ __global__ __launch_bounds__(ANT) void k_als_wide_step(AlsArgs a, int n) {
         a.info->rho = rho;
         a.info->rel_err = sqrt(fmax(0.0, 1.0 - rho));
         a.info->normX2 = normX2;
+        if (a.status_word != nullptr && st != 0) *a.status_word |= st;
         if (stop) fl[0] = 1;
+    }
+}
+
+// Warm start of the grid-wide form: the Grams of the caller's factors
+// At[1..N-1] (left in place: the mode products read them there) and a fresh
+// sweep state.
+__global__ __launch_bounds__(ANT) void k_als_wide_warm(AlsArgs a) {
+    extern __shared__ __align__(16) unsigned char als_smem[];
+    float* F = (float*)als_smem;
+    const int tid = threadIdx.x;
+    const int N = a.N, R = a.R;
+    double* G = a.state + kStG;
+    for (int n = 1; n < N; ++n) {
+        const int ln = a.l[n];
+        for (int e = tid; e < ln * R; e += ANT) F[e] = a.At[n][e];
+        __syncthreads();
+        gram_mfma(F, ln, R, G + n * R * R);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int* fl = (int*)a.state;
+        fl[0] = 0;
+        fl[1] = 0;
+        fl[2] = 0;
+        a.state[2] = 0.0;
     }
 }
 
@@ -1331,6 +1304,15 @@ hipError_t launch_als_wide_init(const AlsArgs& a, int n, hipStream_t s) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kAlsLds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_als_wide_init, dim3(1), dim3(ANT), smem, s, a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_als_wide_warm(const AlsArgs& a, hipStream_t s) {
+    if (a.state == nullptr) return hipErrorInvalidValue;
+    int lmax = 0;
+    for (int m = 0; m < a.N; ++m) lmax = lmax > a.l[m] ? lmax : a.l[m];
+    const size_t smem = (size_t)lmax * a.R * sizeof(float);
+    hipLaunchKernelGGL(k_als_wide_warm, dim3(1), dim3(ANT), smem, s, a);
     return hipGetLastError();
 }
 
@@ -1435,10 +1417,3 @@ hipError_t launch_als_batch(const AlsArgs* dargs, const AlsArgs* hargs, int coun
 
 }  // namespace rcp
 
-#ifdef RCP_ALS_TIMING
-extern "C" int rcp_debug_als_stamps(unsigned long long* host_out) {
-    int e = (int)hipMemcpyFromSymbol(host_out, HIP_SYMBOL(rcp::g_als_stamps), sizeof(rcp::g_als_stamps));
-    if (e) return e;
-    return (int)hipMemcpyFromSymbol(host_out + 64, HIP_SYMBOL(rcp::g_als_ns), sizeof(rcp::g_als_ns));
-}
-#endif

@@ -391,7 +391,7 @@ __device__ __forceinline__ void householder_q(double* A, int lda, int m, int n, 
 
 template <bool USE_LDS, int NB>
 __global__ __launch_bounds__(qr_threads<NB>()) void k_qr(double* Yg, int m, int n, int ldy, float* Qpad, int ldq,
-                                            float* Qout, int second_pass) {
+                                            float* Qout, int second_pass, int* status) {
     extern __shared__ double qsm[];
     __shared__ double taus[64];
     __shared__ double betas[64];
@@ -475,6 +475,7 @@ __global__ __launch_bounds__(qr_threads<NB>()) void k_qr(double* Yg, int m, int 
             }
             if (!flag) {
                 householder_q(A, lda, m, n, scratch, taus, betas, red);
+                if (tid == 0 && status != nullptr) *status |= RCP_INFO_QR_HOUSEHOLDER;
                 break;
             }
             apply_upper<NB>(A, lda, m, n, X);
@@ -516,36 +517,36 @@ static size_t qr_lds_bytes(int64_t m, int n) {
 
 template <bool L, int NB>
 static hipError_t launch_qr_t(double* Y, int m, int n, int ldy, float* Qpad, int ldq, float* Qout,
-                              int sp, size_t lds, hipStream_t s) {
+                              int sp, int* status, size_t lds, hipStream_t s) {
     hipError_t e = hipFuncSetAttribute((const void*)k_qr<L, NB>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_qr<L, NB>), dim3(1), dim3(qr_threads<NB>()), lds, s, Y, m, n, ldy, Qpad, ldq,
-                       Qout, sp);
+                       Qout, sp, status);
     return hipGetLastError();
 }
 
 template <bool L>
 static hipError_t launch_qr_l(double* Y, int m, int n, int ldy, float* Qpad, int ldq, float* Qout,
-                              int sp, size_t lds, hipStream_t s) {
+                              int sp, int* status, size_t lds, hipStream_t s) {
     switch ((n + 15) >> 4) {
-        case 1: return launch_qr_t<L, 1>(Y, m, n, ldy, Qpad, ldq, Qout, sp, lds, s);
-        case 2: return launch_qr_t<L, 2>(Y, m, n, ldy, Qpad, ldq, Qout, sp, lds, s);
-        case 3: return launch_qr_t<L, 3>(Y, m, n, ldy, Qpad, ldq, Qout, sp, lds, s);
-        default: return launch_qr_t<L, 4>(Y, m, n, ldy, Qpad, ldq, Qout, sp, lds, s);
+        case 1: return launch_qr_t<L, 1>(Y, m, n, ldy, Qpad, ldq, Qout, sp, status, lds, s);
+        case 2: return launch_qr_t<L, 2>(Y, m, n, ldy, Qpad, ldq, Qout, sp, status, lds, s);
+        case 3: return launch_qr_t<L, 3>(Y, m, n, ldy, Qpad, ldq, Qout, sp, status, lds, s);
+        default: return launch_qr_t<L, 4>(Y, m, n, ldy, Qpad, ldq, Qout, sp, status, lds, s);
     }
 }
 
 hipError_t launch_qr(double* Y, int64_t m, int n, int ldy, float* Qpad, int ldq, float* Qout,
-                     bool final_basis, hipStream_t s) {
+                     bool final_basis, int* status, hipStream_t s) {
     const int np = (n + 15) & ~15;
     if (n < 1 || n > 64 || ldy < np || ldq < n || m < n || m > ((int64_t)1 << 24)) return hipErrorInvalidValue;
     const int sp = final_basis ? 1 : 0;
     const size_t lds = qr_lds_bytes(m, n);
     if (lds <= kQrLds - 4096)
-        return launch_qr_l<true>(Y, (int)m, n, ldy, Qpad, ldq, Qout, sp, lds, s);
+        return launch_qr_l<true>(Y, (int)m, n, ldy, Qpad, ldq, Qout, sp, status, lds, s);
     const size_t small = (2 * (size_t)np * np + 2 * kQrScratch) * sizeof(double);
-    return launch_qr_l<false>(Y, (int)m, n, ldy, Qpad, ldq, Qout, sp, small, s);
+    return launch_qr_l<false>(Y, (int)m, n, ldy, Qpad, ldq, Qout, sp, status, small, s);
 }
 
 }  // namespace rcp

@@ -31,7 +31,7 @@ struct Layout {
     int64_t Imax;
     int LPmax;
     // offsets (bytes)
-    size_t part, red1, y64, qt, sq, norm, qb[RCP_MAX_NDIM], tb[2], zbuf, als, alsst,
+    size_t part, red1, y64, qt, sq, norm, status, qb[RCP_MAX_NDIM], tb[2], zbuf, als, alsst,
         at[RCP_MAX_NDIM], lam, raw, total;
     size_t part_elems, tb_elems[2], zbuf_elems, als_doubles;
     int64_t core_dims[RCP_MAX_NDIM];
@@ -112,6 +112,7 @@ Layout make_layout(const rcp_problem* p) {
     for (int n = 0; n < L.N; ++n) nib = std::max(nib, contract_out_row_blocks(L.dims[n], 1));
     L.sq = take((size_t)kPmax * nib * sizeof(double));
     L.norm = take(64 * sizeof(double));
+    L.status = take(sizeof(int32_t));
     for (int n = 0; n < L.N; ++n) L.qb[n] = take((size_t)L.dims[n] * L.l[n] * sizeof(float));
     L.tb[0] = take(L.tb_elems[0] * sizeof(float));
     L.tb[1] = take(L.tb_elems[1] * sizeof(float));
@@ -174,6 +175,7 @@ struct rcp_plan_t {
     Profiler prof;
     template <class T>
     T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+    int* status_word() const { return at<int>(L.status); }
 };
 
 namespace {
@@ -265,7 +267,7 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
     const bool fused = power_fused_fits(I, l, pl->smem_limit);
     for (int it = 0; it < pl->prob.q; ++it) {
         RCP_TRY(timed(pl, RCP_KERNEL_QR, qr_bytes, 2.0 * qr_flops,
-                      [&] { return launch_qr(Y, I, l, LP, Qt, LP, nullptr, false, pl->stream); }));
+                      [&] { return launch_qr(Y, I, l, LP, Qt, LP, nullptr, false, pl->status_word(), pl->stream); }));
         if (fused) {
             RCP_TRY(timed(pl, RCP_KERNEL_POWER, 4.0 * S + 4.0 * I * l, 4.0 * S * l,
                           [&] { return launch_power_fused(g, l, Qt, part, P, pl->stream, pl->prob.precision); }));
@@ -282,7 +284,7 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
         if (st != RCP_OK) return st;
     }
     RCP_TRY(timed(pl, RCP_KERNEL_QR, qr_bytes, 3.0 * qr_flops,
-                  [&] { return launch_qr(Y, I, l, LP, Qt, LP, Q, true, pl->stream); }));
+                  [&] { return launch_qr(Y, I, l, LP, Qt, LP, Q, true, pl->status_word(), pl->stream); }));
     return RCP_OK;
 }
 
@@ -327,6 +329,7 @@ hipError_t als_wide(rcp_plan_t* pl, AlsArgs a) {
         if (e != hipSuccess) return e;
         a.normX2 = state + 3;
     }
+    if (a.warm) return launch_als_wide_warm(a, pl->stream);
     // Algorithm 2 step 2: Grams B_(n) B_(n)^T as Y = T (T^T I) over the GPU
     for (int n = 1; n < N; ++n) {
         const StreamGeom g = make_geom(a.B, cd, N, n);
@@ -363,7 +366,7 @@ hipError_t als_wide(rcp_plan_t* pl, AlsArgs a) {
 }
 
 rcp_status als_impl(rcp_plan_t* pl, const float* core, float* const* At, float* lambda,
-                    const double* normX2, rcp_als_info* info) {
+                    const double* normX2, rcp_als_info* info, int warm) {
     const Layout& L = pl->L;
     AlsArgs a{};
     a.B = core;
@@ -371,10 +374,12 @@ rcp_status als_impl(rcp_plan_t* pl, const float* core, float* const* At, float* 
     for (int n = 0; n < L.N; ++n) { a.l[n] = L.l[n]; a.At[n] = At[n]; }
     a.R = L.R;
     a.max_iters = pl->prob.max_iters;
+    a.warm = warm;
     a.tol = pl->prob.tol;
     a.normX2 = normX2;
     a.lambda = lambda;
     a.info = info;
+    a.status_word = pl->status_word();
     int64_t S = 1;
     for (int n = 0; n < L.N; ++n) S *= L.l[n];
     const int R = L.R;
@@ -462,7 +467,22 @@ rcp_status rcp_init(rcp_plan* plan, const rcp_problem* prob, void* workspace,
     pl->ws_bytes = workspace_bytes;
     pl->P = std::max(1, std::min(kPmax, cus));
     pl->smem_limit = kLdsBytes;
+    if (hipMemsetAsync(pl->status_word(), 0, sizeof(int32_t), pl->stream) != hipSuccess) {
+        delete pl;
+        return RCP_ERR_HIP;
+    }
     *plan = pl;
+    return RCP_OK;
+}
+
+rcp_status rcp_read_status(rcp_plan plan, int32_t* status) {
+    if (plan == nullptr || status == nullptr) return RCP_ERR_INVALID_ARG;
+    int32_t v = 0;
+    RCP_TRY(hipMemcpyAsync(&v, plan->status_word(), sizeof(int32_t), hipMemcpyDeviceToHost,
+                           plan->stream));
+    RCP_TRY(hipMemsetAsync(plan->status_word(), 0, sizeof(int32_t), plan->stream));
+    RCP_TRY(hipStreamSynchronize(plan->stream));
+    *status = v;
     return RCP_OK;
 }
 
@@ -548,14 +568,14 @@ rcp_status rcp_norm2(rcp_plan plan, const float* X, int64_t count, double* out) 
 }
 
 rcp_status rcp_als(rcp_plan plan, const float* core, float* const* At, float* lambda,
-                   const double* normX2, rcp_als_info* info) {
+                   const double* normX2, rcp_als_info* info, int32_t use_given_init) {
     if (plan == nullptr || core == nullptr || At == nullptr || lambda == nullptr || info == nullptr)
         return RCP_ERR_INVALID_ARG;
     for (int n = 0; n < plan->L.N; ++n)
         if (At[n] == nullptr || !aligned(At[n], 4)) return RCP_ERR_INVALID_ARG;
     if (!aligned(core, 4) || !aligned(info, 8) || (normX2 && !aligned(normX2, 8)))
         return RCP_ERR_INVALID_ARG;
-    return als_impl(plan, core, At, lambda, normX2, info);
+    return als_impl(plan, core, At, lambda, normX2, info, use_given_init != 0 ? 1 : 0);
 }
 
 rcp_status rcp_expand(rcp_plan plan, const float* const* Q, const float* const* At,
@@ -623,6 +643,7 @@ AlsArgs core_als_args(rcp_plan_t* plan, const float* core, rcp_als_info* info) {
     a.normX2 = plan->at<double>(L.norm);
     a.lambda = plan->at<float>(L.lam);
     a.info = info;
+    a.status_word = plan->status_word();
     a.Ebuf = plan->at<double>(L.als);
     return a;
 }
@@ -637,7 +658,7 @@ ExpandArgs core_expand_args(rcp_plan_t* plan, float* const* A, float* lambda) {
         e.l[n] = L.l[n];
         e.Q[n] = plan->at<float>(L.qb[n]);
         e.At[n] = plan->at<float>(L.at[n]);
-        e.A[n] = A[n];
+        e.A[n] = A != nullptr ? A[n] : nullptr;
     }
     e.lambda_in = plan->at<float>(L.lam);
     e.lambda_out = lambda;
@@ -662,7 +683,7 @@ rcp_status rcp_decompose(rcp_plan plan, const float* X, float* const* A, float* 
     float* At[RCP_MAX_NDIM];
     for (int n = 0; n < N; ++n) At[n] = plan->at<float>(L.at[n]);
     float* lam = plan->at<float>(L.lam);
-    st = als_impl(plan, core, At, lam, plan->at<double>(L.norm), info);
+    st = als_impl(plan, core, At, lam, plan->at<double>(L.norm), info, 0);
     if (st != RCP_OK) return st;
     const float* Qc[RCP_MAX_NDIM];
     const float* Atc[RCP_MAX_NDIM];
@@ -682,10 +703,13 @@ struct rcp_batch_t {
     hipEvent_t fork = nullptr;
     hipEvent_t join[kBatchStreams] = {};
     std::vector<rcp_plan_t*> plans;
-    std::vector<AlsArgs> h_als;
+    std::vector<AlsArgs> h_als;           // per-problem arguments, outputs as last bound
     std::vector<ExpandArgs> h_exp;
-    AlsArgs* d_als = nullptr;
+    AlsArgs* pin_als = nullptr;           // pinned staging of the argument tables
+    ExpandArgs* pin_exp = nullptr;
+    AlsArgs* d_als = nullptr;             // device argument tables (in the workspace)
     ExpandArgs* d_exp = nullptr;
+    bool bound = false;                   // output pointers uploaded at least once
     std::vector<const float*> X;          // inputs of the captured graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -728,7 +752,8 @@ rcp_status batch_layout(const rcp_problem* probs, int32_t count, BatchLayout* ou
 // The compressions of the problems go round-robin to the side streams (forked
 // from and joined back into the batch stream by events, so a recorded graph
 // gets independent branches); CP-ALS and the back-projection of all problems
-// then run as one launch each on the batch stream.
+// then run as one launch each on the batch stream, reading their outputs from
+// the device argument tables.
 rcp_status batch_enqueue(rcp_batch_t* b, const float* const* X) {
     RCP_TRY(hipEventRecord(b->fork, b->stream));
     for (int s = 0; s < kBatchStreams; ++s) RCP_TRY(hipStreamWaitEvent(b->side[s], b->fork, 0));
@@ -764,71 +789,47 @@ void batch_drop_graph(rcp_batch_t* b) {
     b->graph = nullptr;
 }
 
-}  // namespace
-
-rcp_status rcp_batch_workspace_size(const rcp_problem* probs, int32_t count, size_t* bytes) {
-    if (bytes == nullptr) return RCP_ERR_INVALID_ARG;
-    BatchLayout B;
-    rcp_status st = batch_layout(probs, count, &B);
-    if (st != RCP_OK) return st;
-    *bytes = B.total;
-    return RCP_OK;
-}
-
-rcp_status rcp_batch_init(rcp_batch* batch, const rcp_problem* probs, int32_t count,
-                          float* const* const* A, float* const* lambda, rcp_als_info* info,
-                          void* workspace, size_t workspace_bytes, void* hip_stream) {
-    if (batch == nullptr) return RCP_ERR_INVALID_ARG;
-    *batch = nullptr;
-    BatchLayout B;
-    rcp_status st = batch_layout(probs, count, &B);
-    if (st != RCP_OK) return st;
-    if (A == nullptr || lambda == nullptr || info == nullptr || !aligned(info, 8))
+rcp_status batch_check_io(const rcp_batch_t* b, const float* const* X, float* const* const* A,
+                          float* const* lambda, const rcp_als_info* info) {
+    if (X == nullptr || A == nullptr || lambda == nullptr || info == nullptr || !aligned(info, 8))
         return RCP_ERR_INVALID_ARG;
-    for (int i = 0; i < count; ++i) {
-        if (A[i] == nullptr || lambda[i] == nullptr) return RCP_ERR_INVALID_ARG;
-        for (int n = 0; n < probs[i].ndim; ++n)
+    for (int i = 0; i < b->count; ++i) {
+        if (X[i] == nullptr || !aligned(X[i], 4)) return RCP_ERR_INVALID_ARG;
+        if (A[i] == nullptr || lambda[i] == nullptr || !aligned(lambda[i], 4)) return RCP_ERR_INVALID_ARG;
+        for (int n = 0; n < b->h_exp[i].N; ++n)
             if (A[i][n] == nullptr || !aligned(A[i][n], 4)) return RCP_ERR_INVALID_ARG;
     }
-    if (workspace == nullptr || workspace_bytes < B.total || !aligned(workspace, kAlign))
-        return RCP_ERR_WORKSPACE;
-    rcp_batch_t* b = new (std::nothrow) rcp_batch_t;
-    if (b == nullptr) return RCP_ERR_HIP;
-    b->count = count;
-    b->stream = (hipStream_t)hip_stream;
-    bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
-    for (int s = 0; ok && s < kBatchStreams; ++s)
-        ok = hipStreamCreateWithFlags(&b->side[s], hipStreamNonBlocking) == hipSuccess &&
-             hipEventCreateWithFlags(&b->join[s], hipEventDisableTiming) == hipSuccess;
-    if (!ok) { rcp_batch_destroy(b); return RCP_ERR_HIP; }
-    char* ws = (char*)workspace;
-    for (int i = 0; i < count; ++i) {
-        rcp_plan pl = nullptr;
-        st = rcp_init(&pl, &probs[i], ws + B.off[i], B.size[i], b->side[i % kBatchStreams]);
-        if (st != RCP_OK) { rcp_batch_destroy(b); return st; }
-        b->plans.push_back(pl);
-        const Layout& L = pl->L;
-        const float* core = pl->at<float>(L.tb[(L.N - 1) % 2]);
-        b->h_als.push_back(core_als_args(pl, core, info + i));
-        b->h_exp.push_back(core_expand_args(pl, A[i], lambda[i]));
-    }
-    b->d_als = (AlsArgs*)(ws + B.als);
-    b->d_exp = (ExpandArgs*)(ws + B.exp);
-    if (hipMemcpy(b->d_als, b->h_als.data(), count * sizeof(AlsArgs), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b->d_exp, b->h_exp.data(), count * sizeof(ExpandArgs), hipMemcpyHostToDevice) != hipSuccess) {
-        rcp_batch_destroy(b);
-        return RCP_ERR_HIP;
-    }
-    b->use_graph = hip_stream != nullptr;
-    b->workgroups = b->plans[0]->P;
-    *batch = b;
     return RCP_OK;
 }
 
-rcp_status rcp_batch_decompose(rcp_batch batch, const float* const* X) {
-    if (batch == nullptr || X == nullptr) return RCP_ERR_INVALID_ARG;
-    for (int i = 0; i < batch->count; ++i)
-        if (X[i] == nullptr || !aligned(X[i], 4)) return RCP_ERR_INVALID_ARG;
+// Points the argument tables at the given outputs.  Only when they differ
+// from the last upload: the batch stream is drained first (an earlier launch
+// may still read the tables), then the tables go up in stream order.
+rcp_status batch_bind_outputs(rcp_batch_t* b, float* const* const* A, float* const* lambda,
+                              rcp_als_info* info) {
+    bool same = b->bound;
+    for (int i = 0; same && i < b->count; ++i) {
+        same = b->h_als[i].info == info + i && b->h_exp[i].lambda_out == lambda[i];
+        for (int n = 0; same && n < b->h_exp[i].N; ++n) same = b->h_exp[i].A[n] == A[i][n];
+    }
+    if (same) return RCP_OK;
+    RCP_TRY(hipStreamSynchronize(b->stream));
+    for (int i = 0; i < b->count; ++i) {
+        b->h_als[i].info = info + i;
+        b->h_exp[i].lambda_out = lambda[i];
+        for (int n = 0; n < b->h_exp[i].N; ++n) b->h_exp[i].A[n] = A[i][n];
+    }
+    std::memcpy(b->pin_als, b->h_als.data(), b->count * sizeof(AlsArgs));
+    std::memcpy(b->pin_exp, b->h_exp.data(), b->count * sizeof(ExpandArgs));
+    RCP_TRY(hipMemcpyAsync(b->d_als, b->pin_als, b->count * sizeof(AlsArgs), hipMemcpyHostToDevice,
+                           b->stream));
+    RCP_TRY(hipMemcpyAsync(b->d_exp, b->pin_exp, b->count * sizeof(ExpandArgs),
+                           hipMemcpyHostToDevice, b->stream));
+    b->bound = true;
+    return RCP_OK;
+}
+
+rcp_status batch_run(rcp_batch_t* batch, const float* const* X) {
     if (!batch->use_graph) return batch_enqueue(batch, X);
     bool same = batch->exec != nullptr && (int)batch->X.size() == batch->count;
     for (int i = 0; same && i < batch->count; ++i) same = batch->X[i] == X[i];
@@ -857,17 +858,91 @@ rcp_status rcp_batch_decompose(rcp_batch batch, const float* const* X) {
     return RCP_OK;
 }
 
+}  // namespace
+
+rcp_status rcp_batch_workspace_size(const rcp_problem* probs, int32_t count, size_t* bytes) {
+    if (bytes == nullptr) return RCP_ERR_INVALID_ARG;
+    BatchLayout B;
+    rcp_status st = batch_layout(probs, count, &B);
+    if (st != RCP_OK) return st;
+    *bytes = B.total;
+    return RCP_OK;
+}
+
+rcp_status rcp_batch_init(rcp_batch* batch, const rcp_problem* probs, int32_t count,
+                          void* workspace, size_t workspace_bytes, void* hip_stream) {
+    if (batch == nullptr) return RCP_ERR_INVALID_ARG;
+    *batch = nullptr;
+    BatchLayout B;
+    rcp_status st = batch_layout(probs, count, &B);
+    if (st != RCP_OK) return st;
+    if (workspace == nullptr || workspace_bytes < B.total || !aligned(workspace, kAlign))
+        return RCP_ERR_WORKSPACE;
+    rcp_batch_t* b = new (std::nothrow) rcp_batch_t;
+    if (b == nullptr) return RCP_ERR_HIP;
+    b->count = count;
+    b->stream = (hipStream_t)hip_stream;
+    bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+    for (int s = 0; ok && s < kBatchStreams; ++s)
+        ok = hipStreamCreateWithFlags(&b->side[s], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&b->join[s], hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&b->pin_als, count * sizeof(AlsArgs), hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&b->pin_exp, count * sizeof(ExpandArgs), hipHostMallocDefault) == hipSuccess;
+    if (!ok) { rcp_batch_destroy(b); return RCP_ERR_HIP; }
+    char* ws = (char*)workspace;
+    for (int i = 0; i < count; ++i) {
+        rcp_plan pl = nullptr;
+        st = rcp_init(&pl, &probs[i], ws + B.off[i], B.size[i], b->side[i % kBatchStreams]);
+        if (st != RCP_OK) { rcp_batch_destroy(b); return st; }
+        b->plans.push_back(pl);
+        const Layout& L = pl->L;
+        const float* core = pl->at<float>(L.tb[(L.N - 1) % 2]);
+        b->h_als.push_back(core_als_args(pl, core, nullptr));
+        b->h_exp.push_back(core_expand_args(pl, nullptr, nullptr));
+    }
+    // the plans' status words are cleared on the side streams: the batch
+    // stream waits for that before its first use of the workspace
+    for (int s = 0; ok && s < kBatchStreams; ++s)
+        ok = hipEventRecord(b->join[s], b->side[s]) == hipSuccess &&
+             hipStreamWaitEvent(b->stream, b->join[s], 0) == hipSuccess;
+    if (!ok) { rcp_batch_destroy(b); return RCP_ERR_HIP; }
+    b->d_als = (AlsArgs*)(ws + B.als);
+    b->d_exp = (ExpandArgs*)(ws + B.exp);
+    b->use_graph = hip_stream != nullptr;
+    b->workgroups = b->plans[0]->P;
+    *batch = b;
+    return RCP_OK;
+}
+
+rcp_status rcp_batch_decompose(rcp_batch batch, const float* const* X, float* const* const* A,
+                               float* const* lambda, rcp_als_info* info) {
+    if (batch == nullptr) return RCP_ERR_INVALID_ARG;
+    rcp_status st = batch_check_io(batch, X, A, lambda, info);
+    if (st != RCP_OK) return st;
+    st = batch_bind_outputs(batch, A, lambda, info);
+    if (st != RCP_OK) return st;
+    return batch_run(batch, X);
+}
+
+rcp_status rcp_batch_read_status(rcp_batch batch, int32_t index, int32_t* status) {
+    if (batch == nullptr || index < 0 || index >= batch->count) return RCP_ERR_INVALID_ARG;
+    RCP_TRY(hipStreamSynchronize(batch->stream));
+    return rcp_read_status(batch->plans[index], status);
+}
+
 constexpr double kAutotuneGain = 0.97;
 
 // Coordinate search over the launch shape: each knob in turn takes every
 // candidate value with the others at their best so far; each candidate is
 // recorded (graph) once and timed over two replays.
-rcp_status rcp_batch_autotune(rcp_batch batch, const float* const* X, int32_t* shape,
+rcp_status rcp_batch_autotune(rcp_batch batch, const float* const* X, float* const* const* A,
+                              float* const* lambda, rcp_als_info* info, int32_t* shape,
                               double* best_ms) {
-    if (batch == nullptr || X == nullptr || shape == nullptr || best_ms == nullptr)
-        return RCP_ERR_INVALID_ARG;
-    for (int i = 0; i < batch->count; ++i)
-        if (X[i] == nullptr || !aligned(X[i], 4)) return RCP_ERR_INVALID_ARG;
+    if (batch == nullptr || shape == nullptr || best_ms == nullptr) return RCP_ERR_INVALID_ARG;
+    rcp_status st = batch_check_io(batch, X, A, lambda, info);
+    if (st != RCP_OK) return st;
+    st = batch_bind_outputs(batch, A, lambda, info);
+    if (st != RCP_OK) return st;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         if (e0 != nullptr) (void)hipEventDestroy(e0);
@@ -876,17 +951,16 @@ rcp_status rcp_batch_autotune(rcp_batch batch, const float* const* X, int32_t* s
     const int cus_default = batch->plans[0]->P;
     int best[3] = {batch->streams, batch->workgroups, batch->mb_cap};
     double best_t = -1.0;
-    rcp_status st = RCP_OK;
     auto measure = [&](const int* c, double* ms) -> rcp_status {
         batch->streams = c[0];
         batch->workgroups = c[1];
         batch->mb_cap = c[2];
         batch_apply_shape(batch);
         batch_drop_graph(batch);
-        rcp_status r = rcp_batch_decompose(batch, X);         // records the graph
+        rcp_status r = batch_run(batch, X);         // records the graph
         if (r != RCP_OK) return r;
         if (hipEventRecord(e0, batch->stream) != hipSuccess) return RCP_ERR_HIP;
-        for (int rep = 0; rep < 2 && r == RCP_OK; ++rep) r = rcp_batch_decompose(batch, X);
+        for (int rep = 0; rep < 2 && r == RCP_OK; ++rep) r = batch_run(batch, X);
         if (r != RCP_OK) return r;
         if (hipEventRecord(e1, batch->stream) != hipSuccess ||
             hipEventSynchronize(e1) != hipSuccess)
@@ -931,6 +1005,7 @@ rcp_status rcp_batch_autotune(rcp_batch batch, const float* const* X, int32_t* s
 
 rcp_status rcp_batch_destroy(rcp_batch batch) {
     if (batch == nullptr) return RCP_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(batch->stream);
     batch_drop_graph(batch);
     for (rcp_plan_t* p : batch->plans) rcp_destroy(p);
     for (int s = 0; s < kBatchStreams; ++s) {
@@ -938,6 +1013,8 @@ rcp_status rcp_batch_destroy(rcp_batch batch) {
         if (batch->join[s] != nullptr) hipEventDestroy(batch->join[s]);
     }
     if (batch->fork != nullptr) hipEventDestroy(batch->fork);
+    if (batch->pin_als != nullptr) hipHostFree(batch->pin_als);
+    if (batch->pin_exp != nullptr) hipHostFree(batch->pin_exp);
     delete batch;
     return RCP_OK;
 }
@@ -964,6 +1041,17 @@ rcp_status rcp_debug_omega(rcp_plan plan, int32_t mode, int64_t row0, int64_t nr
     if (!aligned(omega, 4)) return RCP_ERR_INVALID_ARG;
     RCP_TRY(launch_omega(plan->prob.seed, omega_stream_tag(0, (uint32_t)mode), row0, nrows, l, omega,
                          plan->stream));
+    return RCP_OK;
+}
+
+rcp_status rcp_debug_philox(rcp_plan plan, int32_t mode, int64_t row0, int64_t nrows,
+                            int32_t ngroups, uint32_t* words) {
+    if (plan == nullptr || words == nullptr || mode < 0 || mode >= 256 || row0 < 0 || nrows < 0 ||
+        ngroups < 1 || ngroups > RCP_MAX_L / 4)
+        return RCP_ERR_INVALID_ARG;
+    if (!aligned(words, 4)) return RCP_ERR_INVALID_ARG;
+    RCP_TRY(launch_philox_words(plan->prob.seed, omega_stream_tag(0, (uint32_t)mode), row0, nrows,
+                                ngroups, words, plan->stream));
     return RCP_OK;
 }
 

@@ -74,6 +74,10 @@ hipError_t launch_sumsq(const float* x, int64_t count, double* part, int nblocks
                         hipStream_t s);
 hipError_t launch_omega(uint64_t seed, uint32_t tag, int64_t row0, int64_t nrows, int l,
                         float* out, hipStream_t s);
+// the raw Philox4x32-10 words behind rows [row0, row0 + nrows) of Omega:
+// out[(r * ngroups + g) * 4 + i] is word i of column group g of row row0 + r
+hipError_t launch_philox_words(uint64_t seed, uint32_t tag, int64_t row0, int64_t nrows,
+                               int ngroups, uint32_t* out, hipStream_t s);
 hipError_t launch_pad_q(const float* Q, int64_t I, int l, float* Qpad, int ldq, hipStream_t s);
 constexpr uint32_t omega_stream_tag(uint32_t batch, uint32_t mode) { return (batch << 8) | (mode & 0xFFu); }
 
@@ -82,9 +86,10 @@ constexpr uint32_t omega_stream_tag(uint32_t batch, uint32_t mode) { return (bat
 // Cholesky QR passes (the first shifted), a third for the returned basis
 // (final_basis), Householder when a pivot vanishes.  Writes Q (diag(R) > 0) as
 // float32 into Qpad (m x ldq, columns >= n zeroed) and, if non-null, into
-// Qout (m x n).
+// Qout (m x n).  status (device, may be null): RCP_INFO_QR_HOUSEHOLDER is
+// or-ed in when the Householder fallback runs.
 hipError_t launch_qr(double* Y, int64_t m, int n, int ldy, float* Qpad, int ldq, float* Qout,
-                     bool final_basis, hipStream_t s);
+                     bool final_basis, int* status, hipStream_t s);
 
 // CP-ALS on the core (als_kernel.hip)
 struct AlsArgs {
@@ -93,11 +98,13 @@ struct AlsArgs {
     int l[RCP_MAX_NDIM];
     int R;
     int max_iters;
+    int warm;                  // nonzero: At[1..N-1] hold the starting factors (no eigenvector start)
     double tol;
     const double* normX2;      // may be null
     float* At[RCP_MAX_NDIM];   // l_n x R outputs
     float* lambda;             // R
     rcp_als_info* info;
+    int* status_word;          // the plan's device status word (RCP_INFO_* or-ed in), may be null
     // workspace
     double* Ebuf;              // Jacobi scratch (2 x 64 x 64), then M_n (l_max x R)
     // grid-wide form (cores larger than LDS): reduced mode product or Gram
@@ -120,6 +127,8 @@ bool als_core_in_lds(int N, const int* l, int R);
 size_t als_state_doubles(int N, int R);
 // Algorithm 2 step 2 for mode n from its Gram B_(n) B_(n)^T in a.Y
 hipError_t launch_als_wide_init(const AlsArgs& a, int n, hipStream_t s);
+// warm start: the Grams of the given factors At[1..N-1] and a fresh state
+hipError_t launch_als_wide_warm(const AlsArgs& a, hipStream_t s);
 // steps 4-10 for mode n from its reduced mode product in a.Y; after the
 // last mode, the fit and the stopping rule
 hipError_t launch_als_wide_step(const AlsArgs& a, int n, hipStream_t s);

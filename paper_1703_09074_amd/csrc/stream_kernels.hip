@@ -80,6 +80,25 @@ __global__ __launch_bounds__(NT) void k_omega(uint64_t seed, uint32_t tag, int64
     }
 }
 
+__global__ __launch_bounds__(NT) void k_philox_words(uint64_t seed, uint32_t tag, int64_t row0,
+                                                     int64_t nrows, int ng, uint32_t* out) {
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= nrows * ng) return;
+    const int64_t r = e / ng;
+    const int gi = (int)(e - r * ng);
+    const uint64_t j = (uint64_t)(row0 + r);
+    U4 c;
+    c.x = (uint32_t)j;
+    c.y = (uint32_t)(j >> 32);
+    c.z = (uint32_t)gi;
+    c.w = tag;
+    const U4 x = philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    out[4 * e + 0] = x.x;
+    out[4 * e + 1] = x.y;
+    out[4 * e + 2] = x.z;
+    out[4 * e + 3] = x.w;
+}
+
 // Q (I x l) -> Qpad (I x ldq), zero columns >= l.
 __global__ __launch_bounds__(NT) void k_pad_q(const float* Q, int64_t I, int l, float* Qpad,
                                               int ldq) {
@@ -243,6 +262,16 @@ hipError_t launch_omega(uint64_t seed, uint32_t tag, int64_t row0, int64_t nrows
     const unsigned blocks = (unsigned)((n + NT - 1) / NT);
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_omega, dim3(blocks), dim3(NT), 0, s, seed, tag, row0, nrows, l, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox_words(uint64_t seed, uint32_t tag, int64_t row0, int64_t nrows,
+                               int ngroups, uint32_t* out, hipStream_t s) {
+    const int64_t n = nrows * ngroups;
+    const unsigned blocks = (unsigned)((n + NT - 1) / NT);
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_philox_words, dim3(blocks), dim3(NT), 0, s, seed, tag, row0, nrows,
+                       ngroups, out);
     return hipGetLastError();
 }
 

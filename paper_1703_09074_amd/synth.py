@@ -144,6 +144,9 @@ WORKLOADS = {
     # k=30 p=15 q in {1,3}, 200 sweeps.
     "rcp4way": dict(dims=(256, 256, 256, 64), R=30, noise=0.05, kind="collinear",
                     k=30, p=15, q=3, iters=200, data_seed=20170330, seed=1003),
+    # the same tensor with a single power iteration
+    "rcp4way_q1": dict(dims=(256, 256, 256, 64), R=30, noise=0.05, kind="collinear",
+                       k=30, p=15, q=1, iters=200, data_seed=20170330, seed=1003),
 }
 
 

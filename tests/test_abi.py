@@ -132,7 +132,10 @@ def test_null_plan_rejected_everywhere(lib):
     dims = _lib.dims_array((4, 4, 4))
     assert lib.rcp_sketch(None, None, dims, 0, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_compress(None, None, dims, 0, None, None) == _lib.RCP_ERR_INVALID_ARG
-    assert lib.rcp_als(None, None, None, None, None, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_als(None, None, None, None, None, None, 0) == _lib.RCP_ERR_INVALID_ARG
+    v = ctypes.c_int32(0)
+    assert lib.rcp_read_status(None, ctypes.byref(v)) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_debug_philox(None, 0, 0, 1, 1, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_expand(None, None, None, None, None, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_decompose(None, None, None, None, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_norm2(None, None, 0, None) == _lib.RCP_ERR_INVALID_ARG
@@ -140,8 +143,15 @@ def test_null_plan_rejected_everywhere(lib):
     assert lib.rcp_get_bases(None, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_get_core(None, None, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_destroy(None) == _lib.RCP_ERR_INVALID_ARG
-    assert lib.rcp_batch_decompose(None, None) == _lib.RCP_ERR_INVALID_ARG
-    assert lib.rcp_batch_autotune(None, None, None, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_batch_decompose(None, None, None, None, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_batch_autotune(None, None, None, None, None, None, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_batch_read_status(None, 0, ctypes.byref(v)) == _lib.RCP_ERR_INVALID_ARG
+    prob = _lib.make_problem((40, 30, 20), 5, 5, 1, 10, 0.0, 1)
+    h = ctypes.c_void_p(0)
+    assert lib.rcp_batch_init(ctypes.byref(h), ctypes.byref(prob), 1, None, 0, None) == \
+        _lib.RCP_ERR_WORKSPACE
+    assert lib.rcp_batch_init(ctypes.byref(h), ctypes.byref(prob), 0, None, 0, None) == \
+        _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_batch_destroy(None) == _lib.RCP_ERR_INVALID_ARG
 
 

@@ -116,3 +116,40 @@ def test_batch_autotune_keeps_a_valid_shape():
         cong = evaluate.congruence([_np(a) for a in b.A[i]], ref.factors)[0]
         assert abs(e_gpu - e_ref) <= 1e-4, (i, e_gpu, e_ref)
         assert cong >= 0.999, (i, cong)
+
+
+def test_batch_bf16_subset_of_the_large_batch_matches_oracle():
+    """A seeded subset of the 512-problem workload (modes U{32..256}, R
+    U{4..16}, noise 0.05, k = R, p = 10, q = 2, 50 sweeps, bfloat16 range
+    finder): every problem within 1e-4 of the float64 oracle's relative
+    error, congruence >= 0.999; the error difference is printed per problem."""
+    shapes = synth.batch_problems(512, 20170331, lo=32, hi=256, rlo=4, rhi=16)
+    pick = [shapes[i] for i in range(0, 512, 43)]                # 12 problems
+    probs, tensors = [], []
+    for dims, R, dseed in pick:
+        w = synth.low_rank(dims, R, 0.05, dseed)
+        probs.append(dict(dims=list(dims), k=R, p=10, q=2, max_iters=50, seed=dseed % 100003,
+                          precision="bf16"))
+        tensors.append(w.X)
+    Xs = [torch.from_numpy(x).cuda() for x in tensors]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b = rcpgpu.Batch(probs)
+        b.decompose(Xs)
+    torch.cuda.synchronize()
+    infos = b.read_info()
+    worst = 0.0
+    for i, (pr, x) in enumerate(zip(probs, tensors)):
+        assert infos[i]["status"] == 0 and infos[i]["iters"] == 50, infos[i]
+        assert b.read_status(i) == 0
+        ref = rcp.rcp_als(x.astype(np.float64), pr["k"], pr["p"], pr["q"], pr["max_iters"], 0.0,
+                          pr["seed"])
+        e_ref = evaluate.relative_error(x, ref.lam, ref.factors)
+        e_gpu = evaluate.relative_error(x, _np(b.lam[i]), [_np(a) for a in b.A[i]])
+        cong = evaluate.congruence([_np(a) for a in b.A[i]], ref.factors)[0]
+        print(f"[batch-bf16] {pr['dims']} R={pr['k']}: rel_err gpu {e_gpu:.7f} oracle {e_ref:.7f} "
+              f"diff {e_gpu - e_ref:+.2e} congruence {cong:.6f}", flush=True)
+        worst = max(worst, abs(e_gpu - e_ref))
+        assert abs(e_gpu - e_ref) <= 1e-4, (i, e_gpu, e_ref)
+        assert cong >= 0.999, (i, cong)
+    print(f"[batch-bf16] max |rel_err diff| {worst:.2e}", flush=True)

@@ -1,25 +1,31 @@
-"""The full-size workloads on the GPU, checked through properties that hold
-at any size and through core entries the oracle computes one at a time.
+"""The full-size workloads on the GPU against the float64 oracle, end to end:
 
-  * 2048 x 2048 x 512, R = 50, noise 0.1 rms, k = 50, p = 10, q = 2, 100 sweeps;
+  * 2048 x 2048 x 512, R = 50, noise 0.1 rms, k = 50, p = 10, q = 2, 100 sweeps,
+    float32 and bfloat16 range-finder operands;
   * 256 x 256 x 256 x 64, R = 30, pairwise factor cosine 0.8, noise 0.05 rms,
-    k = 30, p = 15, q = 3, 200 sweeps.
+    k = 30, p = 15, q = 3 (float32 and float16 range finder) and q = 1
+    (float32), 200 sweeps.
 
-The tensors are built on the GPU from the seeded recipe (the oracle cannot
-decompose them in reasonable time).  Checks:
-  * every basis Q_n is orthonormal (|Q^T Q - I| <= 1e-5);
-  * the true factors lie in span(Q_n) up to the noise;
-  * sampled core entries B[i] = X x_1 q_1^T ... x_N q_N^T match the oracle's
-    float64 mode products of the same X and Q_n (relative to max|B|);
-  * CP-ALS on the GPU's core matches the oracle's CP-ALS on the same core
-    (relative error within 1e-4);
-  * the relative error is not below the noise floor ||E|| / ||X|| (by more
-    than the few percent a rank-R model can fit of the noise), and, where
-    ALS reaches it in the given sweeps, sits at it with the true factors
-    recovered.  For 2048 x 2048 x 512 with R = 50, 100 sweeps from the
-    eigenvector start stop at a relative error of about 0.18 on the oracle
-    as on the GPU (identical values), so there only the parity checks apply.
+The tensors are assembled on the GPU from the seeded recipe and copied back;
+the oracle's unmodified ``rcp_als`` decomposes the host copy of the same
+buffer (float64, about 3.5x the tensor's float32 size of host memory at its
+peak: the float32 copy, its float64 upcast and one unfolding-sized
+temporary).  Both results go through the same float64 evaluator
+(relative error ||X - Xhat|| / ||X|| computed slab by slab from X) and the
+congruence of their factors:
+
+  * |rel_err_gpu - rel_err_oracle| <= 1e-4 and congruence >= 0.999, for
+    every precision (a 16-bit range finder only perturbs the bases, which the
+    float64 QR re-orthonormalises, so the bar is the float32 one); each
+    result's difference from the oracle is printed;
+  * every basis is orthonormal to 1e-5.
+
+For 2048 x 2048 x 512 with R = 50, 100 sweeps from the eigenvector start end
+at a relative error of about 0.18, above the noise floor of about 0.1, on the
+oracle as on the GPU: the parity bar still applies to the stalled fit.
 """
+import resource
+
 import numpy as np
 import pytest
 
@@ -31,72 +37,71 @@ from paper_1703_09074_amd import synth  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-
-def _core_entry(X_host, Qs, idx):
-    """B[idx] by the oracle's mode products, one slab of mode 0 at a time."""
-    q0 = Qs[0][:, idx[0]].astype(np.float64)
-    acc = None
-    slab = 64
-    for a0 in range(0, X_host.shape[0], slab):
-        a1 = min(X_host.shape[0], a0 + slab)
-        blk = X_host[a0:a1].astype(np.float64)
-        v = rcp.mode_product(blk, q0[a0:a1][None, :], 0)          # 1 x ...
-        acc = v if acc is None else acc + v
-    for n in range(1, len(Qs)):
-        acc = rcp.mode_product(acc, Qs[n][:, idx[n]].astype(np.float64)[None, :], n)
-    return float(acc.reshape(-1)[0])
+_X = {}        # data seed -> (device tensor, host copy)
+_REF = {}      # workload name -> oracle result and its relative error
 
 
-@pytest.mark.parametrize("name,cong_min", [("rcp2048", None), ("rcp4way", 0.99)])
-def test_full_size_workload(name, cong_min):
+def _tensor(cfg):
+    key = (cfg["data_seed"], tuple(cfg["dims"]))
+    if key not in _X:
+        _X.clear()
+        torch.cuda.empty_cache()
+        X, _, _, _ = synth.low_rank_device(list(cfg["dims"]), cfg["R"], cfg["noise"],
+                                           cfg["data_seed"], kind=cfg["kind"])
+        torch.cuda.synchronize()
+        _X[key] = (X, X.cpu().numpy())
+    return _X[key]
+
+
+def _oracle(name, cfg, X_host):
+    if name not in _REF:
+        print(f"[fullsize] oracle rcp_als on {name} ...", flush=True)
+        ref = rcp.rcp_als(X_host, cfg["k"], cfg["p"], cfg["q"], cfg["iters"], 0.0, cfg["seed"])
+        e_ref = evaluate.relative_error(X_host, ref.lam, ref.factors)
+        rss_gib = resource.getrusage(resource.RUSAGE_SELF).ru_maxrss / 2 ** 20
+        print(f"[fullsize] oracle {name}: rel_err {e_ref:.7f} (fit form {ref.rel_err:.7f}), "
+              f"host peak RSS {rss_gib:.1f} GiB", flush=True)
+        _REF.clear()
+        _REF[name] = (ref, e_ref)
+    return _REF[name]
+
+
+@pytest.mark.parametrize("name,prec", [("rcp2048", "fp32"), ("rcp2048", "bf16"),
+                                       ("rcp4way", "fp32"), ("rcp4way", "fp16"),
+                                       ("rcp4way_q1", "fp32")])
+def test_full_size_matches_oracle(name, prec):
     cfg = synth.WORKLOADS[name]
     dims = list(cfg["dims"])
-    print(f"[fullsize] {name} dims {dims}", flush=True)
-    X, factors, weights, sigma = synth.low_rank_device(dims, cfg["R"], cfg["noise"],
-                                                       cfg["data_seed"], kind=cfg["kind"])
-    k, p, q, iters = cfg["k"], cfg["p"], cfg["q"], cfg["iters"]
-    plan = rcpgpu.Plan(dims, k, p, q, iters, 0.0, cfg["seed"])
+    k = cfg["k"]
+    print(f"[fullsize] {name} {prec} dims {dims} q {cfg['q']}", flush=True)
+    X, X_host = _tensor(cfg)
+    plan = rcpgpu.Plan(dims, k, cfg["p"], cfg["q"], cfg["iters"], 0.0, cfg["seed"], precision=prec)
     A = [torch.empty((d, k), dtype=torch.float32, device="cuda") for d in dims]
     lam = torch.empty((k,), dtype=torch.float32, device="cuda")
     info = plan._info_buffer()
     plan.decompose_into(X, A, lam, info)
     torch.cuda.synchronize()
     res = rcpgpu.Plan.read_info(info)
-    assert res["status"] == 0 and res["iters"] == iters, res
-    Qs = [b.cpu().numpy().astype(np.float64) for b in plan.bases()]
-    for n, Q in enumerate(Qs):
+    assert res["status"] == 0 and res["iters"] == cfg["iters"], res
+    for n, b in enumerate(plan.bases()):
+        Q = b.cpu().numpy().astype(np.float64)
         err = np.max(np.abs(Q.T @ Q - np.eye(Q.shape[1])))
         assert err <= 1e-5, (n, err)
-        At = factors[n]
-        resid = np.linalg.norm(At - Q @ (Q.T @ At)) / np.linalg.norm(At)
-        print(f"[fullsize] mode {n}: orthonormality {err:.2e}, true-factor residual {resid:.3e}", flush=True)
-        assert resid <= 0.05, (n, resid)
-    core = plan.core().cpu().numpy().astype(np.float64)
-    X_host = X.cpu().numpy()
-    rng = np.random.default_rng(7)
-    bmax = np.max(np.abs(core))
-    for _ in range(2):
-        idx = tuple(int(rng.integers(0, s)) for s in core.shape)
-        want = _core_entry(X_host, Qs, idx)
-        got = core[idx]
-        print(f"[fullsize] core{idx}: gpu {got:.6g} oracle {want:.6g}", flush=True)
-        assert abs(got - want) <= 1e-4 * bmax, (idx, got, want, bmax)
-    # the oracle's CP-ALS on the same core (float64), same sweeps and normX2
-    ref = rcp.als(core, k, iters, normX2=res["normX2"])
-    ref_err = float(np.sqrt(max(0.0, 1.0 - ref.rho)))
-    print(f"[fullsize] ALS on the core: gpu rel_err {res['rel_err']:.6f}, oracle {ref_err:.6f}", flush=True)
-    assert abs(res["rel_err"] - ref_err) <= 1e-4, (res["rel_err"], ref_err)
-    # noise floor: ||E||^2 = sigma^2 * count (expected), ||X||^2 from the run
-    count = float(np.prod(dims))
-    floor = np.sqrt(sigma * sigma * count / res["normX2"])
-    print(f"[fullsize] rel_err {res['rel_err']:.6f}, noise floor {floor:.6f}", flush=True)
-    assert res["rel_err"] >= 0.95 * floor, (res["rel_err"], floor)
     lam_h = lam.cpu().numpy().astype(np.float64)
-    assert np.all(np.isfinite(lam_h))
-    if cong_min is not None:
-        assert res["rel_err"] <= 1.02 * floor, (res["rel_err"], floor)
-        A_h = [a.cpu().numpy().astype(np.float64) for a in A]
-        true = [f * (weights[None, :] if n == 0 else 1.0) for n, f in enumerate(factors)]
-        cong = evaluate.congruence(A_h, true)[0]
-        print(f"[fullsize] congruence with the true factors {cong}", flush=True)
-        assert cong >= cong_min, cong
+    A_h = [a.cpu().numpy().astype(np.float64) for a in A]
+    del plan
+    ref, e_ref = _oracle(name, cfg, X_host)
+    e_gpu = evaluate.relative_error(X_host, lam_h, A_h)
+    cong, cmin, _ = evaluate.congruence(A_h, ref.factors)
+    print(f"[fullsize] {name} {prec}: rel_err gpu {e_gpu:.7f} oracle {e_ref:.7f} "
+          f"diff {e_gpu - e_ref:+.2e}; congruence mean {cong:.6f} min {cmin:.6f}", flush=True)
+    assert abs(e_gpu - e_ref) <= 1e-4, (e_gpu, e_ref)
+    assert cong >= 0.999, cong
+    # the device-side fit agrees with the evaluator
+    assert abs(res["rel_err"] - e_gpu) <= 1e-4, (res["rel_err"], e_gpu)
+
+
+def teardown_module(module):
+    _X.clear()
+    _REF.clear()
+    torch.cuda.empty_cache()

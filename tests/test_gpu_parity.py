@@ -57,6 +57,17 @@ def test_omega_bits_match_oracle():
         assert np.max(np.abs(got - want)) <= 4e-6, (mode, row0, np.max(np.abs(got - want)))
 
 
+def test_philox_words_match_oracle_bitwise():
+    """The uint32 Philox4x32-10 stream behind Omega is the oracle's, bit for bit
+    (rows past 2^32 included, so the counter's high word is exercised)."""
+    seed = (0xDEADBEEF << 32) | 0x12345678
+    plan = rcpgpu.Plan((64, 64, 64), 5, 5, 0, 1, 0.0, seed)
+    for mode, row0, nrows, ng in [(0, 0, 4096, 16), (1, 77777, 1000, 3), (2, (1 << 32) - 10, 20, 8)]:
+        got = plan.philox_words(mode, row0, nrows, ng).cpu().numpy().view(np.uint32)
+        want = philox.omega_bits(seed, mode, 0, row0, nrows, ng).astype(np.uint32)
+        np.testing.assert_array_equal(got.reshape(nrows, 4 * ng), want)
+
+
 SKETCH_CASES = [
     # shape, mode, k, p, q
     ((37, 50, 41), 0, 5, 5, 0),        # ragged, case A (Rr = 2050)
@@ -133,6 +144,78 @@ def test_als_matches_oracle(dims, R, iters):
     cong, cmin, perm = evaluate.congruence([_np(a) for a in At], ref.factors)
     assert cmin >= 0.9999
     np.testing.assert_allclose(gl, ref.lam[perm], rtol=1e-4)
+
+
+# The stopping rule of Section 3.3 in the one-workgroup kernel (core in LDS):
+# after sweep j >= 2 the run ends once the fit changes by less than tol.
+@pytest.mark.parametrize("dims,R,tol", [((40, 35, 30), 4, 1e-6), ((20, 18, 16, 14), 3, 1e-7),
+                                        ((30, 28, 26), 6, 1e-5)])
+def test_als_stopping_rule_in_lds(dims, R, tol):
+    w, comp = _core_problem(dims, R, 0.05, 17, R, 5, 1)
+    core = comp.core.astype(np.float32)
+    normX2 = float(np.sum(w.X.astype(np.float64) ** 2))
+    plan = rcpgpu.Plan(dims, R, 5, 1, 500, tol, 17)
+    nx = torch.tensor([normX2], dtype=torch.float64, device="cuda")
+    At, lam, info = plan.als(_dev(core), nx)
+    info = rcpgpu.Plan.read_info(info)
+    ref = rcp.als(core.astype(np.float64), R, 500, tol=tol, normX2=normX2)
+    assert 2 <= ref.iters < 500
+    assert info["iters"] == ref.iters, (info["iters"], ref.iters)
+    assert abs(info["rho"] - ref.rho) <= 1e-7, (info["rho"], ref.rho)
+    cong, cmin, perm = evaluate.congruence([_np(a) for a in At], ref.factors)
+    assert cmin >= 0.9999, cmin
+
+
+# Warm start (rcp_als with given factors): the sweeps continue from the
+# caller's factors instead of the eigenvector start, in both the in-LDS and
+# the grid-wide form; the oracle continues from the same factors.
+@pytest.mark.parametrize("dims,R", [((40, 35, 30), 4), ((20, 18, 16, 14), 3), ((60, 55, 50), 40)])
+def test_als_warm_start_matches_oracle(dims, R):
+    w, comp = _core_problem(dims, R, 0.05, 23, R, 5, 1)
+    core = comp.core.astype(np.float32)
+    c64 = core.astype(np.float64)
+    normX2 = float(np.sum(w.X.astype(np.float64) ** 2))
+    first = rcp.als(c64, R, 4, normX2=normX2)
+    start = [f.astype(np.float32) for f in first.factors]
+    ref = rcp.als(c64, R, 3, normX2=normX2, init=[s.astype(np.float64) for s in start])
+    plan = rcpgpu.Plan(dims, R, 5, 1, 3, 0.0, 23)
+    nx = torch.tensor([normX2], dtype=torch.float64, device="cuda")
+    At, lam, info = plan.als(_dev(core), nx, init=[_dev(s) for s in start])
+    info = rcpgpu.Plan.read_info(info)
+    assert info["iters"] == 3
+    assert abs(info["rho"] - ref.rho) <= 1e-7, (info["rho"], ref.rho)
+    cong, cmin, perm = evaluate.congruence([_np(a) for a in At], ref.factors)
+    assert cmin >= 0.9999, cmin
+    np.testing.assert_allclose(_np(lam), ref.lam[perm], rtol=1e-4)
+    # three sweeps from the eigenvector start end elsewhere than three more
+    # sweeps after the first four: the given factors were used
+    At_c, lam_c, info_c = plan.als(_dev(core), nx)
+    cold = rcpgpu.Plan.read_info(info_c)
+    assert abs(cold["rho"] - info["rho"]) > 1e-9, (cold["rho"], info["rho"])
+
+
+def test_status_word_collects_numeric_outcomes():
+    """rcp_read_status: a noise-free rank-3 tensor with l = 13 > 3 makes the
+    sketches exactly rank deficient (Householder QR fallback); an all-zero
+    core makes the Gram singular (pseudo-inverse).  The word is cleared by
+    each read."""
+    w = synth.low_rank((60, 50, 40), 3, 0.0, 41)
+    plan = rcpgpu.Plan(w.X.shape, 3, 10, 1, 5, 0.0, 3)
+    assert plan.read_status() == 0
+    plan.decompose(_dev(w.X))
+    st = plan.read_status()
+    assert st & rcpgpu._lib.RCP_INFO_QR_HOUSEHOLDER, st
+    assert plan.read_status() == 0
+    zp = rcpgpu.Plan((9, 8, 7), 3, 4, 0, 3, 0.0, 11)
+    zp.als(_dev(np.zeros((7, 7, 7), np.float32)), torch.tensor([1.0], dtype=torch.float64,
+                                                                 device="cuda"))
+    st = zp.read_status()
+    assert st & rcpgpu._lib.RCP_INFO_PINV_FALLBACK, st
+    # a well-conditioned problem raises nothing
+    w2 = synth.low_rank((50, 40, 30), 4, 0.05, 43)
+    p2 = rcpgpu.Plan(w2.X.shape, 4, 6, 1, 10, 0.0, 5)
+    p2.decompose(_dev(w2.X))
+    assert p2.read_status() == 0
 
 
 # An all-zero core: the first update makes A_0 zero, so every later V is the
