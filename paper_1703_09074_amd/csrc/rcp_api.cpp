@@ -329,9 +329,13 @@ hipError_t als_wide(rcp_plan_t* pl, AlsArgs a) {
         if (e != hipSuccess) return e;
         a.normX2 = state + 3;
     }
-    if (a.warm) return launch_als_wide_warm(a, pl->stream);
+    if (a.warm) {
+        // warm start: the Grams of the caller's factors, a fresh sweep state
+        hipError_t e = launch_als_wide_warm(a, pl->stream);
+        if (e != hipSuccess) return e;
+    }
     // Algorithm 2 step 2: Grams B_(n) B_(n)^T as Y = T (T^T I) over the GPU
-    for (int n = 1; n < N; ++n) {
+    for (int n = 1; n < N && !a.warm; ++n) {
         const StreamGeom g = make_geom(a.B, cd, N, n);
         const int P = (int)std::max<int64_t>(1, std::min<int64_t>(pl->P, g.ntiles));
         const int LPn = lp_of(L.l[n]);
