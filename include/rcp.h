@@ -190,6 +190,27 @@ rcp_status rcp_expand(rcp_plan plan, const float* const* Q, const float* const* 
 rcp_status rcp_decompose(rcp_plan plan, const float* X, float* const* A,
                          float* lambda, rcp_als_info* info);
 
+/* For callers that cannot allocate device memory or pass a workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): rcp_decompose without a plan or workspace.  Same arguments
+ * and results as rcp_init + rcp_decompose + rcp_destroy (prob as for
+ * rcp_init, X and the outputs as for rcp_decompose, hip_stream as for
+ * rcp_init); the workspace is a device array inside the library of
+ * RCP_NOALLOC_SCRATCH_BYTES, one per GPU, held until the process ends, found
+ * on the first call on each device.  The call allocates nothing and enqueues
+ * only kernels (no memset or copy nodes).  RCP_ERR_WORKSPACE when the
+ * problem's rcp_workspace_size exceeds RCP_NOALLOC_SCRATCH_BYTES (e.g.
+ * 256^3 with k + p = 26 fits; 400^3 with k + p = 30 does not);
+ * RCP_ERR_INVALID_ARG / RCP_ERR_UNSUPPORTED as rcp_init / rcp_decompose.
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents: calls that overlap on one GPU (different streams or
+ * threads without ordering between them) race and give undefined results.
+ * The status bits that rcp_read_status would report are not readable for
+ * this entry point; CP-ALS outcomes still land in info->status. */
+#define RCP_NOALLOC_SCRATCH_BYTES (32u << 20)
+rcp_status rcp_decompose_noalloc(const rcp_problem* prob, const float* X, float* const* A,
+                                 float* lambda, rcp_als_info* info, void* hip_stream);
+
 /* Device pointers, inside the workspace, of the bases Q_n (I_n x l_n) and of
  * the core (l_0 x ... x l_{N-1}) that the last rcp_decompose produced.
  * Q: host array of N pointers to fill.  core_dims: host array of N (may be NULL). */

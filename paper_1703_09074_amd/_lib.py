@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "librcp.so")
 RCP_MAX_NDIM = 8
 RCP_MAX_L = 64
 RCP_MAX_RANK = 64
+RCP_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 RCP_OK = 0
 RCP_ERR_INVALID_ARG = 1
@@ -75,6 +76,7 @@ SIGNATURES = {
     "rcp_read_status": (_st, [_vp, ctypes.POINTER(ctypes.c_int32)]),
     "rcp_expand": (_st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, ctypes.POINTER(_vp), _vp]),
     "rcp_decompose": (_st, [_vp, _vp, ctypes.POINTER(_vp), _vp, _vp]),
+    "rcp_decompose_noalloc": (_st, [ctypes.POINTER(Problem), _vp, ctypes.POINTER(_vp), _vp, _vp, _vp]),
     "rcp_get_bases": (_st, [_vp, ctypes.POINTER(_vp)]),
     "rcp_get_core": (_st, [_vp, ctypes.POINTER(_vp), _i64p]),
     "rcp_debug_omega": (_st, [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _vp]),

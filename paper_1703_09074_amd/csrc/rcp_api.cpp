@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -447,23 +448,19 @@ rcp_status rcp_workspace_size(const rcp_problem* prob, size_t* bytes) {
     return RCP_OK;
 }
 
-rcp_status rcp_init(rcp_plan* plan, const rcp_problem* prob, void* workspace,
-                    size_t workspace_bytes, void* hip_stream) {
-    if (plan == nullptr) return RCP_ERR_INVALID_ARG;
-    *plan = nullptr;
+}  // extern "C"
+
+namespace {
+
+// Checks the problem and the workspace and fills *pl (no allocation, no
+// device work): shared by rcp_init and the allocation-free entry point.
+rcp_status plan_setup(rcp_plan_t* pl, const rcp_problem* prob, void* workspace,
+                      size_t workspace_bytes, void* hip_stream, int cus) {
     if (!valid_problem(prob)) return RCP_ERR_INVALID_ARG;
     const Layout L = make_layout(prob);
     if (!als_supported(L.N, L.l, L.R)) return RCP_ERR_UNSUPPORTED;
     if (workspace == nullptr || workspace_bytes < L.total || !aligned(workspace, kAlign))
         return RCP_ERR_WORKSPACE;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return RCP_ERR_HIP;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return RCP_ERR_HIP;
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return RCP_ERR_UNSUPPORTED;
-    const int cus = prop.multiProcessorCount;
-    rcp_plan_t* pl = new (std::nothrow) rcp_plan_t;
-    if (pl == nullptr) return RCP_ERR_HIP;
     pl->prob = *prob;
     pl->L = L;
     pl->stream = (hipStream_t)hip_stream;
@@ -471,6 +468,39 @@ rcp_status rcp_init(rcp_plan* plan, const rcp_problem* prob, void* workspace,
     pl->ws_bytes = workspace_bytes;
     pl->P = std::max(1, std::min(kPmax, cus));
     pl->smem_limit = kLdsBytes;
+    return RCP_OK;
+}
+
+// Compute units of the current device if it is a gfx950, else 0.
+rcp_status device_cus(int* cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RCP_ERR_HIP;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return RCP_ERR_HIP;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return RCP_ERR_UNSUPPORTED;
+    *cus = prop.multiProcessorCount;
+    return RCP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rcp_status rcp_init(rcp_plan* plan, const rcp_problem* prob, void* workspace,
+                    size_t workspace_bytes, void* hip_stream) {
+    if (plan == nullptr) return RCP_ERR_INVALID_ARG;
+    *plan = nullptr;
+    rcp_plan_t probe;
+    // argument errors before any device query
+    rcp_status st = plan_setup(&probe, prob, workspace, workspace_bytes, hip_stream, 1);
+    if (st != RCP_OK) return st;
+    int cus = 0;
+    st = device_cus(&cus);
+    if (st != RCP_OK) return st;
+    rcp_plan_t* pl = new (std::nothrow) rcp_plan_t;
+    if (pl == nullptr) return RCP_ERR_HIP;
+    st = plan_setup(pl, prob, workspace, workspace_bytes, hip_stream, cus);
+    if (st != RCP_OK) { delete pl; return st; }
     if (hipMemsetAsync(pl->status_word(), 0, sizeof(int32_t), pl->stream) != hipSuccess) {
         delete pl;
         return RCP_ERR_HIP;
@@ -672,13 +702,12 @@ ExpandArgs core_expand_args(rcp_plan_t* plan, float* const* A, float* lambda) {
 
 }  // namespace
 
-rcp_status rcp_decompose(rcp_plan plan, const float* X, float* const* A, float* lambda,
-                         rcp_als_info* info) {
-    if (plan == nullptr || X == nullptr || A == nullptr || lambda == nullptr || info == nullptr)
-        return RCP_ERR_INVALID_ARG;
-    for (int n = 0; n < plan->L.N; ++n)
-        if (A[n] == nullptr || !aligned(A[n], 4)) return RCP_ERR_INVALID_ARG;
-    if (!aligned(X, 4) || !aligned(info, 8)) return RCP_ERR_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+
+rcp_status decompose_impl(rcp_plan_t* plan, const float* X, float* const* A, float* lambda,
+                          rcp_als_info* info) {
     const Layout& L = plan->L;
     const int N = L.N;
     const float* core = nullptr;
@@ -693,6 +722,84 @@ rcp_status rcp_decompose(rcp_plan plan, const float* X, float* const* A, float* 
     const float* Atc[RCP_MAX_NDIM];
     for (int n = 0; n < N; ++n) { Qc[n] = plan->at<float>(L.qb[n]); Atc[n] = At[n]; }
     return expand_impl(plan, Qc, Atc, lam, A, lambda);
+}
+
+bool valid_outputs(int N, const float* X, float* const* A, const float* lambda,
+                   const rcp_als_info* info) {
+    if (X == nullptr || A == nullptr || lambda == nullptr || info == nullptr) return false;
+    for (int n = 0; n < N; ++n)
+        if (A[n] == nullptr || !aligned(A[n], 4)) return false;
+    return aligned(X, 4) && aligned(lambda, 4) && aligned(info, 8);
+}
+
+}  // namespace
+
+extern "C" {
+
+rcp_status rcp_decompose(rcp_plan plan, const float* X, float* const* A, float* lambda,
+                         rcp_als_info* info) {
+    if (plan == nullptr || !valid_outputs(plan->L.N, X, A, lambda, info)) return RCP_ERR_INVALID_ARG;
+    return decompose_impl(plan, X, A, lambda, info);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free whole path.  Its workspace is this file-scope device array:
+// every GPU the library runs on holds its own copy, at its own address, until
+// the process ends.  In host code the array's name is only a host-side
+// stand-in; the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current.
+static __device__ __align__(256) unsigned char scratch[RCP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+int g_scratch_cus[kMaxDevices] = {};
+
+rcp_status scratch_of_current_device(char** ptr, int* cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RCP_ERR_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return RCP_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[dev] == nullptr) {
+        int c = 0;
+        const rcp_status st = device_cus(&c);
+        if (st != RCP_OK) return st;
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+            return RCP_ERR_HIP;
+        g_scratch[dev] = (char*)p;
+        g_scratch_cus[dev] = c;
+    }
+    *ptr = g_scratch[dev];
+    *cus = g_scratch_cus[dev];
+    return RCP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rcp_status rcp_decompose_noalloc(const rcp_problem* prob, const float* X, float* const* A,
+                                 float* lambda, rcp_als_info* info, void* hip_stream) {
+    if (prob == nullptr || !valid_problem(prob)) return RCP_ERR_INVALID_ARG;
+    if (!valid_outputs(prob->ndim, X, A, lambda, info)) return RCP_ERR_INVALID_ARG;
+    const Layout L = make_layout(prob);
+    if (!als_supported(L.N, L.l, L.R)) return RCP_ERR_UNSUPPORTED;
+    if (L.total > (size_t)RCP_NOALLOC_SCRATCH_BYTES) return RCP_ERR_WORKSPACE;
+    char* ws = nullptr;
+    int cus = 0;
+    rcp_status st = scratch_of_current_device(&ws, &cus);
+    if (st != RCP_OK) return st;
+    rcp_plan_t pl;
+    st = plan_setup(&pl, prob, ws, (size_t)RCP_NOALLOC_SCRATCH_BYTES, hip_stream, cus);
+    if (st != RCP_OK) return st;
+    // the status word starts at zero (a fill kernel: no memset node under capture)
+    RCP_TRY(launch_fill_i32(pl.status_word(), 0, 1, pl.stream));
+    return decompose_impl(&pl, X, A, lambda, info);
 }
 
 // ---------------------------------------------------------------------------

@@ -64,6 +64,8 @@ struct KrSpec {
 KrSpec kr_spec(int N, int n, const int* l, int R, const float* const* fac, const int* skip);
 // partial M = B_(n) KR (per workgroup, I x 16*ceil(R/16)) for the reduction
 hipError_t launch_mttkrp(const StreamGeom& g, const KrSpec& kr, float* part, int P, hipStream_t s);
+// p[0..n) <- v (a kernel, not a memset node, so that it can sit in a captured graph)
+hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
 // Qpad (I x ldq) <- the identity padded with zero columns
 hipError_t launch_eye(float* Qpad, int64_t I, int ldq, hipStream_t s);
 int reduce_split(int P);

@@ -116,8 +116,19 @@ __global__ __launch_bounds__(NT) void k_eye(float* Qpad, int64_t I, int ldq) {
     Qpad[e] = (e - i * ldq == i) ? 1.0f : 0.0f;
 }
 
+__global__ __launch_bounds__(NT) void k_fill_i32(int* p, int v, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e < n) p[e] = v;
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launchers.
+
+hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, p, v, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_eye(float* Qpad, int64_t I, int ldq, hipStream_t s) {
     const int64_t n = I * ldq;
