@@ -13,6 +13,9 @@ Follows the paper step by step:
                               column normalisation, eigenvector
                               initialisation, back-projection A_n = Q_n Ã_n
                               (eq. qbs) and a final renormalisation.
+  Section 3.2.2 / Algorithm 3 block coordinate descent on the compressed
+                              tensor: rank-one components found one after
+                              another on the implicitly deflated residual.
   Section 3.3                 the fit rho used for the stopping rule.
 
 Conventions (readings where the paper is silent; all listed with reasons in
@@ -337,6 +340,102 @@ def als(B: np.ndarray, R: int, max_iters: int, tol: float = 0.0,
     return ALSResult(factors=A, lam=lam, rho=rho, iters=it, rho_history=hist)
 
 
+# ---------------------------------------------------------------------------
+# Block coordinate descent on the core (Section 3.2.2, Algorithm 3)
+
+@dataclass
+class BCDResult:
+    factors: List[np.ndarray]
+    lam: np.ndarray
+    rho: float
+    iters: int                      # sweeps summed over the R components
+    component_iters: List[int] = field(default_factory=list)
+    rho_history: List[float] = field(default_factory=list)
+
+
+def bcd_fit(B: np.ndarray, factors: Sequence[np.ndarray], lam: np.ndarray, r: int,
+            normX2: float) -> float:
+    """rho = 1 - ||X - Xhat||^2 / ||X||^2 (Section 3.3) for the model made of
+    components 0..r, evaluated on the core as in ``als``:
+    ||X - Xhat||^2 = ||X||^2 - 2 <B, Bhat> + ||Bhat||^2."""
+    N = B.ndim
+    idx = list(range(r + 1))
+    Fs = [f[:, idx] for f in factors]
+    lr = np.asarray(lam, dtype=np.float64)[idx]
+    M = mttkrp(B, Fs, N - 1)
+    inner = float(np.sum(lr * np.sum(M * Fs[N - 1], axis=0)))
+    model = float(lr @ gram_hadamard(Fs, skip=None) @ lr)
+    err2 = normX2 - 2.0 * inner + model
+    return 1.0 - err2 / normX2 if normX2 > 0 else 0.0
+
+
+def bcd(B: np.ndarray, R: int, max_iters: int, tol: float = 0.0,
+        normX2: Optional[float] = None, init: Optional[Sequence[np.ndarray]] = None) -> BCDResult:
+    """Rank-one block coordinate descent on B (Algorithm 3 steps 2-15).
+
+    The components are found one after another.  For component r the
+    residual is Y = B - sum_{s<r} lam_s a_s^(0) o ... o a_s^(N-1) (step 14),
+    and the sweeps update its blocks in mode order:
+        a_r^(n) = Y_(n) (KR_{m != n} a_r^(m)) / prod_{m != n} <a_r^(m), a_r^(m)>
+    (steps 6, 8, 10: the least-squares update of one block, the
+    pseudo-inverse of the scalar Gram product), scaled to unit norm for
+    n < N-1 and split into lam_r and a unit vector for n = N-1 (steps 7, 9,
+    11, 12).  Y is never formed (the remark before Algorithm 3): by
+    multilinearity
+        Y_(n) (KR a_r) = B_(n) (KR a_r)
+                         - sum_{s<r} lam_s a_s^(n) prod_{m != n} <a_s^(m), a_r^(m)>.
+    Starting vectors (step 2): column r of the leading eigenvectors of
+    B_(n) B_(n)^T for modes 1..N-1; mode 0 is updated first.
+    Stopping (step 13): after sweep j >= 2 of a component once the fit
+    (``bcd_fit`` of components 0..r) changes by less than tol; tol = 0 runs
+    exactly max_iters sweeps per component.
+    """
+    B = np.asarray(B, dtype=np.float64)
+    N = B.ndim
+    normB2 = float(np.dot(B.ravel(), B.ravel()))
+    if normX2 is None:
+        normX2 = normB2
+    if init is None:
+        A = [np.zeros((B.shape[0], R))] + [eig_init(B, R, n) for n in range(1, N)]
+    else:
+        A = [np.array(a, dtype=np.float64) for a in init]
+    lam = np.zeros(R)
+    hist, comp_iters = [], []
+    rho = 0.0
+    total = 0
+    for r in range(R):
+        rho_prev = None
+        it = 0
+        for it in range(1, int(max_iters) + 1):
+            for n in range(N):
+                cols = [A[m][:, r:r + 1] for m in range(N)]
+                v = mttkrp(B, cols, n)[:, 0]
+                for s in range(r):
+                    w = 1.0
+                    for m in range(N):
+                        if m != n:
+                            w *= float(A[m][:, s] @ A[m][:, r])
+                    v = v - lam[s] * w * A[n][:, s]
+                d = 1.0
+                for m in range(N):
+                    if m != n:
+                        d *= float(A[m][:, r] @ A[m][:, r])
+                v = v / d if d > 0 else np.zeros_like(v)
+                nu = float(np.sqrt(v @ v))
+                A[n][:, r] = v / nu if nu > 0 else v
+                if n == N - 1:
+                    lam[r] = nu
+            rho = bcd_fit(B, A, lam, r, normX2)
+            hist.append(rho)
+            if tol > 0 and rho_prev is not None and abs(rho - rho_prev) < tol:
+                break
+            rho_prev = rho
+        comp_iters.append(it)
+        total += it
+    return BCDResult(factors=A, lam=lam, rho=rho, iters=total, component_iters=comp_iters,
+                     rho_history=hist)
+
+
 def finalize(lam: np.ndarray, factors: Sequence[np.ndarray]):
     """Algorithm 2 step 13: re-normalise the columns, fold the norms into
     lambda, sort by lambda (descending) and fix signs (largest-magnitude
@@ -390,6 +489,31 @@ def rcp_als(X: np.ndarray, R: int, p: int = 10, q: int = 2, max_iters: int = 50,
     rel = float(np.sqrt(max(0.0, 1.0 - res.rho)))
     return RCPResult(lam=lam, factors=A, rho=res.rho, rel_err=rel, iters=res.iters,
                      compression=comp, als=res)
+
+
+def rcp_bcd(X: np.ndarray, R: int, p: int = 10, q: int = 2, max_iters: int = 50,
+            tol: float = 0.0, seed: int = 0, scheme: str = "sequential",
+            normalizer: str = "qr", batch: int = 0) -> RCPResult:
+    """Randomized CP via block coordinate descent (Algorithm 3): the same
+    compression as ``rcp_als`` (step 1), ``bcd`` on the core (steps 2-15),
+    back-projection and renormalisation (steps 16-17)."""
+    X = np.asarray(X, dtype=np.float64)
+    normX2 = float(np.dot(X.ravel(), X.ravel()))
+    comp = compress(X, R, p, q, seed, batch, scheme, normalizer)
+    res = bcd(comp.core, R, max_iters, tol, normX2=normX2)
+    lam, A = expand(comp.Q, res.factors, res.lam)
+    rel = float(np.sqrt(max(0.0, 1.0 - res.rho)))
+    return RCPResult(lam=lam, factors=A, rho=res.rho, rel_err=rel, iters=res.iters,
+                     compression=comp, als=res)
+
+
+def cp_bcd(X: np.ndarray, R: int, max_iters: int = 50, tol: float = 0.0):
+    """Deterministic CP via block coordinate descent on the full tensor (the
+    solver of Algorithm 3 with Q_n = I)."""
+    X = np.asarray(X, dtype=np.float64)
+    res = bcd(X, R, max_iters, tol)
+    lam, A = finalize(res.lam, res.factors)
+    return lam, A, res
 
 
 def cp_als(X: np.ndarray, R: int, max_iters: int = 50, tol: float = 0.0):

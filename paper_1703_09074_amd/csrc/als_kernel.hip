@@ -259,8 +259,8 @@ __device__ __forceinline__ bool eig_init(const AlsCtx& c, const float* Bg, int n
 // transpose into the right part of the augmented system.
 template <int NN>
 __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, const int* st,
-                                       const float* ones, float* P, double* M, double* Xt,
-                                       int ldx) {
+                                       const float* ones, float* P, int pfloats, double* M,
+                                       double* Xt, int ldx) {
     constexpr int D = NN - 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
@@ -283,7 +283,9 @@ __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, c
     const float* fin = c.fbase + fo[D - 1];
     const int nib = (ln + 15) >> 4, ncb = (R + 15) >> 4;
     const int blocks = nib * ncb;
-    const int kp = (blocks >= ANW) ? 1 : min(ANW / blocks, Ko);
+    // slices of the outer index per block, as many as idle wavefronts and
+    // the pfloats of LDS for their partial blocks allow
+    const int kp = (blocks >= ANW) ? 1 : min(min(ANW / blocks, Ko), 1 + pfloats / (blocks * 256));
     const int units = blocks * kp;
     const int per = (Ko + kp - 1) / kp;
     f32x4 keep = {0.f, 0.f, 0.f, 0.f};
@@ -451,189 +453,140 @@ __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, c
     }
 }
 
-// Blocked Gauss-Jordan elimination without pivoting on the augmented system
-// Aug = [V | Xt] (Rp x (Rp + ln), row stride ldx), V symmetric positive
-// definite (padded with identity up to Rp, a multiple of GB): on return the
-// right part holds V^{-1} Xt.  GB pivots per step: the update of entry
-// (i, c) is a_ic - sum_t f_it u_tc with u = P^{-1} p_c, P the GB x GB pivot
-// block (plain Gauss-Jordan inverse, whose pivots are the successive Schur
-// complements, i.e. the pivots of unblocked elimination), p_c and f_i the
-// pivot rows and columns.  Wavefront 0 owns the next pivot block: it updates
-// those GB x GB entries itself, inverts the result and publishes the inverse
-// while the other wavefronts update the rest, so nobody inverts on the
-// critical path of a step and a step needs one barrier.  The pivot rows and
-// columns of the next step go to the other half of a double buffer.
-// Columns left of the pivot block are never read again and are not updated.
-// pb holds 2 GB (ldx + Rp) + 2 GB^2 + 1 doubles.  Returns 0 when a pivot of
-// the first R is not above thr.
-constexpr int GB = 4;
+// Inverse of the pivot block P = A[0..pbs) x [0..pbs) (row stride lda; a
+// 16 x 16 block padded with the identity past pbs) in one wavefront's
+// registers: Gauss-Jordan on [P | I] with lane c holding column c (lanes
+// 0..15 P, 16..31 I) and the rows rotating through the registers so that the
+// pivot row is always register 0; the pivot column is read into scalar
+// registers before each step's updates.  P^{-1} goes to Pinv (16 x 16).
+// Returns 0 if a pivot of the first rreal rows is not above thr (or is NaN).
+__device__ __forceinline__ int invert16_wave(const double* A, int lda, int pbs, int rreal, double thr,
+                                             double* Pinv) {
+    const int c = threadIdx.x & 63;
+    double col[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        double v = 0.0;
+        if (c < 16) v = (i < pbs && c < pbs) ? A[i * lda + c] : ((i == c) ? 1.0 : 0.0);
+        else if (c < 32) v = (c - 16 == i) ? 1.0 : 0.0;
+        col[i] = v;
+    }
+    double pmin = __builtin_huge_val();
+    bool pnan = false;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        double sk[16];
+        sk[0] = readlane_f64(col[0], k);
+        const double u = col[0] / sk[0];
+#pragma unroll
+        for (int i = 1; i < 16; ++i) sk[i] = readlane_f64(col[i], k);
+        __builtin_amdgcn_sched_barrier(0);
+        if (k < rreal) {
+            pmin = fmin(pmin, sk[0]);
+            pnan = pnan || (sk[0] != sk[0]);
+        }
+#pragma unroll
+        for (int i = 1; i < 16; ++i) col[i] -= sk[i] * u;
+#pragma unroll
+        for (int i = 0; i < 15; ++i) col[i] = col[i + 1];
+        col[15] = u;
+    }
+    if (c >= 16 && c < 32) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Pinv[i * 16 + (c - 16)] = col[i];
+    }
+    return (!pnan && (rreal == 0 || pmin > thr)) ? 1 : 0;
+}
 
-// Gauss-Jordan inverse of the GB x GB block m (destroyed); pivots of rows
-// row0 + t < R must exceed thr.
-__device__ __forceinline__ int invert_block(double (&m)[GB][GB], double (&inv)[GB][GB], int row0,
-                                            int R, double thr) {
-    int ok = 1;
+// Blocked Gauss-Jordan elimination without pivoting on the augmented system
+// Aug = [V | Xt] (Rp x W, row stride ldx, V symmetric positive definite and
+// padded with the identity up to Rp): on return columns Rp..W-1 hold
+// V^{-1} Xt.  Pivot blocks of up to 16 rows; per block j0 (pbs rows):
+//   1. wavefront 0 inverts the pivot block P in its registers;
+//   2. the pivot rows become P^{-1} [pivot rows] (float64 matrix cores);
+//   3. every other row block i loses F_i [pivot rows], F_i its entries in the
+//      pivot columns (matrix cores).
+// The pivots of the inverted blocks are the Schur complements, i.e. the
+// pivots of unblocked elimination, and each must exceed rtol times the
+// largest of V's first R diagonal entries for the rows < R.  Columns left of the pivot block are never read again and are not
+// updated; every column block is read whole before it is written, so the
+// updates run in place.  pb holds 258 doubles (P^{-1} and the flag).
+__device__ __forceinline__ int block16_gj(double* Aug, int ldx, int R, int Rp, int W, double rtol,
+                                          double* pb) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    double* Pinv = pb;
+    double* okp = pb + 256;
+    if (threadIdx.x == 0) *okp = 1.0;
+    // the pivot threshold, needed by wavefront 0 only (R <= 64 = one lane per row)
+    double thr = 0.0;
+    if (wave == 0) {
+        double d = (lane < R) ? Aug[lane * ldx + lane] : 0.0;
 #pragma unroll
-    for (int t = 0; t < GB; ++t)
+        for (int o = 32; o > 0; o >>= 1) d = fmax(d, __shfl_xor(d, o, 64));
+        thr = rtol * d;
+    }
+    const int nrb = (Rp + 15) >> 4;
+    for (int j0 = 0; j0 < Rp; j0 += 16) {
+        const int pbs = min(16, Rp - j0);
+        const int rreal = max(0, min(pbs, R - j0));
+        if (wave == 0) {
+            const int ok = invert16_wave(Aug + j0 * ldx + j0, ldx, pbs, rreal, thr, Pinv);
+            if (lane == 0 && !ok) *okp = 0.0;
+        }
+        __syncthreads();
+        const int c0 = j0 + pbs;                   // first column to update
+        const int ncb = (W - c0 + 15) >> 4;
+        // 2. pivot rows <- P^{-1} pivot rows
+        for (int cb = wave; cb < ncb; cb += ANW) {
+            const int cc = c0 + cb * 16 + li;
+            const bool cv = cc < W;
+            double bop[4], aop[4];
 #pragma unroll
-        for (int s2 = 0; s2 < GB; ++s2) inv[t][s2] = (t == s2) ? 1.0 : 0.0;
+            for (int kk = 0; kk < 4; ++kk) {
+                const int sr = 4 * kk + lk;
+                bop[kk] = (sr < pbs && cv) ? Aug[(j0 + sr) * ldx + cc] : 0.0;
+                aop[kk] = Pinv[li * 16 + sr];
+            }
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int t = 0; t < GB; ++t) {
-        const double piv = m[t][t];
-        const bool real = row0 + t < R;
-        if (real && !(piv > thr)) ok = 0;
-        const double ip = 1.0 / (piv > thr ? piv : (real ? thr : 1.0));
+            for (int kk = 0; kk < 4; ++kk) acc = mfma64(aop[kk], bop[kk], acc);
 #pragma unroll
-        for (int s2 = 0; s2 < GB; ++s2) { m[t][s2] *= ip; inv[t][s2] *= ip; }
-#pragma unroll
-        for (int r = 0; r < GB; ++r) {
-            if (r == t) continue;
-            const double f = m[r][t];
-#pragma unroll
-            for (int s2 = 0; s2 < GB; ++s2) {
-                m[r][s2] -= f * m[t][s2];
-                inv[r][s2] -= f * inv[t][s2];
+            for (int v = 0; v < 4; ++v) {
+                const int t = lk + 4 * v;
+                if (t < pbs && cv) Aug[(j0 + t) * ldx + cc] = acc[v];
             }
         }
-    }
-    return ok;
-}
-
-// entry e = t GB + s of a register block, selected without dynamic indexing
-__device__ __forceinline__ double pick_block(const double (&m)[GB][GB], int e) {
-    double v = 0.0;
+        __syncthreads();
+        // 3. other row blocks: A_ic -= F_i [pivot rows]
+        const int units = (nrb - 1) * ncb;
+        for (int u = wave; u < units; u += ANW) {
+            int rb = u / ncb;
+            const int cb = u - rb * ncb;
+            if (rb >= (j0 >> 4)) ++rb;            // skip the pivot block
+            const int i0 = rb * 16;
+            const int cc = c0 + cb * 16 + li;
+            const bool cv = cc < W;
+            double aop[4], bop[4];
 #pragma unroll
-    for (int t = 0; t < GB; ++t)
-#pragma unroll
-        for (int s2 = 0; s2 < GB; ++s2)
-            if (e == t * GB + s2) v = m[t][s2];
-    return v;
-}
-
-__device__ __forceinline__ int block_gj(double* Aug, int ldx, int R, int Rp, int ln, double* pb,
-                                        double thr) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int W = Rp + ln;
-    double* prow0 = pb;                              // [2][GB][ldx]
-    double* pcol0 = pb + 2 * GB * ldx;               // [2][GB][Rp]
-    double* pinv0 = pcol0 + 2 * GB * Rp;             // [2][GB][GB]
-    double* okp = pinv0 + 2 * GB * GB;               // 1.0 while every pivot is fine
-    for (int e = tid; e < GB * W; e += ANT) {
-        const int t = e / W, cc = e - (e / W) * W;
-        prow0[t * ldx + cc] = Aug[t * ldx + cc];
-    }
-    for (int e = tid; e < GB * Rp; e += ANT) {
-        const int t = e / Rp, i = e - (e / Rp) * Rp;
-        pcol0[t * Rp + i] = Aug[i * ldx + t];
-    }
-    if (wave == 0) {
-        double m[GB][GB], inv[GB][GB];
-#pragma unroll
-        for (int t = 0; t < GB; ++t)
-#pragma unroll
-            for (int s2 = 0; s2 < GB; ++s2) m[t][s2] = Aug[t * ldx + s2];
-        const int ok = invert_block(m, inv, 0, R, thr);
-        if (lane < GB * GB) pinv0[lane] = pick_block(inv, lane);
-        if (lane == 0) *okp = ok ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    for (int j = 0; j < Rp; j += GB) {
-        const int cur = (j / GB) & 1, nxt = cur ^ 1;
-        const double* pr = prow0 + cur * GB * ldx;
-        const double* pc = pcol0 + cur * GB * Rp;
-        const double* pv = pinv0 + cur * GB * GB;
-        double* nr = prow0 + nxt * GB * ldx;
-        double* nc = pcol0 + nxt * GB * Rp;
-        double inv[GB][GB];
-#pragma unroll
-        for (int t = 0; t < GB; ++t)
-#pragma unroll
-            for (int s2 = 0; s2 < GB; ++s2) inv[t][s2] = pv[t * GB + s2];
-        const int jn = j + GB;                       // first row / column of the next block
-        // update of entry (i, cc) of this step, the same arithmetic for everyone
-        auto updated = [&](int i, int cc) -> double {
-            double p[GB], u[GB];
-#pragma unroll
-            for (int t = 0; t < GB; ++t) p[t] = pr[t * ldx + cc];
-#pragma unroll
-            for (int t = 0; t < GB; ++t) {
-                double acc = 0.0;
-#pragma unroll
-                for (int s2 = 0; s2 < GB; ++s2) acc += inv[t][s2] * p[s2];
-                u[t] = acc;
+            for (int kk = 0; kk < 4; ++kk) {
+                const int sr = 4 * kk + lk;
+                const int ri = i0 + li;
+                aop[kk] = (sr < pbs && ri < Rp) ? -Aug[ri * ldx + j0 + sr] : 0.0;
+                bop[kk] = (sr < pbs && cv) ? Aug[(j0 + sr) * ldx + cc] : 0.0;
             }
-            const int ti = i - j;
-            double na;
-            if (ti >= 0 && ti < GB) {
-                na = u[0];
+            f64x4 acc;
 #pragma unroll
-                for (int t = 1; t < GB; ++t) if (ti == t) na = u[t];
-            } else {
-                na = Aug[i * ldx + cc];
-#pragma unroll
-                for (int t = 0; t < GB; ++t) na -= pc[t * Rp + i] * u[t];
+            for (int v = 0; v < 4; ++v) {
+                const int ri = i0 + lk + 4 * v;
+                acc[v] = (ri < Rp && cv) ? Aug[ri * ldx + cc] : 0.0;
             }
-            return na;
-        };
-        if (wave == 0) {
-            if (jn < Rp) {
-                // the next pivot block: update, gather, invert, publish
-                const int tn = (lane >> 2) & (GB - 1), cn = lane & (GB - 1);
-                double na = 0.0;
-                if (lane < GB * GB) {
-                    const int i = jn + tn, cc = jn + cn;
-                    na = updated(i, cc);
-                    Aug[i * ldx + cc] = na;
-                    nr[tn * ldx + cc] = na;
-                    nc[cn * Rp + i] = na;
-                }
-                double m[GB][GB], inv2[GB][GB];
 #pragma unroll
-                for (int t = 0; t < GB; ++t)
+            for (int kk = 0; kk < 4; ++kk) acc = mfma64(aop[kk], bop[kk], acc);
 #pragma unroll
-                    for (int s2 = 0; s2 < GB; ++s2) m[t][s2] = __shfl(na, t * GB + s2, 64);
-                const int ok = invert_block(m, inv2, jn, R, thr);
-                if (lane < GB * GB) pinv0[nxt * GB * GB + lane] = pick_block(inv2, lane);
-                if (lane == 0 && !ok) *okp = 0.0;
-            }
-        } else {
-            // thread t owns column jn + t % wc and rows t / wc, + G, ... so that
-            // u = P^{-1} p of its column is formed once
-            const int wc = W - jn;
-            const int G = max(1, (ANT - 64) / wc);
-            const int t = tid - 64;
-            if (t < G * wc) {
-                const int g = small_div(t, wc, __builtin_amdgcn_rcpf((float)wc));
-                const int cc = jn + (t - g * wc);
-                const int cn = cc - jn;
-                double p[GB], u[GB];
-#pragma unroll
-                for (int q = 0; q < GB; ++q) p[q] = pr[q * ldx + cc];
-#pragma unroll
-                for (int q = 0; q < GB; ++q) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int s2 = 0; s2 < GB; ++s2) acc += inv[q][s2] * p[s2];
-                    u[q] = acc;
-                }
-                for (int i = g; i < Rp; i += G) {
-                    const int tn = i - jn;
-                    if (tn >= 0 && tn < GB && cn < GB) continue;     // wavefront 0's block
-                    const int ti = i - j;
-                    double na;
-                    if (ti >= 0 && ti < GB) {
-                        na = u[0];
-#pragma unroll
-                        for (int q = 1; q < GB; ++q) if (ti == q) na = u[q];
-                    } else {
-                        na = Aug[i * ldx + cc];
-#pragma unroll
-                        for (int q = 0; q < GB; ++q) na -= pc[q * Rp + i] * u[q];
-                    }
-                    Aug[i * ldx + cc] = na;
-                    if (tn >= 0 && tn < GB) nr[tn * ldx + cc] = na;
-                    if (cn < GB) nc[cn * Rp + i] = na;
-                }
+            for (int v = 0; v < 4; ++v) {
+                const int ri = i0 + lk + 4 * v;
+                if (ri < Rp && cv) Aug[ri * ldx + cc] = acc[v];
             }
         }
         __syncthreads();
@@ -647,9 +600,11 @@ __device__ __forceinline__ int block_gj(double* Aug, int ldx, int R, int Rp, int
 __host__ __device__ inline int aug_ld(int Rp, int lmax) { return (Rp + lmax) | 1; }
 
 // doubles of LDS the solvers need beside the augmented system (the blocked
-// one's pivot rows, columns and inverses; the one-wavefront one's flag)
+// one's pivot-block inverse and flag; the one-wavefront one's flag)
 __host__ __device__ inline int gj_buf_doubles(int ldx, int Rp) {
-    return 2 * GB * (ldx + Rp) + 2 * GB * GB + 1;
+    (void)ldx;
+    (void)Rp;
+    return 258;
 }
 
 // One-wavefront variant for small systems (Rp <= 32 rows, W <= 64 columns):
@@ -729,9 +684,7 @@ __device__ __forceinline__ int gj_solve(double* Aug, int ldx, int R, int Rp, int
         __syncthreads();
         return fbuf[0] != 0.0;
     }
-    double dmax = 0.0;
-    for (int r = 0; r < R; ++r) dmax = fmax(dmax, Aug[r * ldx + r]);
-    return block_gj(Aug, ldx, R, Rp, W - Rp, fbuf, rtol * dmax);
+    return block16_gj(Aug, ldx, R, Rp, W, rtol, fbuf);
 }
 
 // Left block of the augmented system: V = *_{m != n} G_m, identity padding up
@@ -955,7 +908,8 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
     double* G = (double*)p;  p += (size_t)N * R * R * sizeof(double);
     double* Aug = (double*)p; p += (size_t)Rp * ldx * sizeof(double);
     double* pb = (double*)p; p += (size_t)gj_buf_doubles(ldx, Rp) * sizeof(double);
-    float* P = (float*)p;    p += (size_t)als_part_floats(N, a.l, R) * sizeof(float);
+    const int pfl = als_part_floats(N, a.l, R);
+    float* P = (float*)p;    p += (size_t)pfl * sizeof(float);
     double* M = a.Ebuf + 2 * kEigLd * kEigLd;            // l_n x R, global (read by the fit and the fallback)
     double* E = EIG_IN_LDS ? (double*)p : a.Ebuf;
     double* Ev = E + kEigLd * kEigLd;
@@ -992,7 +946,7 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
     for (it = 1; it <= a.max_iters; ++it) {
         for (int n = 0; n < N; ++n) {
             hadamard_grams(c, n, G, Aug, ldx, Rp, c.l[n]);
-            mttkrp<NN>(c, n, Bs, sst, ones, P, M, Aug + Rp, ldx);
+            mttkrp<NN>(c, n, Bs, sst, ones, P, pfl, M, Aug + Rp, ldx);
             __syncthreads();
             status |= solve_update(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs,
                                    (n == N - 1) ? lam : lam_tmp);
@@ -1091,16 +1045,22 @@ __device__ __forceinline__ void wide_ctx(const AlsArgs& a, AlsCtx& c, int* sl, i
     __syncthreads();
 }
 
-// Algorithm 2 step 2 for mode n (>= 1) from the Gram B_(n) B_(n)^T (upper
-// triangle of a.Y, row stride a.ldy); mode 1 also resets the sweep state.
-__global__ __launch_bounds__(ANT) void k_als_wide_init(AlsArgs a, int n) {
+// Algorithm 2 step 2 for every mode n >= 1 at once, workgroup n - 1 taking
+// mode n: the leading eigenvectors of the Gram B_(n) B_(n)^T (upper triangle
+// at a.Y + (n - 1) ystride, row stride l_n rounded up to 16).  The sweep
+// state is cleared beforehand by the host; a non-converged Jacobi or-s its
+// bit into it.
+__global__ __launch_bounds__(ANT) void k_als_wide_init(AlsArgs a, int ystride) {
     extern __shared__ __align__(16) unsigned char als_smem[];
     __shared__ double red[ANW];
     __shared__ double sh[128];
     __shared__ int sl[RCP_MAX_NDIM];
     __shared__ int sfoff[RCP_MAX_NDIM];
     const int tid = threadIdx.x;
+    const int n = 1 + (int)blockIdx.x;
     const int R = a.R, ln = a.l[n];
+    const int ldy = (ln + 15) & ~15;
+    const double* Y = a.Y + (size_t)(n - 1) * ystride;
     double* E = (double*)als_smem;
     double* V = E + kEigLd * kEigLd;
     AlsCtx c;
@@ -1108,25 +1068,14 @@ __global__ __launch_bounds__(ANT) void k_als_wide_init(AlsArgs a, int n) {
     for (int e = tid; e < ln * ln; e += ANT) {
         const int i = e / ln, j = e - (e / ln) * ln;
         const int lo = min(i, j), hi = max(i, j);
-        E[i * kEigLd + j] = a.Y[lo * a.ldy + hi];
+        E[i * kEigLd + j] = Y[lo * ldy + hi];
     }
     __syncthreads();
     const bool ok = eig_leading(c, n, E, V);
     double* G = a.state + kStG;
     gram_mfma(c.fac(n), ln, R, G + n * R * R);
     for (int e = tid; e < ln * R; e += ANT) a.At[n][e] = c.fac(n)[e];
-    if (tid == 0) {
-        int* fl = (int*)a.state;
-        const int bit = ok ? 0 : RCP_INFO_EIG_NOT_CONVERGED;
-        if (n == 1) {
-            fl[0] = 0;
-            fl[1] = 0;
-            fl[2] = bit;
-            a.state[2] = 0.0;
-        } else {
-            fl[2] |= bit;
-        }
-    }
+    if (tid == 0 && !ok) atomicOr((int*)a.state + 2, RCP_INFO_EIG_NOT_CONVERGED);
 }
 
 // Algorithm 2 steps 4-10 for mode n of one sweep from M_n in a.Y (row
@@ -1297,13 +1246,15 @@ static size_t wide_step_lds(const AlsArgs& a) {
            (size_t)lmax * a.R * sizeof(float);
 }
 
-hipError_t launch_als_wide_init(const AlsArgs& a, int n, hipStream_t s) {
-    if (n < 1 || n >= a.N || a.Y == nullptr || a.state == nullptr) return hipErrorInvalidValue;
-    const size_t smem = 2 * kEigLd * kEigLd * sizeof(double) + (size_t)a.l[n] * a.R * sizeof(float);
+hipError_t launch_als_wide_init(const AlsArgs& a, int ystride, hipStream_t s) {
+    if (a.N < 2 || a.Y == nullptr || a.state == nullptr) return hipErrorInvalidValue;
+    int lmax = 0;
+    for (int m = 0; m < a.N; ++m) lmax = lmax > a.l[m] ? lmax : a.l[m];
+    const size_t smem = 2 * kEigLd * kEigLd * sizeof(double) + (size_t)lmax * a.R * sizeof(float);
     hipError_t e = hipFuncSetAttribute((const void*)k_als_wide_init,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kAlsLds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_als_wide_init, dim3(1), dim3(ANT), smem, s, a, n);
+    hipLaunchKernelGGL(k_als_wide_init, dim3((unsigned)(a.N - 1)), dim3(ANT), smem, s, a, ystride);
     return hipGetLastError();
 }
 

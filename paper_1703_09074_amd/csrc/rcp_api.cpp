@@ -33,7 +33,8 @@ struct Layout {
     int LPmax;
     // offsets (bytes)
     size_t part, red1, y64, qt, sq, norm, status, qb[RCP_MAX_NDIM], tb[2], zbuf, als, alsst,
-        at[RCP_MAX_NDIM], lam, raw, total;
+        at[RCP_MAX_NDIM], lam, raw, egram, total;
+    int egram_stride;      // doubles per mode of egram
     size_t part_elems, tb_elems[2], zbuf_elems, als_doubles;
     int64_t core_dims[RCP_MAX_NDIM];
 };
@@ -125,6 +126,15 @@ Layout make_layout(const rcp_problem* p) {
     size_t raw = 0;
     for (int n = 0; n < L.N; ++n) raw += (size_t)L.dims[n] * L.R;
     L.raw = take(raw * sizeof(double));
+    // the eigenvector start of a core larger than LDS: the Grams of modes
+    // 1..N-1 side by side
+    L.egram_stride = 0;
+    if (!als_core_in_lds(L.N, L.l, L.R)) {
+        int lmax = 0;
+        for (int n = 0; n < L.N; ++n) lmax = std::max(lmax, L.l[n]);
+        L.egram_stride = lmax * lp_of(lmax);
+        L.egram = take((size_t)(L.N - 1) * L.egram_stride * sizeof(double));
+    }
     L.total = off;
     return L;
 }
@@ -335,19 +345,27 @@ hipError_t als_wide(rcp_plan_t* pl, AlsArgs a) {
         hipError_t e = launch_als_wide_warm(a, pl->stream);
         if (e != hipSuccess) return e;
     }
-    // Algorithm 2 step 2: Grams B_(n) B_(n)^T as Y = T (T^T I) over the GPU
-    for (int n = 1; n < N && !a.warm; ++n) {
-        const StreamGeom g = make_geom(a.B, cd, N, n);
-        const int P = (int)std::max<int64_t>(1, std::min<int64_t>(pl->P, g.ntiles));
-        const int LPn = lp_of(L.l[n]);
-        float* eye = pl->at<float>(L.qt);
-        hipError_t e = launch_eye(eye, L.l[n], LPn, pl->stream);
-        if (e == hipSuccess) e = launch_power_fused(g, L.l[n], eye, part, P, pl->stream, RCP_PREC_FP32);
-        if (e == hipSuccess)
-            e = launch_reduce_partials(part, P, (int64_t)L.l[n] * LPn, red1, Y, nullptr, 0, nullptr,
-                                       pl->stream);
-        a.ldy = LPn;
-        if (e == hipSuccess) e = launch_als_wide_init(a, n, pl->stream);
+    if (!a.warm) {
+        // Algorithm 2 step 2: the Grams B_(n) B_(n)^T as Y = T (T^T I) over the
+        // GPU, side by side, then every mode's eigenvectors at once
+        double* eg = pl->at<double>(L.egram);
+        for (int n = 1; n < N; ++n) {
+            const StreamGeom g = make_geom(a.B, cd, N, n);
+            const int P = (int)std::max<int64_t>(1, std::min<int64_t>(pl->P, g.ntiles));
+            const int LPn = lp_of(L.l[n]);
+            float* eye = pl->at<float>(L.qt);
+            hipError_t e = launch_eye(eye, L.l[n], LPn, pl->stream);
+            if (e == hipSuccess) e = launch_power_fused(g, L.l[n], eye, part, P, pl->stream, RCP_PREC_FP32);
+            if (e == hipSuccess)
+                e = launch_reduce_partials(part, P, (int64_t)L.l[n] * LPn, red1,
+                                           eg + (size_t)(n - 1) * L.egram_stride, nullptr, 0,
+                                           nullptr, pl->stream);
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = launch_fill_i32((int*)state, 0, 6, pl->stream);   // flags and rho
+        AlsArgs ai = a;
+        ai.Y = eg;
+        if (e == hipSuccess) e = launch_als_wide_init(ai, L.egram_stride, pl->stream);
         if (e != hipSuccess) return e;
     }
     const float* facs[RCP_MAX_NDIM];

@@ -268,6 +268,43 @@ def test_als_grid_wide_matches_oracle(dims, R, iters, tol):
     assert abs(info2["rho"] - ref2.rho) <= 1e-6, (info2["rho"], ref2.rho)
 
 
+def test_als_grid_wide_under_graph_capture():
+    """The grid-wide ALS (mode products over the whole GPU, float64
+    reductions, one-workgroup solves, a device-side stop flag) recorded into a
+    HIP graph: three replays (with eager work in between) each match the
+    oracle like the eager run does.  Eight sweeps from the eigenvector start
+    on this core amplify the float32 rounding of the mode products to a few
+    1e-7 in the fit, hence 5e-7 here."""
+    dims, R, iters = (60, 55, 50), 40, 8
+    w, comp = _core_problem(dims, R, 0.05, 29, R, 5, 1)
+    core = _dev(comp.core.astype(np.float32))
+    normX2 = float(np.sum(w.X.astype(np.float64) ** 2))
+    ref = rcp.als(comp.core.astype(np.float32).astype(np.float64), R, iters, normX2=normX2)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan = rcpgpu.Plan(dims, R, 5, 1, iters, 0.0, 29)
+        nx = torch.tensor([normX2], dtype=torch.float64, device="cuda")
+        At_e, lam_e, info_e = plan.als(core, nx)             # eager
+    torch.cuda.synchronize()
+    eager = rcpgpu.Plan.read_info(info_e)
+    assert abs(eager["rho"] - ref.rho) <= 5e-7, (eager["rho"], ref.rho)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        At_g, lam_g, info_g = plan.als(core, nx)
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        got = rcpgpu.Plan.read_info(info_g)
+        assert got["iters"] == iters and got["status"] == 0, got
+        assert abs(got["rho"] - ref.rho) <= 5e-7, (rep, got["rho"], ref.rho)
+        cong, cmin, perm = evaluate.congruence([_np(a) for a in At_g], ref.factors)
+        assert cmin >= 0.999, cmin
+        np.testing.assert_allclose(_np(lam_g), ref.lam[perm], rtol=1e-4)
+        lam_g.zero_()
+        info_g.zero_()
+        torch.cuda.synchronize()
+
+
 def test_expand_matches_oracle():
     dims, R = (50, 40, 30), 4
     w, comp = _core_problem(dims, R, 0.05, 12, R, 6, 1)

@@ -7,6 +7,7 @@ import pytest
 import oracle.philox as philox
 import oracle.rcp as rcp
 from tests import test_oracle_algebra as alg
+from tests import test_oracle_bcd as tbcd
 from tests import test_oracle_philox as tph
 from tests import test_oracle_rcp as trcp
 
@@ -172,3 +173,52 @@ def test_wrong_fit_sign_is_caught(monkeypatch):
     monkeypatch.setattr(rcp, "gram_hadamard", gh)
     with pytest.raises(AssertionError):
         trcp.test_fit_identity_matches_brute_force()
+
+
+def _bcd_variant(drop_deflation=False, wrong_vector=False):
+    """A copy of the oracle's bcd with one planted mistake."""
+    def bcd(B, R, max_iters, tol=0.0, normX2=None, init=None):
+        B = np.asarray(B, dtype=np.float64)
+        N = B.ndim
+        nx = float(np.dot(B.ravel(), B.ravel())) if normX2 is None else normX2
+        A = ([np.zeros((B.shape[0], R))] + [rcp.eig_init(B, R, n) for n in range(1, N)]
+             if init is None else [np.array(a, dtype=np.float64) for a in init])
+        lam = np.zeros(R)
+        hist, comp_iters = [], []
+        rho = 0.0
+        for r in range(R):
+            it = 0
+            for it in range(1, int(max_iters) + 1):
+                for n in range(N):
+                    v = rcp.mttkrp(B, [A[m][:, r:r + 1] for m in range(N)], n)[:, 0]
+                    if not drop_deflation:
+                        for s in range(r):
+                            w = np.prod([A[m][:, s] @ A[m][:, r] for m in range(N) if m != n])
+                            v = v - lam[s] * w * A[n][:, r if wrong_vector else s]
+                    d = np.prod([A[m][:, r] @ A[m][:, r] for m in range(N) if m != n])
+                    v = v / d
+                    nu = float(np.linalg.norm(v))
+                    A[n][:, r] = v / nu if nu > 0 else v
+                    if n == N - 1:
+                        lam[r] = nu
+                rho = rcp.bcd_fit(B, A, lam, r, nx)
+                hist.append(rho)
+            comp_iters.append(it)
+        return rcp.BCDResult(factors=A, lam=lam, rho=rho, iters=sum(comp_iters),
+                             component_iters=comp_iters, rho_history=hist)
+    return bcd
+
+
+def test_bcd_without_deflation_is_caught(monkeypatch):
+    monkeypatch.setattr(rcp, "bcd", _bcd_variant(drop_deflation=True))
+    with pytest.raises(AssertionError):
+        tbcd.test_bcd_updates_are_explicit_residual_least_squares((4, 5, 6), 3)
+    with pytest.raises(AssertionError):
+        tbcd.test_bcd_fit_never_decreases_within_a_component()
+
+
+def test_bcd_deflating_with_the_wrong_vector_is_caught(monkeypatch):
+    monkeypatch.setattr(rcp, "bcd", _bcd_variant(wrong_vector=True))
+    with pytest.raises(AssertionError):
+        tbcd.test_bcd_updates_are_explicit_residual_least_squares((4, 5, 6), 3)
+
