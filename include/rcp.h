@@ -63,6 +63,12 @@ enum { RCP_PREC_FP32 = 0, RCP_PREC_BF16 = 1, RCP_PREC_FP16 = 2 };
  * forms the core by chained mode products afterwards. */
 enum { RCP_SCHEME_SEQUENTIAL = 0, RCP_SCHEME_INDEPENDENT = 1 };
 
+/* rcp_problem.solver: the CP solver rcp_decompose runs on the core.  ALS is
+ * Section 3.2.1 / Algorithm 2 (rcp_als); BCD is the rank-one block coordinate
+ * descent of Section 3.2.2 / Algorithm 3 (rcp_bcd), whose max_iters and tol
+ * apply to each component. */
+enum { RCP_SOLVER_ALS = 0, RCP_SOLVER_BCD = 1 };
+
 /* Device-side status bits: rcp_als_info.status holds those of one CP-ALS
  * run (the first three); the plan's status word (rcp_read_status) collects
  * every bit any call on the plan has raised since it was last read. */
@@ -90,7 +96,7 @@ typedef struct rcp_problem {
     int32_t max_iters;               /* ALS sweeps, >= 1 */
     int32_t precision;               /* RCP_PREC_* */
     int32_t scheme;                  /* RCP_SCHEME_* */
-    int32_t reserved;                /* must be 0 */
+    int32_t solver;                  /* RCP_SOLVER_*: CP solver on the core */
     double tol;                      /* stop when |rho_j - rho_{j-1}| < tol (j >= 2); 0 = run max_iters */
     uint64_t seed;                   /* seed of the Gaussian test matrices */
 } rcp_problem;
@@ -115,7 +121,7 @@ rcp_status rcp_workspace_size(const rcp_problem* prob, size_t* bytes);
  * void*; NULL = the null stream) and returns a plan in *plan.
  * RCP_ERR_INVALID_ARG: ndim outside [2, 8], a dim < 1, k < 1, p < 0, q < 0,
  *   k + p > 64, k > l_n for some n, max_iters < 1, tol < 0, unknown
- *   precision/scheme, reserved != 0, or a null plan / problem pointer.
+ *   precision/scheme/solver, or a null plan / problem pointer.
  * RCP_ERR_WORKSPACE: null or too small workspace.
  * RCP_ERR_UNSUPPORTED: the core factors and Gram matrices of CP-ALS do not
  *   fit one workgroup's LDS (rank and l too large together), or the device
@@ -171,6 +177,21 @@ rcp_status rcp_norm2(rcp_plan plan, const float* X, int64_t count, double* out);
  * per mode (every max_iters sweep is enqueued; after the stopping rule fires
  * the remaining launches return at once).  Results agree to rounding. */
 rcp_status rcp_als(rcp_plan plan, const float* core, float* const* At,
+                   float* lambda, const double* normX2, rcp_als_info* info,
+                   int32_t use_given_init);
+
+/* Block coordinate descent on the core (Algorithm 3 steps 2-15; arguments
+ * as rcp_als).  Components r = 0..R-1 one after another: each sweep updates
+ * a_r^(0..N-1) in mode order, each the least-squares rank-one block update on
+ * the residual B - sum_{s<r} lam_s a_s^(0) o ... o a_s^(N-1) (evaluated
+ * without forming it), unit-normalised with the last mode's norm as
+ * lambda_r; max_iters sweeps per component, fewer when tol > 0 and the fit
+ * of components 0..r changes by less than tol (after sweep 2).
+ * info->iters is the sum of the components' sweeps.  Starts from the leading
+ * eigenvectors of B_(n) B_(n)^T (column r for component r) or, with
+ * use_given_init != 0, from At[1..N-1].  RCP_ERR_UNSUPPORTED when a core
+ * mode exceeds 64 or the float64 factors do not fit one workgroup's LDS. */
+rcp_status rcp_bcd(rcp_plan plan, const float* core, float* const* At,
                    float* lambda, const double* normX2, rcp_als_info* info,
                    int32_t use_given_init);
 
@@ -254,7 +275,8 @@ enum {
     RCP_KERNEL_ALS = 6,          /* CP-ALS on the core */
     RCP_KERNEL_EXPAND = 7,       /* back-projection and renormalisation */
     RCP_KERNEL_OTHER = 8,
-    RCP_KERNEL_COUNT = 9
+    RCP_KERNEL_BCD = 9,          /* block coordinate descent on the core */
+    RCP_KERNEL_COUNT = 10
 };
 rcp_status rcp_profile(rcp_plan plan, int32_t enable);
 rcp_status rcp_profile_read(rcp_plan plan, int32_t kernel_class, int64_t* launches, double* ms,

@@ -55,7 +55,8 @@ class Plan:
 
     def __init__(self, dims: Sequence[int], k: int, p: int = 10, q: int = 2,
                  max_iters: int = 50, tol: float = 0.0, seed: int = 0,
-                 scheme: str = "sequential", precision: str = "fp32", device="cuda"):
+                 scheme: str = "sequential", precision: str = "fp32", device="cuda",
+                 solver: str = "als"):
         torch = _torch()
         self.lib = _lib.load()
         self.dims = [int(d) for d in dims]
@@ -66,7 +67,8 @@ class Plan:
         self.q = int(q)
         self.l = [sketch_width(k, p, d) for d in self.dims]
         self.device = torch.device(device)
-        self.problem = _lib.make_problem(self.dims, k, p, q, max_iters, tol, seed, precision, scheme)
+        self.problem = _lib.make_problem(self.dims, k, p, q, max_iters, tol, seed, precision, scheme,
+                                         solver)
         nbytes = ctypes.c_size_t(0)
         _lib.check(self.lib.rcp_workspace_size(ctypes.byref(self.problem), ctypes.byref(nbytes)),
                    "rcp_workspace_size")
@@ -140,6 +142,9 @@ class Plan:
 
         init: starting factors (l_n x R float32 CUDA tensors, one per mode; the
         first is not read) instead of the eigenvector start (warm start)."""
+        return self._core_solver(self.lib.rcp_als, "rcp_als", core, normX2, init)
+
+    def _core_solver(self, fn, name, core, normX2, init):
         _f32(core, "core")
         if list(core.shape) != self.l:
             raise ValueError(f"core has shape {list(core.shape)}, plan expects {self.l}")
@@ -158,12 +163,16 @@ class Plan:
         if normX2 is not None and (normX2.dtype != _torch().float64 or not normX2.is_cuda):
             raise TypeError("normX2 must be a float64 CUDA tensor")
         nptr = ctypes.c_void_p(normX2.data_ptr()) if normX2 is not None else ctypes.c_void_p(0)
-        _lib.check(self.lib.rcp_als(self.handle, ctypes.c_void_p(core.data_ptr()),
-                                    _lib.ptr_array([a.data_ptr() for a in At]),
-                                    ctypes.c_void_p(lam.data_ptr()), nptr,
-                                    ctypes.c_void_p(info.data_ptr()),
-                                    1 if init is not None else 0), "rcp_als")
+        _lib.check(fn(self.handle, ctypes.c_void_p(core.data_ptr()),
+                      _lib.ptr_array([a.data_ptr() for a in At]),
+                      ctypes.c_void_p(lam.data_ptr()), nptr,
+                      ctypes.c_void_p(info.data_ptr()), 1 if init is not None else 0), name)
         return At, lam, info
+
+    def bcd(self, core, normX2=None, init: Optional[List] = None):
+        """Block coordinate descent on the core (Algorithm 3 steps 2-15):
+        (factors, lambda, info buffer); arguments as ``als``."""
+        return self._core_solver(self.lib.rcp_bcd, "rcp_bcd", core, normX2, init)
 
     def read_status(self) -> int:
         """The plan's device status word (RCP_INFO_* bits raised since the last
@@ -378,8 +387,11 @@ class Batch:
 
 
 def decompose(X, k: int, p: int = 10, q: int = 2, iters: int = 50, tol: float = 0.0,
-              seed: int = 0, scheme: str = "sequential", precision: str = "fp32"):
-    """Randomized CP of X (Algorithm 2).  Returns (lambda, [A_n], info dict)."""
-    plan = Plan(list(X.shape), k, p, q, iters, tol, seed, scheme, precision, device=X.device)
+              seed: int = 0, scheme: str = "sequential", precision: str = "fp32",
+              solver: str = "als"):
+    """Randomized CP of X (Algorithm 2, or Algorithm 3 with solver="bcd").
+    Returns (lambda, [A_n], info dict)."""
+    plan = Plan(list(X.shape), k, p, q, iters, tol, seed, scheme, precision, device=X.device,
+                solver=solver)
     lam, A, info = plan.decompose(X)
     return lam, A, Plan.read_info(info)

@@ -30,8 +30,9 @@ RCP_INFO_QR_HOUSEHOLDER = 8
 
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 KERNEL_CLASSES = ["sketch", "power", "contract_in", "contract_out", "reduce", "qr", "als",
-                  "expand", "other"]
+                  "expand", "other", "bcd"]
 SCHEMES = {"sequential": 0, "independent": 1}
+SOLVERS = {"als": 0, "bcd": 1}
 
 
 class Problem(ctypes.Structure):
@@ -44,7 +45,7 @@ class Problem(ctypes.Structure):
         ("max_iters", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("scheme", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("solver", ctypes.c_int32),
         ("tol", ctypes.c_double),
         ("seed", ctypes.c_uint64),
     ]
@@ -74,6 +75,7 @@ SIGNATURES = {
     "rcp_norm2": (_st, [_vp, _vp, ctypes.c_int64, _vp]),
     "rcp_als": (_st, [_vp, _vp, ctypes.POINTER(_vp), _vp, _vp, _vp, ctypes.c_int32]),
     "rcp_read_status": (_st, [_vp, ctypes.POINTER(ctypes.c_int32)]),
+    "rcp_bcd": (_st, [_vp, _vp, ctypes.POINTER(_vp), _vp, _vp, _vp, ctypes.c_int32]),
     "rcp_expand": (_st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, ctypes.POINTER(_vp), _vp]),
     "rcp_decompose": (_st, [_vp, _vp, ctypes.POINTER(_vp), _vp, _vp]),
     "rcp_decompose_noalloc": (_st, [ctypes.POINTER(Problem), _vp, ctypes.POINTER(_vp), _vp, _vp, _vp]),
@@ -150,7 +152,8 @@ def dims_array(dims):
     return arr
 
 
-def make_problem(dims, k, p, q, max_iters, tol, seed, precision="fp32", scheme="sequential"):
+def make_problem(dims, k, p, q, max_iters, tol, seed, precision="fp32", scheme="sequential",
+                 solver="als"):
     prob = Problem()
     prob.ndim = len(dims)
     prob.k = int(k)
@@ -161,7 +164,7 @@ def make_problem(dims, k, p, q, max_iters, tol, seed, precision="fp32", scheme="
     prob.max_iters = int(max_iters)
     prob.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     prob.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
-    prob.reserved = 0
+    prob.solver = SOLVERS[solver] if isinstance(solver, str) else int(solver)
     prob.tol = float(tol)
     prob.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     return prob

@@ -20,8 +20,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librcp.so")
 
-SOURCES = ["stream_kernels.hip", "stream_kernels_lp.hip", "qr_kernel.hip", "als_kernel.hip", "expand_kernel.hip",
-           "rcp_api.cpp"]
+SOURCES = ["stream_kernels.hip", "stream_kernels_lp.hip", "qr_kernel.hip", "als_kernel.hip",
+           "bcd_kernel.hip", "expand_kernel.hip", "rcp_api.cpp"]
 
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -16,225 +16,12 @@
 // Grams, solves, norms and the fit are float64; the factors feeding the
 // matrix cores are float32.
 
-#include "rcp_device.h"
-#include "rcp_kernels.h"
+#include "als_common.h"
 
 #include <type_traits>
 
 namespace rcp {
 
-
-constexpr int ANT = 512;
-constexpr int ANW = ANT / 64;
-constexpr double kPivotRtol = 1e-13;
-constexpr int kJacobiMaxSweeps = 40;
-constexpr int kEigLd = 64;
-constexpr size_t kAlsLds = 160 * 1024 - 4096;   // dynamic LDS budget
-constexpr int kMtQuads = 8;                      // inner extents up to 32 take the pipelined path
-
-// Floats of LDS for the partial 16 x 16 blocks of the mode products: a mode
-// with `blocks` output blocks splits its contraction over up to
-// ANW / blocks wavefronts, all but the first slice of a block go to LDS.
-__host__ __device__ inline int als_part_floats(int N, const int* l, int R) {
-    int mx = 0;
-    const int ncb = (R + 15) / 16;
-    for (int n = 0; n < N; ++n) {
-        const int blocks = ((l[n] + 15) / 16) * ncb;
-        const int kp = (blocks >= ANW) ? 1 : ANW / blocks;
-        const int f = (kp - 1) * blocks * 256;
-        mx = mx > f ? mx : f;
-    }
-    return mx;
-}
-
-struct AlsCtx {
-    int N, R;
-    int S, Lh, lN;
-    const int* l;                  // LDS: mode sizes l_0..l_{N-1}
-    const int* foff;               // LDS: offset of factor n inside fbase
-    float* fbase;                  // LDS: l_n x R working factors (matrix-core operands)
-    double* red;                   // ANW doubles (LDS)
-    double* sh;                    // 128 doubles (LDS)
-    __device__ __forceinline__ float* fac(int n) const { return fbase + foff[n]; }
-};
-
-// ---------------------------------------------------------------------------
-// Parallel cyclic Jacobi eigen-decomposition of the symmetric n x n matrix
-// A (row stride kEigLd, overwritten; eigenvalues end on the diagonal), with
-// the eigenvectors accumulated in the columns of V.  Round-robin (circle
-// method) ordering: each round rotates n/2 disjoint (p, q) pairs.  A round
-// is two phases: the rotation angles of the pairs, then one update in which
-// a thread owns a 2 x 2 block of A at (pair u, pair v) and replaces it by
-// G_u A_uv G_v^T (G = [[c, -s], [s, c]] of each pair, i.e. the row and the
-// column rotation at once, in place since no other thread touches the block)
-// or two entries of V's row (V <- V G^T).  Returns false if the off-diagonal
-// mass did not fall below 1e-30 of the diagonal's.
-__device__ __forceinline__ bool jacobi_eig(double* A, double* V, int n, double* red, double* sh) {
-    const int tid = threadIdx.x;
-    const int np = (n + 1) & ~1;
-    const int half = np / 2;
-    double* cs = sh;
-    double* sn = sh + 32;
-    int* pp = (int*)(sh + 64);
-    int* qq = pp + 32;
-    for (int i = tid / 64; i < n; i += ANW)
-        for (int j = tid % 64; j < n; j += 64) V[i * kEigLd + j] = (i == j) ? 1.0 : 0.0;
-    __syncthreads();
-    bool converged = false;
-    for (int sweep = 0; sweep < kJacobiMaxSweeps; ++sweep) {
-        double off = 0.0, dia = 0.0;
-        for (int i = tid / 64; i < n; i += ANW)
-            for (int j = tid % 64; j < n; j += 64) {
-                const double v = A[i * kEigLd + j];
-                if (i == j) dia += v * v; else off += v * v;
-            }
-        off = block_sum(off, red);
-        dia = block_sum(dia, red);
-        if (off <= 1e-30 * dia || off == 0.0) { converged = true; break; }
-        for (int round = 0; round < np - 1; ++round) {
-            if (tid < half) {
-                // round-robin pairing: a = (k - 1 + round) mod (np - 1) + 1 for
-                // k > 0, b = (np - 2 - k + round) mod (np - 1) + 1; both
-                // arguments lie in [0, 2 (np - 1)), so one subtraction reduces them
-                const int k = tid, m = np - 1;
-                int xa = k - 1 + round, xb = np - 2 - k + round;
-                if (xa >= m) xa -= m;
-                if (xb >= m) xb -= m;
-                int a = (k == 0) ? 0 : xa + 1;
-                int b = xb + 1;
-                if (a > b) { const int t = a; a = b; b = t; }
-                double c = 1.0, s = 0.0;
-                if (b < n) {
-                    const double apq = A[a * kEigLd + b];
-                    if (apq != 0.0) {
-                        const double app = A[a * kEigLd + a], aqq = A[b * kEigLd + b];
-                        const double th = (aqq - app) / (2.0 * apq);
-                        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                        c = 1.0 / sqrt(t * t + 1.0);
-                        s = t * c;
-                    }
-                }
-                cs[k] = c; sn[k] = s; pp[k] = a; qq[k] = b;
-            }
-            __syncthreads();
-            // A: blocks (u, v); V: (row i, pair v)
-            const int nblk = half * half;
-            for (int e = tid; e < nblk + n * half; e += ANT) {
-                if (e < nblk) {
-                    const int u = e / half, v = e - (e / half) * half;
-                    const double cu = cs[u], su = sn[u], cv = cs[v], sv = sn[v];
-                    if (su == 0.0 && sv == 0.0) continue;
-                    const int p = pp[u], q = qq[u], r = pp[v], t = qq[v];
-                    const bool qv = q < n, tv = t < n;
-                    const double a00 = A[p * kEigLd + r];
-                    const double a01 = tv ? A[p * kEigLd + t] : 0.0;
-                    const double a10 = qv ? A[q * kEigLd + r] : 0.0;
-                    const double a11 = (qv && tv) ? A[q * kEigLd + t] : 0.0;
-                    // rows: [b0; b1] = G_u [a0; a1]
-                    const double b00 = cu * a00 - su * a10, b01 = cu * a01 - su * a11;
-                    const double b10 = su * a00 + cu * a10, b11 = su * a01 + cu * a11;
-                    // columns: [d0 d1] = [b0 b1] G_v^T
-                    A[p * kEigLd + r] = cv * b00 - sv * b01;
-                    if (tv) A[p * kEigLd + t] = sv * b00 + cv * b01;
-                    if (qv) A[q * kEigLd + r] = cv * b10 - sv * b11;
-                    if (qv && tv) A[q * kEigLd + t] = sv * b10 + cv * b11;
-                } else {
-                    const int e2 = e - nblk;
-                    const int i = e2 / half, v = e2 - (e2 / half) * half;
-                    const double sv = sn[v];
-                    if (sv == 0.0) continue;
-                    const double cv = cs[v];
-                    const int r = pp[v], t = qq[v];
-                    const double vr = V[i * kEigLd + r], vt = V[i * kEigLd + t];
-                    V[i * kEigLd + r] = cv * vr - sv * vt;
-                    V[i * kEigLd + t] = sv * vr + cv * vt;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    return converged;
-}
-
-__device__ __forceinline__ int desc_rank(const double* A, int n, int e) {
-    const double w = A[e * kEigLd + e];
-    int r = 0;
-    for (int f = 0; f < n; ++f) {
-        const double v = A[f * kEigLd + f];
-        if (v > w || (v == w && f < e)) ++r;
-    }
-    return r;
-}
-
-// Leading R eigenvectors of the symmetric l_n x l_n matrix in E (stride
-// kEigLd, destroyed), in descending eigenvalue order, each with its
-// largest-magnitude entry positive, into the factor c.fac(n).
-__device__ __forceinline__ bool eig_leading(const AlsCtx& c, int n, double* E, double* V) {
-    const int tid = threadIdx.x;
-    const int ln = c.l[n];
-    const bool ok = jacobi_eig(E, V, ln, c.red, c.sh);
-    for (int e = tid; e < ln; e += ANT) {
-        const int r = desc_rank(E, ln, e);
-        if (r < c.R) {
-            int best = 0;
-            double bv = -1.0;
-            for (int i = 0; i < ln; ++i) {
-                const double v = fabs(V[i * kEigLd + e]);
-                if (v > bv) { bv = v; best = i; }
-            }
-            const double sg = (V[best * kEigLd + e] < 0.0) ? -1.0 : 1.0;
-            for (int i = 0; i < ln; ++i) c.fac(n)[i * c.R + r] = (float)(sg * V[i * kEigLd + e]);
-        }
-    }
-    __syncthreads();
-    return ok;
-}
-
-// Algorithm 2 step 2: leading R eigenvectors of B_(n) B_(n)^T.
-__device__ __forceinline__ bool eig_init(const AlsCtx& c, const float* Bg, int n, double* E,
-                                         double* V) {
-    const int tid = threadIdx.x;
-    const int ln = c.l[n];
-    int Ln = 1, Rn = 1;
-    for (int m = 0; m < n; ++m) Ln *= c.l[m];
-    for (int m = n + 1; m < c.N; ++m) Rn *= c.l[m];
-    const int npairs = ln * (ln + 1) / 2;
-    for (int e = tid; e < npairs; e += ANT) {
-        int i = 0, rem = e;
-        while (rem >= ln - i) { rem -= ln - i; ++i; }
-        const int i2 = i + rem;
-        // sum over k = a Rn + b (a < Ln, b < Rn) of B[a, i, b] B[a, i2, b],
-        // eight products in flight in eight partial sums
-        const float* p1 = Bg + (int64_t)i * Rn;
-        const float* p2 = Bg + (int64_t)i2 * Rn;
-        const int64_t sa = (int64_t)ln * Rn;
-        const int K = Ln * Rn;
-        double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        int a = 0, b = 0, k = 0;
-        for (; k + 8 <= K; k += 8) {
-            float x[8], y[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int64_t off = a * sa + b;
-                x[u] = p1[off];
-                y[u] = p2[off];
-                if (++b == Rn) { b = 0; ++a; }
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) acc[u] += (double)x[u] * (double)y[u];
-        }
-        for (; k < K; ++k) {
-            const int64_t off = a * sa + b;
-            acc[0] += (double)p1[off] * (double)p2[off];
-            if (++b == Rn) { b = 0; ++a; }
-        }
-        const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-        E[i * kEigLd + i2] = s;
-        E[i2 * kEigLd + i] = s;
-    }
-    __syncthreads();
-    return eig_leading(c, n, E, V);
-}
 
 // ---------------------------------------------------------------------------
 // M_n = B_(n) KR(Ã_{m != n}) on the matrix cores.
@@ -707,43 +494,6 @@ __device__ __forceinline__ void hadamard_grams(const AlsCtx& c, int n, const dou
     for (int e = threadIdx.x; e < (Rp - R) * ln; e += ANT) {
         const int r = R + e / ln, i = e - (e / ln) * ln;
         Aug[r * ldx + Rp + i] = 0.0;
-    }
-}
-
-// G = F^T F (R x R, float64) of the float32 factor F (l_n x R, LDS) on the
-// float64 matrix cores: 16 x 16 blocks of the upper triangle, one wavefront
-// per block, mirrored into the lower triangle.
-__device__ __forceinline__ void gram_mfma(const float* F, int ln, int R, double* G) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    const int nb = (R + 15) >> 4;
-    const int U = nb * (nb + 1) / 2;
-    for (int u = wave; u < U; u += ANW) {
-        int bi = 0, rem = u;
-        while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
-        const int bj = bi + rem;
-        const int c1 = bi * 16 + li, c2 = bj * 16 + li;
-        // two independent accumulation chains (even and odd steps of 4 rows)
-        f64x4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < ln; k0 += 8) {
-            const int k = k0 + lk, kb = k + 4;
-            const double a = (k < ln && c1 < R) ? (double)F[k * R + c1] : 0.0;
-            const double b = (k < ln && c2 < R) ? (double)F[k * R + c2] : 0.0;
-            const double a2 = (kb < ln && c1 < R) ? (double)F[kb * R + c1] : 0.0;
-            const double b2 = (kb < ln && c2 < R) ? (double)F[kb * R + c2] : 0.0;
-            acc = mfma64(a, b, acc);
-            acc2 = mfma64(a2, b2, acc2);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] += acc2[v];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = bi * 16 + lk + 4 * v, s = bj * 16 + li;
-            if (r < R && s < R) {
-                G[r * R + s] = acc[v];
-                if (bi != bj) G[s * R + r] = acc[v];
-            }
-        }
     }
 }
 

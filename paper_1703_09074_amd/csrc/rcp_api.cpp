@@ -49,7 +49,7 @@ bool valid_problem(const rcp_problem* p) {
     if (p->precision != RCP_PREC_FP32 && p->precision != RCP_PREC_BF16 &&
         p->precision != RCP_PREC_FP16)
         return false;
-    if (p->reserved != 0) return false;
+    if (p->solver != RCP_SOLVER_ALS && p->solver != RCP_SOLVER_BCD) return false;
     for (int n = 0; n < p->ndim; ++n) {
         if (p->dims[n] < 1 || p->dims[n] > (int64_t)1 << 40) return false;
         const int64_t l = std::min<int64_t>(p->k + p->p, p->dims[n]);
@@ -417,6 +417,39 @@ rcp_status als_impl(rcp_plan_t* pl, const float* core, float* const* At, float* 
     return RCP_OK;
 }
 
+// Algorithm 3 on the core: one workgroup (the core in LDS when it fits);
+// without ||X||^2 the fit is taken against ||core||^2 (second norm slot).
+rcp_status bcd_impl(rcp_plan_t* pl, const float* core, float* const* At, float* lambda,
+                    const double* normX2, rcp_als_info* info, int warm) {
+    const Layout& L = pl->L;
+    AlsArgs a{};
+    a.B = core;
+    a.N = L.N;
+    for (int n = 0; n < L.N; ++n) { a.l[n] = L.l[n]; a.At[n] = At[n]; }
+    a.R = L.R;
+    a.max_iters = pl->prob.max_iters;
+    a.warm = warm;
+    a.tol = pl->prob.tol;
+    a.lambda = lambda;
+    a.info = info;
+    a.status_word = pl->status_word();
+    a.Ebuf = pl->at<double>(L.als);
+    int64_t S = 1;
+    for (int n = 0; n < L.N; ++n) S *= L.l[n];
+    if (normX2 == nullptr) {
+        double* slot = pl->at<double>(L.norm) + 1;
+        const int nb = (int)std::min<int64_t>(256, std::max<int64_t>(1, S / 4096));
+        RCP_TRY(launch_sumsq(core, S, pl->at<double>(L.red1), nb, slot, pl->stream));
+        normX2 = slot;
+    }
+    a.normX2 = normX2;
+    // nominal work: per sweep of each component, N products of the core with a vector
+    const double sweeps = (double)pl->prob.max_iters * L.R;
+    RCP_TRY(timed(pl, RCP_KERNEL_BCD, sweeps * L.N * 4.0 * (double)S, sweeps * L.N * 2.0 * (double)S,
+                  [&] { return launch_bcd(a, pl->stream); }));
+    return RCP_OK;
+}
+
 rcp_status expand_impl(rcp_plan_t* pl, const float* const* Q, const float* const* At,
                        const float* lam_in, float* const* A, float* lam_out) {
     const Layout& L = pl->L;
@@ -477,6 +510,7 @@ rcp_status plan_setup(rcp_plan_t* pl, const rcp_problem* prob, void* workspace,
     if (!valid_problem(prob)) return RCP_ERR_INVALID_ARG;
     const Layout L = make_layout(prob);
     if (!als_supported(L.N, L.l, L.R)) return RCP_ERR_UNSUPPORTED;
+    if (prob->solver == RCP_SOLVER_BCD && !bcd_supported(L.N, L.l, L.R)) return RCP_ERR_UNSUPPORTED;
     if (workspace == nullptr || workspace_bytes < L.total || !aligned(workspace, kAlign))
         return RCP_ERR_WORKSPACE;
     pl->prob = *prob;
@@ -630,6 +664,18 @@ rcp_status rcp_als(rcp_plan plan, const float* core, float* const* At, float* la
     return als_impl(plan, core, At, lambda, normX2, info, use_given_init != 0 ? 1 : 0);
 }
 
+rcp_status rcp_bcd(rcp_plan plan, const float* core, float* const* At, float* lambda,
+                   const double* normX2, rcp_als_info* info, int32_t use_given_init) {
+    if (plan == nullptr || core == nullptr || At == nullptr || lambda == nullptr || info == nullptr)
+        return RCP_ERR_INVALID_ARG;
+    for (int n = 0; n < plan->L.N; ++n)
+        if (At[n] == nullptr || !aligned(At[n], 4)) return RCP_ERR_INVALID_ARG;
+    if (!aligned(core, 4) || !aligned(info, 8) || (normX2 && !aligned(normX2, 8)))
+        return RCP_ERR_INVALID_ARG;
+    if (!bcd_supported(plan->L.N, plan->L.l, plan->L.R)) return RCP_ERR_UNSUPPORTED;
+    return bcd_impl(plan, core, At, lambda, normX2, info, use_given_init != 0 ? 1 : 0);
+}
+
 rcp_status rcp_expand(rcp_plan plan, const float* const* Q, const float* const* At,
                       const float* lambda_in, float* const* A, float* lambda_out) {
     if (plan == nullptr || Q == nullptr || At == nullptr || A == nullptr || lambda_in == nullptr ||
@@ -734,7 +780,9 @@ rcp_status decompose_impl(rcp_plan_t* plan, const float* X, float* const* A, flo
     float* At[RCP_MAX_NDIM];
     for (int n = 0; n < N; ++n) At[n] = plan->at<float>(L.at[n]);
     float* lam = plan->at<float>(L.lam);
-    st = als_impl(plan, core, At, lam, plan->at<double>(L.norm), info, 0);
+    st = plan->prob.solver == RCP_SOLVER_BCD
+             ? bcd_impl(plan, core, At, lam, plan->at<double>(L.norm), info, 0)
+             : als_impl(plan, core, At, lam, plan->at<double>(L.norm), info, 0);
     if (st != RCP_OK) return st;
     const float* Qc[RCP_MAX_NDIM];
     const float* Atc[RCP_MAX_NDIM];
@@ -863,6 +911,7 @@ rcp_status batch_layout(const rcp_problem* probs, int32_t count, BatchLayout* ou
     size_t off = 0;
     for (int i = 0; i < count; ++i) {
         if (!valid_problem(&probs[i])) return RCP_ERR_INVALID_ARG;
+        if (probs[i].solver != RCP_SOLVER_ALS) return RCP_ERR_UNSUPPORTED;
         const Layout L = make_layout(&probs[i]);
         if (!als_supported(L.N, L.l, L.R)) return RCP_ERR_UNSUPPORTED;
         B.off.push_back(off);

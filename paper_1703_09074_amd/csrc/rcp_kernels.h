@@ -116,6 +116,10 @@ struct AlsArgs {
     double* state;
 };
 hipError_t launch_als(const AlsArgs& a, hipStream_t s);
+// Block coordinate descent on the core (bcd_kernel.hip), one workgroup, the
+// same arguments (a.normX2 must be set; At[1..N-1] read when a.warm)
+bool bcd_supported(int N, const int* l, int R);
+hipError_t launch_bcd(const AlsArgs& a, hipStream_t s);
 // one launch for `count` problems: dargs on the device, hargs the same on the host
 hipError_t launch_als_batch(const AlsArgs* dargs, const AlsArgs* hargs, int count, hipStream_t s);
 size_t als_workspace_doubles(int N, const int* l, int R);

@@ -94,7 +94,7 @@ def test_workspace_size_valid_and_monotone(lib):
 
 @pytest.mark.parametrize("field,value", [
     ("ndim", 1), ("ndim", 9), ("k", 0), ("p", -1), ("q", -1), ("k", 65), ("p", 60),
-    ("max_iters", 0), ("tol", -1.0), ("precision", 7), ("scheme", 3), ("reserved", 1),
+    ("max_iters", 0), ("tol", -1.0), ("precision", 7), ("scheme", 3), ("solver", 2),
 ])
 def test_invalid_problems_rejected(lib, field, value):
     prob = _lib.make_problem((40, 30, 20), 5, 5, 1, 10, 0.0, 1)
@@ -133,6 +133,7 @@ def test_null_plan_rejected_everywhere(lib):
     assert lib.rcp_sketch(None, None, dims, 0, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_compress(None, None, dims, 0, None, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_als(None, None, None, None, None, None, 0) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_bcd(None, None, None, None, None, None, 0) == _lib.RCP_ERR_INVALID_ARG
     v = ctypes.c_int32(0)
     assert lib.rcp_read_status(None, ctypes.byref(v)) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_debug_philox(None, 0, 0, 1, 1, None) == _lib.RCP_ERR_INVALID_ARG
