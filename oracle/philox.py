@@ -106,3 +106,66 @@ def omega(seed: int, mode: int, batch: int, row0: int, nrows: int, l: int):
         z[:, 4 * m + 2] = rb * np.cos(tb)
         z[:, 4 * m + 3] = rb * np.sin(tb)
     return z[:, :l]
+
+
+def omega_uniform(seed: int, mode: int, batch: int, row0: int, nrows: int, l: int):
+    """Rows [row0, row0+nrows) of the uniform test matrix (Algorithm 1 step 5
+    writes rand(J, l); the remark after Algorithm 1 notes that a uniform test
+    matrix is sufficient in practice): entry (j, c) is the uniform u of word
+    c mod 4 of counter group c // 4 of row j, in (0, 1]; float64."""
+    ngroups = (int(l) + 3) // 4
+    return uniforms(omega_bits(seed, mode, batch, row0, nrows, ngroups))[:, :l]
+
+
+# the first 64 primes: the Halton bases of columns 0..63
+PRIMES = [2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53, 59, 61, 67, 71, 73,
+          79, 83, 89, 97, 101, 103, 107, 109, 113, 127, 131, 137, 139, 149, 151, 157, 163,
+          167, 173, 179, 181, 191, 193, 197, 199, 211, 223, 227, 229, 233, 239, 241, 251,
+          257, 263, 269, 271, 277, 281, 283, 293, 307, 311]
+
+
+def radical_inverse(i: int, base: int) -> float:
+    """The base-b radical inverse of the integer i >= 1: its digits mirrored
+    about the radix point, as the exact ratio of two integers."""
+    num, den = 0, 1
+    while i > 0:
+        i, d = divmod(i, base)
+        num = num * base + d
+        den *= base
+    return num / den
+
+
+def omega_halton(row0: int, nrows: int, l: int):
+    """Rows [row0, row0+nrows) of the quasi-random test matrix (the note in
+    Section 3.1 on drawing the entries from a Halton sequence): row j is the
+    Halton point j + 1, entry (j, c) the radical inverse of j + 1 in the c-th
+    prime base; deterministic, in (0, 1); float64."""
+    out = np.empty((nrows, l))
+    for c in range(l):
+        b = PRIMES[c]
+        out[:, c] = [radical_inverse(j + 1, b) for j in range(row0, row0 + nrows)]
+    return out
+
+
+def select_columns(seed: int, mode: int, batch: int, J: int, l: int):
+    """l distinct column indices out of J (the remark after Algorithm 1:
+    randomly selected columns in place of the sketch's product), by Floyd's
+    sampling without replacement: for i = J - l, ..., J - 1 draw t uniform on
+    {0, ..., i}; keep t unless already chosen, else keep i.  Draw number s
+    takes the Philox words of counter (s mod 2^32, s >> 32, 2^31,
+    (batch << 8) | mode): t = floor(x * (i + 1) / 2^64) with
+    x = (word1 << 32) | word0.  Returned sorted ascending."""
+    if l > J:
+        raise ValueError("cannot select more columns than the unfolding has")
+    seed = int(seed)
+    k0, k1 = seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF
+    tag = ((int(batch) << 8) | int(mode)) & 0xFFFFFFFF
+    chosen = set()
+    for s, i in enumerate(range(J - l, J)):
+        w = philox4x32_10(np.uint64(s & 0xFFFFFFFF), np.uint64(s >> 32), np.uint64(1 << 31),
+                          np.uint64(tag), k0, k1)
+        x = (int(w[1]) << 32) | int(w[0])
+        t = (x * (i + 1)) >> 64
+        chosen.add(i if t in chosen else t)
+    return np.array(sorted(chosen), dtype=np.int64)
+

@@ -154,18 +154,42 @@ class ModeStage:
     Q: np.ndarray           # I_n x l
 
 
+TEST_MATRICES = ("gaussian", "uniform", "halton", "columns")
+
+
+def test_matrix(kind: str, seed: int, n: int, batch: int, J: int, l: int) -> np.ndarray:
+    """The J x l test matrix Omega of mode n (Algorithm 1 step 5): Gaussian
+    (Section 3.1), uniform (the rand of step 5 and the remark after
+    Algorithm 1), quasi-random Halton (the note in Section 3.1), or the
+    selection of l random columns (the remark after Algorithm 1), as the
+    0/1 matrix picking them."""
+    if kind == "gaussian":
+        return philox.omega(seed, n, batch, 0, J, l)
+    if kind == "uniform":
+        return philox.omega_uniform(seed, n, batch, 0, J, l)
+    if kind == "halton":
+        return philox.omega_halton(0, J, l)
+    if kind == "columns":
+        sel = philox.select_columns(seed, n, batch, J, l)
+        Om = np.zeros((J, l))
+        Om[sel, np.arange(l)] = 1.0
+        return Om
+    raise ValueError(kind)
+
+
 def range_finder(T: np.ndarray, n: int, l: int, q: int, seed: int,
-                 batch: int = 0, normalizer: str = "qr"):
+                 batch: int = 0, normalizer: str = "qr", test: str = "gaussian"):
     """Basis Q_n of the mode-n range of T (Algorithm 1 steps 4-12).
 
-    Omega is the J x l Gaussian test matrix of mode n; the sketch
-    Y = T_(n) Omega (eq. sampleMatrix) goes through q normalised power
-    iterations  Q~ = nrm(Y),  Z = nrm(T_(n)^T Q~),  Y = T_(n) Z
-    (eq. IMPsampleMatrix, Algorithm 1 steps 7-11), then Q_n = qr(Y).
+    Omega is the J x l test matrix of mode n (Gaussian unless ``test`` says
+    otherwise); the sketch Y = T_(n) Omega (eq. sampleMatrix) goes through q
+    normalised power iterations  Q~ = nrm(Y),  Z = nrm(T_(n)^T Q~),
+    Y = T_(n) Z  (eq. IMPsampleMatrix, Algorithm 1 steps 7-11), then
+    Q_n = qr(Y).
     """
     Tn = unfold(T, n)
     J = Tn.shape[1]
-    Om = philox.omega(seed, n, batch, 0, J, l)
+    Om = test_matrix(test, seed, n, batch, J, l)
     Y = Tn @ Om
     y0 = Y.copy()
     for _ in range(int(q)):
@@ -185,22 +209,33 @@ class Compression:
 
 def compress(X: np.ndarray, k: int, p: int = 10, q: int = 2, seed: int = 0,
              batch: int = 0, scheme: str = "sequential",
-             normalizer: str = "qr") -> Compression:
+             normalizer: str = "qr", test: str = "gaussian",
+             modes: Optional[Sequence[int]] = None,
+             p_modes: Optional[Sequence[int]] = None) -> Compression:
     """Randomized tensor compression (Algorithm 1).
 
     scheme="sequential": the paper's loop, in which mode n is sketched on the
     tensor already compressed in modes < n (the algorithm sets X <- B_n after
     each mode).  scheme="independent": every Q_n is taken from X itself and
     B = X x_1 Q_1^T ... x_N Q_N^T is formed afterwards.
+    modes / p_modes (the remark after Algorithm 1: the user chooses the modes
+    to compress and their oversampling): a mode left out keeps Q_n = I
+    (its full size in the core); p_modes[n] replaces p for mode n.
     """
     X = np.asarray(X, dtype=np.float64)
     N = X.ndim
     T = X
     Qs, stages = [], []
+    chosen = set(range(N)) if modes is None else set(int(m) for m in modes)
     for n in range(N):
         src = T if scheme == "sequential" else X
-        l = sketch_width(k, p, src.shape[n])
-        st = range_finder(src, n, l, q, seed, batch, normalizer)
+        if n not in chosen:
+            Qs.append(np.eye(src.shape[n]))
+            stages.append(None)
+            continue
+        pn = p if p_modes is None else int(p_modes[n])
+        l = sketch_width(k, pn, src.shape[n])
+        st = range_finder(src, n, l, q, seed, batch, normalizer, test)
         stages.append(st)
         Qs.append(st.Q)
         if scheme == "sequential":
@@ -208,7 +243,8 @@ def compress(X: np.ndarray, k: int, p: int = 10, q: int = 2, seed: int = 0,
     if scheme == "independent":
         T = X
         for n in range(N):
-            T = mode_product(T, Qs[n].T, n)
+            if n in chosen:
+                T = mode_product(T, Qs[n].T, n)
     elif scheme != "sequential":
         raise ValueError(scheme)
     return Compression(core=T, Q=Qs, stages=stages)
@@ -478,12 +514,14 @@ class RCPResult:
 
 def rcp_als(X: np.ndarray, R: int, p: int = 10, q: int = 2, max_iters: int = 50,
             tol: float = 0.0, seed: int = 0, scheme: str = "sequential",
-            normalizer: str = "qr", batch: int = 0) -> RCPResult:
+            normalizer: str = "qr", batch: int = 0, test: str = "gaussian",
+            modes: Optional[Sequence[int]] = None,
+            p_modes: Optional[Sequence[int]] = None) -> RCPResult:
     """Randomized CP via ALS (Algorithm 2): compress with target rank k = R,
     fit CP-ALS on the core, back-project and renormalise."""
     X = np.asarray(X, dtype=np.float64)
     normX2 = float(np.dot(X.ravel(), X.ravel()))
-    comp = compress(X, R, p, q, seed, batch, scheme, normalizer)
+    comp = compress(X, R, p, q, seed, batch, scheme, normalizer, test, modes, p_modes)
     res = als(comp.core, R, max_iters, tol, normX2=normX2)
     lam, A = expand(comp.Q, res.factors, res.lam)
     rel = float(np.sqrt(max(0.0, 1.0 - res.rho)))

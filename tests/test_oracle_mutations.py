@@ -112,9 +112,9 @@ def test_dropped_power_iteration_is_caught(monkeypatch):
     """range_finder running q - 1 normalised power iterations instead of q."""
     from tests import test_oracle_power_sequential as tps
 
-    def rf_short(T, n, l, q, seed, batch=0, normalizer="qr"):
+    def rf_short(T, n, l, q, seed, batch=0, normalizer="qr", test="gaussian"):
         Tn = rcp.unfold(T, n)
-        Om = philox.omega(seed, n, batch, 0, Tn.shape[1], l)
+        Om = rcp.test_matrix(test, seed, n, batch, Tn.shape[1], l)
         Y = Tn @ Om
         y0 = Y.copy()
         for _ in range(max(0, int(q) - 1)):
@@ -136,9 +136,10 @@ def test_sequential_scheme_sketching_x_is_caught(monkeypatch):
     from tests import test_oracle_power_sequential as tps
     orig = rcp.compress
 
-    def compress_bad(X, k, p=10, q=2, seed=0, batch=0, scheme="sequential", normalizer="qr"):
+    def compress_bad(X, k, p=10, q=2, seed=0, batch=0, scheme="sequential", normalizer="qr",
+                     test="gaussian", modes=None, p_modes=None):
         if scheme != "sequential":
-            return orig(X, k, p, q, seed, batch, scheme, normalizer)
+            return orig(X, k, p, q, seed, batch, scheme, normalizer, test, modes, p_modes)
         X = np.asarray(X, dtype=np.float64)
         T, Qs, stages = X, [], []
         for n in range(X.ndim):
