@@ -13,8 +13,10 @@
  *   - Every tensor / matrix pointer is a DEVICE pointer unless stated.
  *     Arrays of pointers (``float* const* A``) are HOST arrays of device
  *     pointers, one per mode.
- *   - l_n = min(k + p, I_n) is the sketch width of mode n; the core has
- *     dims l_0 x ... x l_{N-1}; R = k is the CP rank.
+ *   - l_n = min(k + p_n, I_n) is the sketch width of mode n (p_n = p unless
+ *     rcp_problem.per_mode_p; l_n = I_n for a mode left out of
+ *     compress_mask); the core has dims l_0 x ... x l_{N-1}; R = k is the
+ *     CP rank.
  *   - The library never allocates device memory.  The caller provides one
  *     workspace buffer (size from rcp_workspace_size) and every input and
  *     output buffer; the library owns only the host-side plan object.
@@ -63,6 +65,24 @@ enum { RCP_PREC_FP32 = 0, RCP_PREC_BF16 = 1, RCP_PREC_FP16 = 2 };
  * forms the core by chained mode products afterwards. */
 enum { RCP_SCHEME_SEQUENTIAL = 0, RCP_SCHEME_INDEPENDENT = 1 };
 
+/* rcp_problem.test_matrix: Omega_n of Algorithm 1 step 5, a pure function of
+ * (seed, mode, batch, row j, column c), never stored:
+ *   GAUSSIAN  N(0, 1) entries (Section 3.1): Philox4x32-10 on the counter
+ *             (j mod 2^32, j >> 32, c / 4, (batch << 8) | mode) with key
+ *             (seed mod 2^32, seed >> 32), uniforms ((x >> 8) + 1) 2^-24,
+ *             Box-Muller on the pairs (u0, u1), (u2, u3);
+ *   UNIFORM   the uniforms themselves, entry c taking word c mod 4 (the
+ *             rand(J, l) of step 5; the remark after Algorithm 1);
+ *   HALTON    quasi-random (the note in Section 3.1): entry (j, c) is the
+ *             radical inverse of j + 1 in the c-th prime base (no seed);
+ *   COLUMNS   l randomly selected columns of the unfolding (the remark after
+ *             Algorithm 1): Floyd's sampling without replacement, draw s
+ *             taking t = floor(x (i + 1) / 2^64) on {0..i}, i = J - l + s,
+ *             x = (word1 << 32) | word0 of the counter (s mod 2^32, s >> 32,
+ *             2^31, (batch << 8) | mode); indices sorted ascending; needs
+ *             l_n <= J_n (the product of the other current mode sizes). */
+enum { RCP_TEST_GAUSSIAN = 0, RCP_TEST_UNIFORM = 1, RCP_TEST_HALTON = 2, RCP_TEST_COLUMNS = 3 };
+
 /* rcp_problem.solver: the CP solver rcp_decompose runs on the core.  ALS is
  * Section 3.2.1 / Algorithm 2 (rcp_als); BCD is the rank-one block coordinate
  * descent of Section 3.2.2 / Algorithm 3 (rcp_bcd), whose max_iters and tol
@@ -98,7 +118,13 @@ typedef struct rcp_problem {
     int32_t scheme;                  /* RCP_SCHEME_* */
     int32_t solver;                  /* RCP_SOLVER_*: CP solver on the core */
     double tol;                      /* stop when |rho_j - rho_{j-1}| < tol (j >= 2); 0 = run max_iters */
-    uint64_t seed;                   /* seed of the Gaussian test matrices */
+    uint64_t seed;                   /* seed of the random test matrices */
+    /* variants of Algorithm 1 (all zero = the defaults above) */
+    int32_t test_matrix;             /* RCP_TEST_*: the test matrix Omega_n of step 5 */
+    uint32_t compress_mask;          /* bit n set: compress mode n; 0 = every mode.  A mode
+                                        left out keeps Q_n = I (needs I_n <= 64) */
+    int32_t per_mode_p;              /* nonzero: mode_p[n] replaces p for mode n */
+    int32_t mode_p[RCP_MAX_NDIM];    /* per-mode oversampling, >= 0, k + mode_p[n] <= 64 */
 } rcp_problem;
 
 /* Written on the device by rcp_als / rcp_decompose. */
@@ -238,11 +264,10 @@ rcp_status rcp_decompose_noalloc(const rcp_problem* prob, const float* X, float*
 rcp_status rcp_get_bases(rcp_plan plan, float** Q);
 rcp_status rcp_get_core(rcp_plan plan, float** core, int64_t* core_dims);
 
-/* Rows [row0, row0 + nrows) of the Gaussian test matrix Omega of a mode,
- * width l <= 64 (nrows x l row-major, device).  Omega[j, c] is a pure
- * function of (seed, mode, batch 0, j, c): Philox4x32-10 on the counter
- * (j mod 2^32, j >> 32, c / 4, mode) with key (seed mod 2^32, seed >> 32),
- * uniforms ((x >> 8) + 1) 2^-24, Box-Muller on the pairs (u0,u1), (u2,u3). */
+/* Rows [row0, row0 + nrows) of the test matrix Omega of a mode, width
+ * l <= 64 (nrows x l row-major, device), of the plan's kind (GAUSSIAN,
+ * UNIFORM or HALTON as rcp_problem.test_matrix describes, batch 0; for
+ * COLUMNS see rcp_debug_columns). */
 rcp_status rcp_debug_omega(rcp_plan plan, int32_t mode, int64_t row0, int64_t nrows,
                            int32_t l, float* omega);
 
@@ -253,6 +278,11 @@ rcp_status rcp_debug_omega(rcp_plan plan, int32_t mode, int64_t row0, int64_t nr
  * ngroups in [1, 16]. */
 rcp_status rcp_debug_philox(rcp_plan plan, int32_t mode, int64_t row0, int64_t nrows,
                             int32_t ngroups, uint32_t* words);
+
+/* The l column indices (device int64, sorted ascending) that the COLUMNS
+ * test matrix selects out of J for a mode (seed of the plan, batch 0).
+ * RCP_ERR_INVALID_ARG unless 1 <= l <= min(J, 64). */
+rcp_status rcp_debug_columns(rcp_plan plan, int32_t mode, int64_t J, int32_t l, int64_t* idx);
 
 /* Per-kernel timing of a plan's launches (for roofline reporting).
  * rcp_profile(plan, 1) starts recording a HIP event pair around every kernel

@@ -56,7 +56,11 @@ class Plan:
     def __init__(self, dims: Sequence[int], k: int, p: int = 10, q: int = 2,
                  max_iters: int = 50, tol: float = 0.0, seed: int = 0,
                  scheme: str = "sequential", precision: str = "fp32", device="cuda",
-                 solver: str = "als"):
+                 solver: str = "als", test_matrix: str = "gaussian",
+                 modes: Optional[Sequence[int]] = None, p_modes: Optional[Sequence[int]] = None):
+        """``test_matrix``: "gaussian", "uniform", "halton" or "columns";
+        ``modes``: the modes Algorithm 1 compresses (default all; the others
+        keep Q_n = I); ``p_modes``: oversampling per mode in place of ``p``."""
         torch = _torch()
         self.lib = _lib.load()
         self.dims = [int(d) for d in dims]
@@ -65,10 +69,15 @@ class Plan:
         self.R = int(k)
         self.p = int(p)
         self.q = int(q)
-        self.l = [sketch_width(k, p, d) for d in self.dims]
+        self.p_modes = [int(p)] * self.N if p_modes is None else [int(v) for v in p_modes]
+        if len(self.p_modes) != self.N:
+            raise ValueError(f"p_modes needs {self.N} entries")
+        self.modes = list(range(self.N)) if modes is None else sorted({int(m) for m in modes})
+        self.l = [sketch_width(k, self.p_modes[n], d) if n in self.modes else d
+                  for n, d in enumerate(self.dims)]
         self.device = torch.device(device)
         self.problem = _lib.make_problem(self.dims, k, p, q, max_iters, tol, seed, precision, scheme,
-                                         solver)
+                                         solver, test_matrix, modes, p_modes)
         nbytes = ctypes.c_size_t(0)
         _lib.check(self.lib.rcp_workspace_size(ctypes.byref(self.problem), ctypes.byref(nbytes)),
                    "rcp_workspace_size")
@@ -108,7 +117,7 @@ class Plan:
         """Orthonormal basis Q_n (I_n x l) of mode ``mode`` (Algorithm 1 steps 3-12)."""
         _f32(T, "T")
         cur = list(T.shape) if cur_dims is None else [int(d) for d in cur_dims]
-        l = sketch_width(self.k, self.p, cur[mode])
+        l = sketch_width(self.k, self.p_modes[mode], cur[mode])
         Q = self._empty((cur[mode], l))
         _lib.check(self.lib.rcp_sketch(self.handle, ctypes.c_void_p(T.data_ptr()),
                                        _lib.dims_array(cur), int(mode),
@@ -274,6 +283,14 @@ class Plan:
                                             ctypes.c_void_p(out.data_ptr())), "rcp_debug_omega")
         return out
 
+    def columns(self, mode: int, J: int, l: int):
+        """The l unfolding columns (ascending, int64) that the column-selection
+        sketch of mode ``mode`` takes out of J."""
+        out = self._empty((l,), dtype=_torch().int64)
+        _lib.check(self.lib.rcp_debug_columns(self.handle, int(mode), int(J), int(l),
+                                              ctypes.c_void_p(out.data_ptr())), "rcp_debug_columns")
+        return out
+
     def philox_words(self, mode: int, row0: int, nrows: int, ngroups: int):
         """Raw Philox4x32-10 words (nrows x ngroups x 4, int32 bit patterns of
         the uint32 words) behind rows [row0, row0 + nrows) of Omega_mode."""
@@ -291,7 +308,7 @@ class Batch:
     non-default stream records the work in a HIP graph on the first call).
 
     problems: sequence of dicts with keys dims, k and optionally p, q,
-    max_iters, tol, seed, precision, scheme.
+    max_iters, tol, seed, precision, scheme, test_matrix, modes, p_modes.
     """
 
     def __init__(self, problems, device="cuda"):
@@ -307,7 +324,9 @@ class Batch:
             arr[i] = _lib.make_problem(dims, pr["k"], pr.get("p", 10), pr.get("q", 2),
                                        pr.get("max_iters", 50), pr.get("tol", 0.0),
                                        pr.get("seed", 0), pr.get("precision", "fp32"),
-                                       pr.get("scheme", "sequential"))
+                                       pr.get("scheme", "sequential"), "als",
+                                       pr.get("test_matrix", "gaussian"), pr.get("modes"),
+                                       pr.get("p_modes"))
             self.dims.append(dims)
             self.k.append(int(pr["k"]))
         self._problems = arr
@@ -388,10 +407,11 @@ class Batch:
 
 def decompose(X, k: int, p: int = 10, q: int = 2, iters: int = 50, tol: float = 0.0,
               seed: int = 0, scheme: str = "sequential", precision: str = "fp32",
-              solver: str = "als"):
+              solver: str = "als", test_matrix: str = "gaussian",
+              modes: Optional[Sequence[int]] = None, p_modes: Optional[Sequence[int]] = None):
     """Randomized CP of X (Algorithm 2, or Algorithm 3 with solver="bcd").
     Returns (lambda, [A_n], info dict)."""
     plan = Plan(list(X.shape), k, p, q, iters, tol, seed, scheme, precision, device=X.device,
-                solver=solver)
+                solver=solver, test_matrix=test_matrix, modes=modes, p_modes=p_modes)
     lam, A, info = plan.decompose(X)
     return lam, A, Plan.read_info(info)

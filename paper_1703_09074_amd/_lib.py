@@ -33,6 +33,7 @@ KERNEL_CLASSES = ["sketch", "power", "contract_in", "contract_out", "reduce", "q
                   "expand", "other", "bcd"]
 SCHEMES = {"sequential": 0, "independent": 1}
 SOLVERS = {"als": 0, "bcd": 1}
+TEST_MATRICES = {"gaussian": 0, "uniform": 1, "halton": 2, "columns": 3}
 
 
 class Problem(ctypes.Structure):
@@ -48,6 +49,10 @@ class Problem(ctypes.Structure):
         ("solver", ctypes.c_int32),
         ("tol", ctypes.c_double),
         ("seed", ctypes.c_uint64),
+        ("test_matrix", ctypes.c_int32),
+        ("compress_mask", ctypes.c_uint32),
+        ("per_mode_p", ctypes.c_int32),
+        ("mode_p", ctypes.c_int32 * RCP_MAX_NDIM),
     ]
 
 
@@ -83,6 +88,7 @@ SIGNATURES = {
     "rcp_get_core": (_st, [_vp, ctypes.POINTER(_vp), _i64p]),
     "rcp_debug_omega": (_st, [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _vp]),
     "rcp_debug_philox": (_st, [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _vp]),
+    "rcp_debug_columns": (_st, [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, _vp]),
     "rcp_profile": (_st, [_vp, ctypes.c_int32]),
     "rcp_profile_read": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -153,7 +159,7 @@ def dims_array(dims):
 
 
 def make_problem(dims, k, p, q, max_iters, tol, seed, precision="fp32", scheme="sequential",
-                 solver="als"):
+                 solver="als", test_matrix="gaussian", modes=None, p_modes=None):
     prob = Problem()
     prob.ndim = len(dims)
     prob.k = int(k)
@@ -167,4 +173,12 @@ def make_problem(dims, k, p, q, max_iters, tol, seed, precision="fp32", scheme="
     prob.solver = SOLVERS[solver] if isinstance(solver, str) else int(solver)
     prob.tol = float(tol)
     prob.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    prob.test_matrix = TEST_MATRICES[test_matrix] if isinstance(test_matrix, str) else int(test_matrix)
+    if modes is not None and not list(modes):
+        raise ValueError("at least one mode must be compressed")
+    prob.compress_mask = 0 if modes is None else sum(1 << int(m) for m in modes)
+    prob.per_mode_p = 0 if p_modes is None else 1
+    if p_modes is not None:
+        for i, v in enumerate(p_modes):
+            prob.mode_p[i] = int(v)
     return prob

@@ -32,12 +32,24 @@ struct Layout {
     int64_t Imax;
     int LPmax;
     // offsets (bytes)
-    size_t part, red1, y64, qt, sq, norm, status, qb[RCP_MAX_NDIM], tb[2], zbuf, als, alsst,
+    int ncompressed;       // modes Algorithm 1 compresses (the others keep Q_n = I)
+    size_t part, red1, y64, qt, sq, norm, status, colidx, qb[RCP_MAX_NDIM], tb[2], zbuf, als, alsst,
         at[RCP_MAX_NDIM], lam, raw, egram, total;
     int egram_stride;      // doubles per mode of egram
     size_t part_elems, tb_elems[2], zbuf_elems, als_doubles;
     int64_t core_dims[RCP_MAX_NDIM];
 };
+
+// Algorithm 1 variants (the remarks after Algorithm 1): which modes are
+// compressed and their oversampling.
+bool mode_compressed(const rcp_problem* p, int n) {
+    return p->compress_mask == 0 || ((p->compress_mask >> n) & 1u) != 0;
+}
+int mode_oversampling(const rcp_problem* p, int n) { return p->per_mode_p ? p->mode_p[n] : p->p; }
+// l_n for a (current) mode size I: the sketch width, or I for a mode left out
+int64_t mode_width(const rcp_problem* p, int n, int64_t I) {
+    return mode_compressed(p, n) ? std::min<int64_t>(p->k + mode_oversampling(p, n), I) : I;
+}
 
 bool valid_problem(const rcp_problem* p) {
     if (p == nullptr) return false;
@@ -50,10 +62,31 @@ bool valid_problem(const rcp_problem* p) {
         p->precision != RCP_PREC_FP16)
         return false;
     if (p->solver != RCP_SOLVER_ALS && p->solver != RCP_SOLVER_BCD) return false;
+    if (p->test_matrix < RCP_TEST_GAUSSIAN || p->test_matrix > RCP_TEST_COLUMNS) return false;
+    if ((p->compress_mask >> p->ndim) != 0) return false;
+    if (p->per_mode_p != 0 && p->per_mode_p != 1) return false;
     for (int n = 0; n < p->ndim; ++n) {
         if (p->dims[n] < 1 || p->dims[n] > (int64_t)1 << 40) return false;
-        const int64_t l = std::min<int64_t>(p->k + p->p, p->dims[n]);
-        if (p->k > l) return false;
+        if (mode_compressed(p, n)) {
+            const int pn = mode_oversampling(p, n);
+            if (pn < 0 || p->k + pn > RCP_MAX_L) return false;
+        } else if (p->dims[n] > RCP_MAX_L) {
+            return false;              // a mode kept whole must fit the core solvers
+        }
+        if (p->k > mode_width(p, n, p->dims[n])) return false;
+    }
+    if (p->test_matrix == RCP_TEST_COLUMNS) {
+        // every compressed mode needs l_n <= J_n (the other current sizes)
+        int64_t cur[RCP_MAX_NDIM];
+        for (int n = 0; n < p->ndim; ++n) cur[n] = p->dims[n];
+        for (int n = 0; n < p->ndim; ++n) {
+            if (!mode_compressed(p, n)) continue;
+            double J = 1.0;
+            for (int m = 0; m < p->ndim; ++m)
+                if (m != n) J *= (double)cur[m];
+            if ((double)mode_width(p, n, cur[n]) > J) return false;
+            if (p->scheme == RCP_SCHEME_SEQUENTIAL) cur[n] = mode_width(p, n, cur[n]);
+        }
     }
     // total element count must stay well inside int64
     double S = 1.0;
@@ -71,7 +104,7 @@ Layout make_layout(const rcp_problem* p) {
     L.LPmax = 16;
     for (int n = 0; n < L.N; ++n) {
         L.dims[n] = p->dims[n];
-        L.l[n] = (int)std::min<int64_t>(p->k + p->p, p->dims[n]);
+        L.l[n] = (int)mode_width(p, n, p->dims[n]);
         L.LP[n] = lp_of(L.l[n]);
         L.Imax = std::max(L.Imax, p->dims[n]);
         L.LPmax = std::max(L.LPmax, L.LP[n]);
@@ -81,15 +114,19 @@ Layout make_layout(const rcp_problem* p) {
     for (int n = 0; n < L.N; ++n)
         part = std::max(part, (size_t)kPmax * (size_t)L.dims[n] * (size_t)L.LP[n]);
     L.part_elems = part;
-    // compressed tensors: output of mode n goes to buffer n % 2
+    // compressed tensors: the c-th compressed mode writes buffer c % 2
     int64_t cur[RCP_MAX_NDIM];
     for (int n = 0; n < L.N; ++n) cur[n] = L.dims[n];
     L.tb_elems[0] = L.tb_elems[1] = 0;
+    L.ncompressed = 0;
     for (int n = 0; n < L.N; ++n) {
+        if (!mode_compressed(p, n)) continue;
         cur[n] = L.l[n];
         int64_t s = 1;
         for (int m = 0; m < L.N; ++m) s *= cur[m];
-        L.tb_elems[n % 2] = std::max(L.tb_elems[n % 2], (size_t)s);
+        const int buf = L.ncompressed % 2;
+        L.tb_elems[buf] = std::max(L.tb_elems[buf], (size_t)s);
+        ++L.ncompressed;
     }
     for (int n = 0; n < L.N; ++n) L.core_dims[n] = L.l[n];
     // stored Z for modes whose tile does not fit the fused power kernel
@@ -115,6 +152,7 @@ Layout make_layout(const rcp_problem* p) {
     L.sq = take((size_t)kPmax * nib * sizeof(double));
     L.norm = take(64 * sizeof(double));
     L.status = take(sizeof(int32_t));
+    L.colidx = take(RCP_MAX_L * sizeof(int64_t));
     for (int n = 0; n < L.N; ++n) L.qb[n] = take((size_t)L.dims[n] * L.l[n] * sizeof(float));
     L.tb[0] = take(L.tb_elems[0] * sizeof(float));
     L.tb[1] = take(L.tb_elems[1] * sizeof(float));
@@ -251,7 +289,7 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
                        double* norm_out) {
     const int N = pl->L.N;
     const int64_t I = cur[mode];
-    const int l = (int)std::min<int64_t>(pl->prob.k + pl->prob.p, I);
+    const int l = (int)std::min<int64_t>(pl->prob.k + mode_oversampling(&pl->prob, mode), I);
     const int LP = lp_of(l);
     const StreamGeom g = make_geom(T, cur, N, mode);
     const int P = (int)std::max<int64_t>(1, std::min<int64_t>(pl->P, g.ntiles));
@@ -268,13 +306,28 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
     // product (I l^2) in float64; two passes, three for the returned basis
     const double qr_bytes = (double)I * l * 8.0 + (double)I * LP * 4.0;
     const double qr_flops = 2.0 * 2.0 * (double)I * l * l;
-    RCP_TRY(timed(pl, RCP_KERNEL_SKETCH, 4.0 * S + 4.0 * I * l, 2.0 * S * l, [&] {
-        return launch_contract_out(g, l, nullptr, pl->prob.seed, tag, part, P,
-                                   norm_out ? sq : nullptr, pl->stream, pl->prob.precision,
-                                   pl->mb_cap);
-    }));
-    rcp_status st = reduce_y(pl, P, I, LP, norm_out ? sq : nullptr, P * nIB, norm_out);
-    if (st != RCP_OK) return st;
+    rcp_status st = RCP_OK;
+    if (pl->prob.test_matrix == RCP_TEST_COLUMNS) {
+        // randomly selected columns in place of the product (the remark after
+        // Algorithm 1): the sketch is a gather of l unfolding columns
+        int64_t* idx = pl->at<int64_t>(pl->L.colidx);
+        if ((double)l > J) return RCP_ERR_INVALID_ARG;
+        RCP_TRY(launch_select_columns(pl->prob.seed, tag, (int64_t)J, l, idx, pl->stream));
+        RCP_TRY(timed(pl, RCP_KERNEL_SKETCH, 4.0 * I * l + 8.0 * I * LP, 0.0,
+                      [&] { return launch_gather_columns(g, l, idx, Y, LP, pl->stream); }));
+        if (norm_out != nullptr) {
+            const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kPmax, ((int64_t)S + 255) / 256));
+            RCP_TRY(launch_sumsq(T, (int64_t)S, sq, nb, norm_out, pl->stream));
+        }
+    } else {
+        RCP_TRY(timed(pl, RCP_KERNEL_SKETCH, 4.0 * S + 4.0 * I * l, 2.0 * S * l, [&] {
+            return launch_contract_out(g, l, nullptr, pl->prob.seed, tag, pl->prob.test_matrix,
+                                       part, P, norm_out ? sq : nullptr, pl->stream,
+                                       pl->prob.precision, pl->mb_cap);
+        }));
+        st = reduce_y(pl, P, I, LP, norm_out ? sq : nullptr, P * nIB, norm_out);
+        if (st != RCP_OK) return st;
+    }
     const bool fused = power_fused_fits(I, l, pl->smem_limit);
     for (int it = 0; it < pl->prob.q; ++it) {
         RCP_TRY(timed(pl, RCP_KERNEL_QR, qr_bytes, 2.0 * qr_flops,
@@ -287,7 +340,7 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
             RCP_TRY(timed(pl, RCP_KERNEL_CONTRACT_IN, 4.0 * S + 4.0 * J * LP, 2.0 * S * l,
                           [&] { return launch_contract_in(g, l, Qt, LP, Z, P, pl->stream, pl->prob.precision); }));
             RCP_TRY(timed(pl, RCP_KERNEL_CONTRACT_OUT, 4.0 * S + 4.0 * J * LP, 2.0 * S * l, [&] {
-                return launch_contract_out(g, l, Z, 0, 0, part, P, nullptr, pl->stream,
+                return launch_contract_out(g, l, Z, 0, 0, 0, part, P, nullptr, pl->stream,
                                            pl->prob.precision, pl->mb_cap);
             }));
         }
@@ -303,7 +356,7 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
 rcp_status compress_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int mode,
                          float* T_out) {
     const int64_t I = cur[mode];
-    const int l = (int)std::min<int64_t>(pl->prob.k + pl->prob.p, I);
+    const int l = (int)std::min<int64_t>(pl->prob.k + mode_oversampling(&pl->prob, mode), I);
     const StreamGeom g = make_geom(T, cur, pl->L.N, mode);
     const int P = (int)std::max<int64_t>(1, std::min<int64_t>(pl->P, g.ntiles));
     const double S = (double)count_of(cur, pl->L.N);
@@ -637,7 +690,7 @@ rcp_status rcp_compress(rcp_plan plan, const float* T, const int64_t* cur_dims, 
     if (!aligned(T, 4) || !aligned(Q, 4) || !aligned(T_out, 4)) return RCP_ERR_INVALID_ARG;
     const int N = plan->L.N;
     const int64_t I = cur_dims[mode];
-    const int l = (int)std::min<int64_t>(plan->prob.k + plan->prob.p, I);
+    const int l = (int)std::min<int64_t>(plan->prob.k + mode_oversampling(&plan->prob, mode), I);
     const int64_t nin = count_of(cur_dims, N);
     const int64_t nout = nin / I * l;
     if (overlap(T, (size_t)nin * 4, T_out, (size_t)nout * 4)) return RCP_ERR_INVALID_ARG;
@@ -688,41 +741,64 @@ rcp_status rcp_expand(rcp_plan plan, const float* const* Q, const float* const* 
 
 namespace {
 
+// Where the core ends up: the buffer of the last compressed mode.
+float* core_location(rcp_plan_t* plan) {
+    return plan->at<float>(plan->L.tb[(plan->L.ncompressed - 1) % 2]);
+}
+
 // Algorithm 1 over every mode: leaves the bases in the plan's qb buffers and
-// the core in the tb buffer of the last mode; *core_out points at it.
+// the core in the buffer of the last compressed mode; *core_out points at it.
+// A mode left out of rcp_problem.compress_mask gets Q_n = I and keeps its
+// size; ||X||^2 comes from the first sketch pass when mode 0 takes a
+// streamed sketch, else from a separate pass.
 rcp_status compress_all(rcp_plan_t* plan, const float* X, const float** core_out) {
     const Layout& L = plan->L;
     const int N = L.N;
+    const rcp_problem* pr = &plan->prob;
     double* normX2 = plan->at<double>(L.norm);
     float* Qb[RCP_MAX_NDIM];
     for (int n = 0; n < N; ++n) Qb[n] = plan->at<float>(L.qb[n]);
     int64_t cur[RCP_MAX_NDIM];
     for (int n = 0; n < N; ++n) cur[n] = L.dims[n];
+    const bool norm_in_sketch = mode_compressed(pr, 0) && pr->test_matrix != RCP_TEST_COLUMNS;
+    if (!norm_in_sketch) {
+        const int64_t S = count_of(cur, N);
+        const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kPmax, (S + 255) / 256));
+        RCP_TRY(launch_sumsq(X, S, plan->at<double>(L.sq), nb, normX2, plan->stream));
+    }
+    for (int n = 0; n < N; ++n)
+        if (!mode_compressed(pr, n)) RCP_TRY(launch_eye(Qb[n], L.dims[n], L.l[n], plan->stream));
     const float* T = X;
+    int c = 0;
     rcp_status st;
-    if (plan->prob.scheme == RCP_SCHEME_SEQUENTIAL) {
+    if (pr->scheme == RCP_SCHEME_SEQUENTIAL) {
         for (int n = 0; n < N; ++n) {
-            st = sketch_impl(plan, T, cur, n, Qb[n], n == 0 ? normX2 : nullptr);
+            if (!mode_compressed(pr, n)) continue;
+            st = sketch_impl(plan, T, cur, n, Qb[n], (n == 0 && norm_in_sketch) ? normX2 : nullptr);
             if (st != RCP_OK) return st;
-            float* out = plan->at<float>(L.tb[n % 2]);
+            float* out = plan->at<float>(L.tb[c % 2]);
             st = compress_impl(plan, T, cur, n, out);
             if (st != RCP_OK) return st;
             cur[n] = L.l[n];
             T = out;
+            ++c;
         }
     } else {
         for (int n = 0; n < N; ++n) {
-            st = sketch_impl(plan, X, cur, n, Qb[n], n == 0 ? normX2 : nullptr);
+            if (!mode_compressed(pr, n)) continue;
+            st = sketch_impl(plan, X, cur, n, Qb[n], (n == 0 && norm_in_sketch) ? normX2 : nullptr);
             if (st != RCP_OK) return st;
         }
         for (int n = 0; n < N; ++n) {
+            if (!mode_compressed(pr, n)) continue;
             RCP_TRY(launch_pad_q(Qb[n], L.dims[n], L.l[n], plan->at<float>(L.qt), L.LP[n],
                                  plan->stream));
-            float* out = plan->at<float>(L.tb[n % 2]);
+            float* out = plan->at<float>(L.tb[c % 2]);
             st = compress_impl(plan, T, cur, n, out);
             if (st != RCP_OK) return st;
             cur[n] = L.l[n];
             T = out;
+            ++c;
         }
     }
     *core_out = T;
@@ -1073,8 +1149,7 @@ rcp_status rcp_batch_init(rcp_batch* batch, const rcp_problem* probs, int32_t co
         st = rcp_init(&pl, &probs[i], ws + B.off[i], B.size[i], b->side[i % kBatchStreams]);
         if (st != RCP_OK) { rcp_batch_destroy(b); return st; }
         b->plans.push_back(pl);
-        const Layout& L = pl->L;
-        const float* core = pl->at<float>(L.tb[(L.N - 1) % 2]);
+        const float* core = core_location(pl);
         b->h_als.push_back(core_als_args(pl, core, nullptr));
         b->h_exp.push_back(core_expand_args(pl, nullptr, nullptr));
     }
@@ -1205,7 +1280,7 @@ rcp_status rcp_get_bases(rcp_plan plan, float** Q) {
 
 rcp_status rcp_get_core(rcp_plan plan, float** core, int64_t* core_dims) {
     if (plan == nullptr || core == nullptr) return RCP_ERR_INVALID_ARG;
-    *core = plan->at<float>(plan->L.tb[(plan->L.N - 1) % 2]);
+    *core = core_location(plan);
     if (core_dims != nullptr)
         for (int n = 0; n < plan->L.N; ++n) core_dims[n] = plan->L.core_dims[n];
     return RCP_OK;
@@ -1216,9 +1291,18 @@ rcp_status rcp_debug_omega(rcp_plan plan, int32_t mode, int64_t row0, int64_t nr
     if (plan == nullptr || omega == nullptr || mode < 0 || mode >= 256 || row0 < 0 || nrows < 0 ||
         l < 1 || l > RCP_MAX_L)
         return RCP_ERR_INVALID_ARG;
-    if (!aligned(omega, 4)) return RCP_ERR_INVALID_ARG;
-    RCP_TRY(launch_omega(plan->prob.seed, omega_stream_tag(0, (uint32_t)mode), row0, nrows, l, omega,
-                         plan->stream));
+    if (!aligned(omega, 4) || plan->prob.test_matrix == RCP_TEST_COLUMNS) return RCP_ERR_INVALID_ARG;
+    RCP_TRY(launch_omega(plan->prob.seed, omega_stream_tag(0, (uint32_t)mode), plan->prob.test_matrix,
+                         row0, nrows, l, omega, plan->stream));
+    return RCP_OK;
+}
+
+rcp_status rcp_debug_columns(rcp_plan plan, int32_t mode, int64_t J, int32_t l, int64_t* idx) {
+    if (plan == nullptr || idx == nullptr || mode < 0 || mode >= 256 || l < 1 || l > RCP_MAX_L ||
+        J < l || !aligned(idx, 8))
+        return RCP_ERR_INVALID_ARG;
+    RCP_TRY(launch_select_columns(plan->prob.seed, omega_stream_tag(0, (uint32_t)mode), J, l, idx,
+                                  plan->stream));
     return RCP_OK;
 }
 

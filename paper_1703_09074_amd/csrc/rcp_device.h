@@ -69,6 +69,61 @@ __device__ __forceinline__ void omega4(uint64_t seed, uint32_t tag, uint64_t j, 
     out[3] = rb * sb;
 }
 
+// Test-matrix kinds (values of rcp_problem.test_matrix generated in-kernel).
+constexpr int kOmegaGaussian = 0;
+constexpr int kOmegaUniform = 1;
+constexpr int kOmegaHalton = 2;
+
+// The first 64 primes: Halton base of columns 0..63.
+__device__ __forceinline__ uint32_t halton_base(int c) {
+    constexpr uint32_t p[64] = {2,   3,   5,   7,   11,  13,  17,  19,  23,  29,  31,  37,  41,
+                                43,  47,  53,  59,  61,  67,  71,  73,  79,  83,  89,  97,  101,
+                                103, 107, 109, 113, 127, 131, 137, 139, 149, 151, 157, 163, 167,
+                                173, 179, 181, 191, 193, 197, 199, 211, 223, 227, 229, 233, 239,
+                                241, 251, 257, 263, 269, 271, 277, 281, 283, 293, 307, 311};
+    return p[c & 63];
+}
+
+// Radical inverse of i >= 1 in base b (digits mirrored about the radix
+// point): the exact ratio num / b^digits, rounded once to float.
+__device__ __forceinline__ float radical_inverse(uint64_t i, uint32_t b) {
+    uint64_t num = 0, den = 1;
+    while (i > 0) {
+        const uint64_t q = i / b;
+        num = num * b + (i - q * b);
+        den *= b;
+        i = q;
+    }
+    return (float)((double)num / (double)den);
+}
+
+// Four entries of row j, columns 4g..4g+3, of a test matrix of the given kind.
+__device__ __forceinline__ void omega4k(int kind, uint64_t seed, uint32_t tag, uint64_t j,
+                                        uint32_t g, float out[4]) {
+    if (kind == kOmegaHalton) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int c = 4 * (int)g + v;
+            out[v] = (c < 64) ? radical_inverse(j + 1, halton_base(c)) : 0.0f;
+        }
+        return;
+    }
+    if (kind == kOmegaUniform) {
+        U4 c;
+        c.x = (uint32_t)j;
+        c.y = (uint32_t)(j >> 32);
+        c.z = g;
+        c.w = tag;
+        const U4 x = philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+        out[0] = uniform24(x.x);
+        out[1] = uniform24(x.y);
+        out[2] = uniform24(x.z);
+        out[3] = uniform24(x.w);
+        return;
+    }
+    omega4(seed, tag, j, g, out);
+}
+
 __device__ __forceinline__ uint32_t omega_tag(uint32_t batch, uint32_t mode) {
     return (batch << 8) | (mode & 0xFFu);
 }

@@ -29,8 +29,9 @@ StreamGeom make_geom(const float* T, const int64_t* dims, int ndim, int mode);
 // mb_cap: at most 64 * mb_cap rows per row block for modes of at most 512
 // rows (a tile shape the batched form's autotuner chooses; taller modes
 // always take 512-row blocks)
+// okind: the test matrix generated for a sketch (kOmega*, Z == null)
 hipError_t launch_contract_out(const StreamGeom& g, int l, const float* Z, uint64_t seed,
-                               uint32_t tag, float* part, int P, double* sq_part,
+                               uint32_t tag, int okind, float* part, int P, double* sq_part,
                                hipStream_t s, int precision, int mb_cap = 8);
 int contract_out_row_blocks(int64_t I, int mb_cap = 8);
 bool power_fused_fits(int64_t I, int l, size_t smem_limit);
@@ -40,8 +41,8 @@ hipError_t launch_contract_in(const StreamGeom& g, int l, const float* Qpadded, 
                               float* out, int P, hipStream_t s, int precision);
 // the 16-bit operand instantiations (stream_kernels_lp.hip)
 hipError_t launch_contract_out_lp(int precision, const StreamGeom& g, int l, const float* Z,
-                                  uint64_t seed, uint32_t tag, float* part, int P, double* sq_part,
-                                  hipStream_t s, int mb_cap);
+                                  uint64_t seed, uint32_t tag, int okind, float* part, int P,
+                                  double* sq_part, hipStream_t s, int mb_cap);
 hipError_t launch_power_fused_lp(int precision, const StreamGeom& g, int l, const float* Qt,
                                  float* part, int P, hipStream_t s);
 hipError_t launch_contract_in_lp(int precision, const StreamGeom& g, int l, const float* Qpadded,
@@ -74,8 +75,14 @@ hipError_t launch_reduce_partials(const float* part, int P, int64_t count, doubl
                                   hipStream_t s);
 hipError_t launch_sumsq(const float* x, int64_t count, double* part, int nblocks, double* out,
                         hipStream_t s);
-hipError_t launch_omega(uint64_t seed, uint32_t tag, int64_t row0, int64_t nrows, int l,
-                        float* out, hipStream_t s);
+hipError_t launch_omega(uint64_t seed, uint32_t tag, int okind, int64_t row0, int64_t nrows,
+                        int l, float* out, hipStream_t s);
+// the COLUMNS test matrix: l <= 64 sorted distinct indices out of J, and the
+// sketch made of those unfolding columns (I x ldy float64, zero past l)
+hipError_t launch_select_columns(uint64_t seed, uint32_t tag, int64_t J, int l, int64_t* idx,
+                                 hipStream_t s);
+hipError_t launch_gather_columns(const StreamGeom& g, int l, const int64_t* idx, double* Y, int ldy,
+                                 hipStream_t s);
 // the raw Philox4x32-10 words behind rows [row0, row0 + nrows) of Omega:
 // out[(r * ngroups + g) * 4 + i] is word i of column group g of row row0 + r
 hipError_t launch_philox_words(uint64_t seed, uint32_t tag, int64_t row0, int64_t nrows,

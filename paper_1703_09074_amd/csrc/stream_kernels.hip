@@ -65,7 +65,7 @@ __global__ void k_sum_doubles(const double* part, int n, double* out) {
 }
 
 // Rows [row0, row0+nrows) of Omega (nrows x l).
-__global__ __launch_bounds__(NT) void k_omega(uint64_t seed, uint32_t tag, int64_t row0,
+__global__ __launch_bounds__(NT) void k_omega(uint64_t seed, uint32_t tag, int okind, int64_t row0,
                                               int64_t nrows, int l, float* out) {
     const int ng = (l + 3) / 4;
     const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(NT) void k_omega(uint64_t seed, uint32_t tag, int64
     const int64_t r = e / ng;
     const int gi = (int)(e - r * ng);
     float z[4];
-    omega4(seed, tag, (uint64_t)(row0 + r), (uint32_t)gi, z);
+    omega4k(okind, seed, tag, (uint64_t)(row0 + r), (uint32_t)gi, z);
     for (int v = 0; v < 4; ++v) {
         const int c = 4 * gi + v;
         if (c < l) out[r * l + c] = z[v];
@@ -171,7 +171,7 @@ hipError_t launch_mttkrp(const StreamGeom& g, const KrSpec& kr, float* part, int
     const dim3 grid((unsigned)P, 1);
     hipError_t e = hipSuccess;
     RCP_NB_SWITCH(NBv, e = (launch_co<NB, 1, kWKr, kPrecFp32>(grid, smem, s, g, kr.R, nullptr, 0, 0,
-                                                              part, nullptr, kr)));
+                                                              0, part, nullptr, kr)));
     return e;
 }
 
@@ -222,11 +222,11 @@ bool power_fused_fits(int64_t I, int l, size_t smem_limit) {
 }
 
 hipError_t launch_contract_out(const StreamGeom& g, int l, const float* Z, uint64_t seed,
-                               uint32_t tag, float* part, int P, double* sq_part, hipStream_t s,
-                               int precision, int mb_cap) {
+                               uint32_t tag, int okind, float* part, int P, double* sq_part,
+                               hipStream_t s, int precision, int mb_cap) {
     if (precision == kPrecFp32)
-        return launch_contract_out_t<kPrecFp32>(g, l, Z, seed, tag, part, P, sq_part, s, mb_cap);
-    return launch_contract_out_lp(precision, g, l, Z, seed, tag, part, P, sq_part, s, mb_cap);
+        return launch_contract_out_t<kPrecFp32>(g, l, Z, seed, tag, okind, part, P, sq_part, s, mb_cap);
+    return launch_contract_out_lp(precision, g, l, Z, seed, tag, okind, part, P, sq_part, s, mb_cap);
 }
 
 hipError_t launch_power_fused(const StreamGeom& g, int l, const float* Qt, float* part, int P,
@@ -266,13 +266,75 @@ hipError_t launch_sumsq(const float* x, int64_t count, double* part, int nblocks
     return hipGetLastError();
 }
 
-hipError_t launch_omega(uint64_t seed, uint32_t tag, int64_t row0, int64_t nrows, int l,
-                        float* out, hipStream_t s) {
+hipError_t launch_omega(uint64_t seed, uint32_t tag, int okind, int64_t row0, int64_t nrows,
+                        int l, float* out, hipStream_t s) {
     const int ng = (l + 3) / 4;
     const int64_t n = nrows * ng;
     const unsigned blocks = (unsigned)((n + NT - 1) / NT);
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_omega, dim3(blocks), dim3(NT), 0, s, seed, tag, row0, nrows, l, out);
+    hipLaunchKernelGGL(k_omega, dim3(blocks), dim3(NT), 0, s, seed, tag, okind, row0, nrows, l, out);
+    return hipGetLastError();
+}
+
+// l distinct column indices out of J, sorted (the COLUMNS test matrix):
+// Floyd's sampling without replacement on one thread, draw s from the
+// Philox words of counter (s mod 2^32, s >> 32, 2^31, tag).
+__global__ void k_select_columns(uint64_t seed, uint32_t tag, int64_t J, int l, int64_t* idx) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int64_t sel[64];
+    for (int s = 0; s < l; ++s) {
+        const int64_t i = J - l + s;
+        U4 c;
+        c.x = (uint32_t)s;
+        c.y = 0u;
+        c.z = 0x80000000u;
+        c.w = tag;
+        const U4 x = philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const uint64_t x64 = ((uint64_t)x.y << 32) | (uint64_t)x.x;
+        const int64_t t = (int64_t)__umul64hi(x64, (uint64_t)(i + 1));
+        bool seen = false;
+        for (int u = 0; u < s; ++u) seen = seen || sel[u] == t;
+        sel[s] = seen ? i : t;
+    }
+    for (int a = 1; a < l; ++a) {          // insertion sort
+        const int64_t v = sel[a];
+        int b = a - 1;
+        while (b >= 0 && sel[b] > v) { sel[b + 1] = sel[b]; --b; }
+        sel[b + 1] = v;
+    }
+    for (int s = 0; s < l; ++s) idx[s] = sel[s];
+}
+
+// Y (I x ldy, float64) <- the selected columns of the mode-n unfolding:
+// column c of Y is unfolding column j = idx[c] = a Rr + b, zero for c >= l.
+__global__ __launch_bounds__(NT) void k_gather_columns(StreamGeom g, int l, const int64_t* idx,
+                                                       double* Y, int ldy) {
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= g.I * ldy) return;
+    const int64_t i = e / ldy;
+    const int c = (int)(e - i * ldy);
+    double v = 0.0;
+    if (c < l) {
+        const int64_t j = idx[c];
+        const int64_t a = j / g.Rr, b = j - a * g.Rr;
+        v = (double)g.T[(a * g.Is + i) * g.Rr + b];
+    }
+    Y[e] = v;
+}
+
+hipError_t launch_select_columns(uint64_t seed, uint32_t tag, int64_t J, int l, int64_t* idx,
+                                 hipStream_t s) {
+    if (l < 1 || l > 64 || J < l) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_select_columns, dim3(1), dim3(64), 0, s, seed, tag, J, l, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_columns(const StreamGeom& g, int l, const int64_t* idx, double* Y, int ldy,
+                                 hipStream_t s) {
+    const int64_t n = g.I * ldy;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_columns, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, g, l,
+                       idx, Y, ldy);
     return hipGetLastError();
 }
 

@@ -8,10 +8,10 @@
 namespace rcp {
 
 hipError_t launch_contract_out_lp(int precision, const StreamGeom& g, int l, const float* Z,
-                                  uint64_t seed, uint32_t tag, float* part, int P, double* sq_part,
-                                  hipStream_t s, int mb_cap) {
-    if (precision == kPrecBf16) return launch_contract_out_t<kPrecBf16>(g, l, Z, seed, tag, part, P, sq_part, s, mb_cap);
-    if (precision == kPrecFp16) return launch_contract_out_t<kPrecFp16>(g, l, Z, seed, tag, part, P, sq_part, s, mb_cap);
+                                  uint64_t seed, uint32_t tag, int okind, float* part, int P,
+                                  double* sq_part, hipStream_t s, int mb_cap) {
+    if (precision == kPrecBf16) return launch_contract_out_t<kPrecBf16>(g, l, Z, seed, tag, okind, part, P, sq_part, s, mb_cap);
+    if (precision == kPrecFp16) return launch_contract_out_t<kPrecFp16>(g, l, Z, seed, tag, okind, part, P, sq_part, s, mb_cap);
     return hipErrorInvalidValue;
 }
 

@@ -348,8 +348,8 @@ __device__ __forceinline__ float kr_entry(const KrSpec& kr, const float* Fs, uin
 
 template <int NB, int MB, int WK, bool CB, int PR>
 __global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const float* Z,
-                                                     uint64_t seed, uint32_t tag, float* part,
-                                                     double* sq_part, KrSpec kr) {
+                                                     uint64_t seed, uint32_t tag, int okind,
+                                                     float* part, double* sq_part, KrSpec kr) {
     constexpr int LPc = NB * 16;
     constexpr int IB = 64 * MB;
     extern __shared__ __align__(16) float smem[];
@@ -413,7 +413,7 @@ __global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const
             for (int e = threadIdx.x; e < JT * NG; e += NTS) {
                 const int jj = e / NG, gi = e % NG;
                 float z[4] = {0.f, 0.f, 0.f, 0.f};
-                if (jj < ti.width) omega4(seed, tag, (uint64_t)(ti.j0 + jj), (uint32_t)gi, z);
+                if (jj < ti.width) omega4k(okind, seed, tag, (uint64_t)(ti.j0 + jj), (uint32_t)gi, z);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int c = 4 * gi + v;
@@ -752,13 +752,13 @@ inline size_t contract_in_smem(int NB) {
 
 template <int NB, int MB, int WK, int PR>
 static hipError_t launch_co(dim3 grid, size_t smem, hipStream_t s, const StreamGeom& g, int l,
-                            const float* Z, uint64_t seed, uint32_t tag, float* part,
+                            const float* Z, uint64_t seed, uint32_t tag, int okind, float* part,
                             double* sq, const KrSpec& kr = KrSpec{}) {
     auto k = g.caseB ? k_contract_out<NB, MB, WK, true, PR> : k_contract_out<NB, MB, WK, false, PR>;
     hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)smem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, grid, dim3(NTS), smem, s, g, l, Z, seed, tag, part, sq, kr);
+    hipLaunchKernelGGL(k, grid, dim3(NTS), smem, s, g, l, Z, seed, tag, okind, part, sq, kr);
     return hipGetLastError();
 }
 
@@ -784,7 +784,7 @@ static hipError_t launch_co(dim3 grid, size_t smem, hipStream_t s, const StreamG
 
 template <int PR>
 hipError_t launch_contract_out_t(const StreamGeom& g, int l, const float* Z, uint64_t seed,
-                                 uint32_t tag, float* part, int P, double* sq_part,
+                                 uint32_t tag, int okind, float* part, int P, double* sq_part,
                                  hipStream_t s, int mb_cap) {
     const int NBv = lp_blocks(l);
     int MBv = (int)((g.I + 63) / 64);
@@ -797,9 +797,9 @@ hipError_t launch_contract_out_t(const StreamGeom& g, int l, const float* Z, uin
     const dim3 grid((unsigned)P, nIB);
     hipError_t e = hipSuccess;
     if (Z == nullptr) {
-        RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_co<NB, MB, kWOmega, PR>(grid, smem, s, g, l, Z, seed, tag, part, sq_part))));
+        RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_co<NB, MB, kWOmega, PR>(grid, smem, s, g, l, Z, seed, tag, okind, part, sq_part))));
     } else {
-        RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_co<NB, MB, kWStored, PR>(grid, smem, s, g, l, Z, seed, tag, part, sq_part))));
+        RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_co<NB, MB, kWStored, PR>(grid, smem, s, g, l, Z, seed, tag, okind, part, sq_part))));
     }
     return e;
 }

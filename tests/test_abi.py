@@ -113,6 +113,35 @@ def test_invalid_dims_rejected(lib):
     assert lib.rcp_workspace_size(None, None) == _lib.RCP_ERR_INVALID_ARG
 
 
+def test_variant_fields_validated(lib):
+    """Algorithm 1 variants: the test-matrix kind, the mode subset and the
+    per-mode oversampling are checked on the host."""
+    ok = _lib.make_problem((40, 30, 20), 5, 5, 1, 10, 0.0, 1, test_matrix="halton",
+                           modes=[0, 2], p_modes=[3, 0, 9])
+    assert _ws(lib, ok)[0] == _lib.RCP_OK
+    prob = _lib.make_problem((40, 30, 20), 5, 5, 1, 10, 0.0, 1)
+    prob.test_matrix = 4
+    assert _ws(lib, prob)[0] == _lib.RCP_ERR_INVALID_ARG
+    prob = _lib.make_problem((40, 30, 20), 5, 5, 1, 10, 0.0, 1)
+    prob.compress_mask = 1 << 3                       # a mode the tensor does not have
+    assert _ws(lib, prob)[0] == _lib.RCP_ERR_INVALID_ARG
+    # a mode kept whole must fit the core solvers (<= 64)
+    big = _lib.make_problem((40, 65, 20), 5, 5, 1, 10, 0.0, 1, modes=[0, 2])
+    assert _ws(lib, big)[0] == _lib.RCP_ERR_INVALID_ARG
+    assert _ws(lib, _lib.make_problem((40, 64, 20), 5, 5, 1, 10, 0.0, 1, modes=[0, 2]))[0] == \
+        _lib.RCP_OK
+    # per-mode oversampling: k + p_n <= 64 and l_n >= k
+    assert _ws(lib, _lib.make_problem((40, 30, 20), 5, 5, 1, 10, 0.0, 1,
+                                      p_modes=[60, 1, 1]))[0] == _lib.RCP_ERR_INVALID_ARG
+    assert _ws(lib, _lib.make_problem((40, 30, 20), 5, 5, 1, 10, 0.0, 1,
+                                      p_modes=[1, -1, 1]))[0] == _lib.RCP_ERR_INVALID_ARG
+    # column selection needs l_n <= J_n at every step of the sequential scheme
+    assert _ws(lib, _lib.make_problem((40, 3, 3), 2, 8, 1, 10, 0.0, 1,
+                                      test_matrix="columns"))[0] == _lib.RCP_ERR_INVALID_ARG
+    assert _ws(lib, _lib.make_problem((40, 30, 20), 5, 5, 1, 10, 0.0, 1,
+                                      test_matrix="columns"))[0] == _lib.RCP_OK
+
+
 def test_init_checks_before_touching_the_gpu(lib):
     prob = _lib.make_problem((40, 30, 20), 5, 5, 1, 10, 0.0, 1)
     h = ctypes.c_void_p(0)
@@ -141,6 +170,7 @@ def test_null_plan_rejected_everywhere(lib):
     assert lib.rcp_decompose(None, None, None, None, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_norm2(None, None, 0, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_debug_omega(None, 0, 0, 1, 4, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_debug_columns(None, 0, 10, 4, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_get_bases(None, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_get_core(None, None, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_destroy(None) == _lib.RCP_ERR_INVALID_ARG

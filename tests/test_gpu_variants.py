@@ -1,0 +1,169 @@
+"""Algorithm 1 variants on the GPU against the float64 oracle on the same
+inputs: the uniform and Halton test matrices (step 5; the note in Section 3.1
+and the remark after Algorithm 1), column selection in place of the product
+(the same remark), a subset of compressed modes and per-mode oversampling.
+
+Tolerances: the generated entries are exact in float32 (uniform: bit-exact;
+Halton: the float32 rounding of the exact ratio, one ulp); the column indices
+are integers (bit-exact); bases within 2e-4 entrywise as for the Gaussian
+sketch (after a full decomposition within 5e-4 + 1e-5 cond(Y)); end to end
+|rel_err_gpu - rel_err_oracle| <= 1e-4 and congruence >= 0.999, as for the
+default path.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1703_09074_amd as rcpgpu  # noqa: E402
+from oracle import evaluate, philox, rcp  # noqa: E402
+from paper_1703_09074_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def _np(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _rand(shape, seed):
+    return np.random.default_rng(seed).standard_normal(shape).astype(np.float32)
+
+
+def test_uniform_omega_bit_exact():
+    seed = (77 << 32) | 5
+    plan = rcpgpu.Plan((64, 64, 64), 5, 5, 0, 1, 0.0, seed, test_matrix="uniform")
+    for mode, row0, nrows, l in [(0, 0, 3000, 30), (2, 4321, 500, 13), (1, (1 << 32) + 7, 200, 64)]:
+        got = _np(plan.omega(mode, row0, nrows, l))
+        want = philox.omega_uniform(seed, mode, 0, row0, nrows, l)
+        np.testing.assert_array_equal(got, want)
+        assert got.min() > 0.0 and got.max() <= 1.0
+
+
+def test_halton_omega_matches_oracle():
+    plan = rcpgpu.Plan((64, 64, 64), 5, 5, 0, 1, 0.0, 3, test_matrix="halton")
+    for mode, row0, nrows, l in [(0, 0, 2000, 30), (1, 99991, 300, 64), (2, (1 << 33) + 1, 50, 17)]:
+        got = _np(plan.omega(mode, row0, nrows, l))
+        want = philox.omega_halton(row0, nrows, l)
+        np.testing.assert_array_equal(got, want.astype(np.float32).astype(np.float64))
+
+
+def test_columns_omega_is_rejected():
+    plan = rcpgpu.Plan((64, 64, 64), 5, 5, 0, 1, 0.0, 3, test_matrix="columns")
+    with pytest.raises(rcpgpu._lib.RcpError):
+        plan.omega(0, 0, 10, 10)
+
+
+@pytest.mark.parametrize("mode,J,l", [(0, 100, 10), (1, 64, 64), (2, 3000, 64), (0, 1 << 40, 37),
+                                      (3, 12, 1)])
+def test_selected_columns_bit_exact(mode, J, l):
+    seed = (0xABCDEF << 32) | 99
+    plan = rcpgpu.Plan((16, 16, 16, 16), 1, 0, 0, 1, 0.0, seed, test_matrix="columns")
+    got = plan.columns(mode, J, l).cpu().numpy()
+    want = philox.select_columns(seed, mode, 0, J, l)
+    np.testing.assert_array_equal(got, want)
+    assert np.all(np.diff(got) > 0) and got[0] >= 0 and got[-1] < J
+
+
+SKETCH_CASES = [
+    # shape, mode, k, p, q, kind
+    ((37, 50, 41), 0, 5, 5, 0, "uniform"),
+    ((37, 50, 41), 1, 5, 5, 1, "uniform"),
+    ((37, 50, 41), 2, 5, 5, 2, "halton"),
+    ((64, 48, 5), 1, 4, 6, 1, "halton"),
+    ((37, 50, 41), 0, 5, 5, 0, "columns"),
+    ((37, 50, 41), 1, 5, 5, 2, "columns"),
+    ((30, 11, 3, 7), 3, 3, 4, 1, "columns"),
+    ((700, 9, 40), 0, 8, 8, 1, "uniform"),
+]
+
+
+@pytest.mark.parametrize("shape,mode,k,p,q,kind", SKETCH_CASES)
+def test_variant_sketch_matches_oracle(shape, mode, k, p, q, kind):
+    T = _rand(shape, sum(shape) + mode)
+    seed = 41 + mode
+    plan = rcpgpu.Plan(shape, k, p, q, 1, 0.0, seed, test_matrix=kind)
+    Q = _np(plan.sketch(_dev(T), mode))
+    l = rcp.sketch_width(k, p, shape[mode])
+    want = rcp.range_finder(T.astype(np.float64), mode, l, q, seed, test=kind).Q
+    assert Q.shape == want.shape
+    np.testing.assert_allclose(Q.T @ Q, np.eye(l), atol=2e-6)
+    err = np.max(np.abs(Q - want))
+    print(f"[variant] sketch {shape} mode {mode} {kind} q={q}: max|dQ| {err:.2e}", flush=True)
+    assert err <= 2e-4, err
+
+
+DECOMPOSE_CASES = [
+    # dims, R, noise, p, q, scheme, kind, modes, p_modes
+    ((60, 50, 40), 4, 0.05, 6, 1, "sequential", "uniform", None, None),
+    ((60, 50, 40), 4, 0.05, 6, 2, "sequential", "halton", None, None),
+    ((60, 50, 40), 4, 0.05, 6, 1, "sequential", "columns", None, None),
+    ((80, 30, 70), 5, 0.05, 8, 2, "sequential", "gaussian", [0, 2], None),
+    ((80, 30, 70), 5, 0.05, 8, 1, "independent", "gaussian", [0, 2], None),
+    ((70, 60, 50), 5, 0.05, 0, 2, "sequential", "gaussian", None, [4, 8, 12]),
+    ((24, 20, 22, 18), 3, 0.05, 5, 1, "sequential", "gaussian", [1, 3], [0, 2, 0, 7]),
+    ((24, 20, 22, 18), 3, 0.05, 5, 1, "independent", "columns", [0, 1, 2], None),
+]
+
+
+@pytest.mark.parametrize("dims,R,noise,p,q,scheme,kind,modes,p_modes", DECOMPOSE_CASES)
+def test_variant_decompose_matches_oracle(dims, R, noise, p, q, scheme, kind, modes, p_modes):
+    w = synth.low_rank(dims, R, noise, 61 + sum(dims))
+    iters, seed = 25, 13
+    plan = rcpgpu.Plan(dims, R, p, q, iters, 0.0, seed, scheme=scheme, test_matrix=kind,
+                       modes=modes, p_modes=p_modes)
+    lam, A, info = plan.decompose(_dev(w.X))
+    info = rcpgpu.Plan.read_info(info)
+    lam = _np(lam)
+    A = [_np(a) for a in A]
+    ref = rcp.rcp_als(w.X.astype(np.float64), R, p, q, iters, 0.0, seed, scheme=scheme, test=kind,
+                      modes=modes, p_modes=p_modes)
+    e_gpu = evaluate.relative_error(w.X, lam, A)
+    e_ref = evaluate.relative_error(w.X, ref.lam, ref.factors)
+    cong = evaluate.congruence(A, ref.factors)[0]
+    print(f"[variant] decompose {dims} {scheme} {kind} modes={modes} p={p_modes}: rel_err gpu "
+          f"{e_gpu:.7f} oracle {e_ref:.7f} congruence {cong:.6f}", flush=True)
+    assert info["status"] == 0, info
+    assert abs(e_gpu - e_ref) <= 1e-4, (e_gpu, e_ref)
+    assert cong >= 0.999, cong
+    # the core has the oracle's shape; a mode left out keeps Q_n = I
+    core = plan.core()
+    assert list(core.shape) == list(ref.compression.core.shape)
+    Qs = plan.bases()
+    for n in range(len(dims)):
+        if modes is not None and n not in modes:
+            np.testing.assert_array_equal(_np(Qs[n]), np.eye(dims[n]))
+        else:
+            # Q_n = Y R^-1 moves by about cond(Y) times the relative change of
+            # the tensor it is sketched from (float32 rounding of the
+            # compressed tensor in the sequential scheme)
+            kappa = np.linalg.cond(ref.compression.stages[n].y_final)
+            err = np.max(np.abs(_np(Qs[n]) - ref.compression.Q[n]))
+            assert err <= 5e-4 + 1e-5 * kappa, (n, err, kappa)
+
+
+def test_variant_batch_matches_single_plans():
+    """A batch mixing the variants gives the results of one plan per problem."""
+    probs = [
+        dict(dims=(40, 36, 30), k=4, p=6, q=1, max_iters=15, seed=2, test_matrix="halton"),
+        dict(dims=(50, 20, 44), k=3, p=5, q=1, max_iters=15, seed=3, modes=[0, 2]),
+        dict(dims=(30, 30, 30), k=5, p=0, q=2, max_iters=15, seed=4, p_modes=[5, 10, 3],
+             test_matrix="columns"),
+    ]
+    Xs = [synth.low_rank(pr["dims"], pr["k"], 0.05, 90 + i).X for i, pr in enumerate(probs)]
+    b = rcpgpu.Batch(probs)
+    b.decompose([_dev(x) for x in Xs])
+    infos = b.read_info()
+    for i, pr in enumerate(probs):
+        plan = rcpgpu.Plan(pr["dims"], pr["k"], pr["p"], pr["q"], pr["max_iters"], 0.0, pr["seed"],
+                           test_matrix=pr.get("test_matrix", "gaussian"), modes=pr.get("modes"),
+                           p_modes=pr.get("p_modes"))
+        lam, A, info = plan.decompose(_dev(Xs[i]))
+        info = rcpgpu.Plan.read_info(info)
+        assert abs(infos[i]["rho"] - info["rho"]) <= 1e-9, (i, infos[i], info)
+        np.testing.assert_allclose(_np(b.lam[i]), _np(lam), rtol=1e-6)
