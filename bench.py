@@ -74,6 +74,8 @@ def parse():
                     help="timed solves with bfloat16 and float16 operands (0 skips the comparison)")
     ap.add_argument("--mixed-large-steps", type=int, default=2,
                     help="timed solves per precision of the large mixed-precision workloads (0 skips)")
+    ap.add_argument("--det-steps", type=int, default=2,
+                    help="timed runs of deterministic CP-ALS on the secondary workload (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU oracle sample budget (0 disables the cpu_baseline leg)")
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "traffic.json"),
@@ -451,6 +453,8 @@ def main():
             sec["rel_err_minus_oracle"] = sec["rel_err"] - s_oracle
         if args.concurrent > 1:
             sec["concurrent_streams"] = concurrent(args, torch, rcpgpu, dev, sname, X2, sec)
+        if args.det_steps > 0:
+            sec["deterministic_cp_als"] = deterministic(args, torch, rcpgpu, dev, sname, X2, sec)
         if args.mixed_steps > 0:
             sm = {}
             for prec in ("bf16", "fp16"):
@@ -500,6 +504,43 @@ def main():
         out["oracle_rel_err"] = oracle_err
         out["rel_err_minus_oracle"] = head["rel_err"] - oracle_err
     print(json.dumps(out), flush=True)
+
+
+def deterministic(args, torch, rcpgpu, dev, name, X, base):
+    """Deterministic CP-ALS on the full tensor (the method the paper measures
+    the randomized one against) on the same input and sweep count: its time,
+    error and the randomized method's speed-up over it; the full-tensor mode
+    product's HBM rate from the plan's per-kernel event timing."""
+    from paper_1703_09074_amd import synth
+    cfg = dict(synth.WORKLOADS[name])
+    dims = list(cfg["dims"])
+    plan = rcpgpu.Plan(dims, cfg["k"], cfg["p"], 4, cfg["iters"], 0.0, cfg["seed"], device=dev,
+                       solver="cp_als")
+    A = [torch.empty((d, cfg["k"]), dtype=torch.float32, device=dev) for d in dims]
+    lam = torch.empty((cfg["k"],), dtype=torch.float32, device=dev)
+    info = plan._info_buffer()
+    plan.decompose_into(X, A, lam, info)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.det_steps):
+        plan.decompose_into(X, A, lam, info)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.det_steps
+    rel = rcpgpu.Plan.read_info(info)["rel_err"]
+    plan.profile(True)
+    plan.decompose_into(X, A, lam, info)
+    prof = plan.profile_read()
+    plan.profile(False)
+    mt = prof.get("mttkrp", {})
+    out = {"ms_per_solve": ms, "rel_err": rel, "rel_err_minus_rcp": rel - base["rel_err"],
+           "rcp_speedup": ms / base["ms_per_step"], "sweeps": cfg["iters"],
+           "start": "eigenvectors by subspace iteration, q=4",
+           "kernels_ms": {k: v["ms"] for k, v in prof.items()}}
+    if mt.get("ms"):
+        gbs = mt["bytes"] / (mt["ms"] * 1e-3) / 1e9
+        out["mttkrp_full"] = {"launches": mt["launches"], "ms": mt["ms"], "GB_per_s": gbs,
+                              "frac_hbm": gbs / PEAK_HBM_GBS}
+    return out
 
 
 def concurrent(args, torch, rcpgpu, dev, name, X, base):

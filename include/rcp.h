@@ -86,8 +86,10 @@ enum { RCP_TEST_GAUSSIAN = 0, RCP_TEST_UNIFORM = 1, RCP_TEST_HALTON = 2, RCP_TES
 /* rcp_problem.solver: the CP solver rcp_decompose runs on the core.  ALS is
  * Section 3.2.1 / Algorithm 2 (rcp_als); BCD is the rank-one block coordinate
  * descent of Section 3.2.2 / Algorithm 3 (rcp_bcd), whose max_iters and tol
- * apply to each component. */
-enum { RCP_SOLVER_ALS = 0, RCP_SOLVER_BCD = 1 };
+ * apply to each component.  CP_ALS is the deterministic method the
+ * randomized one is measured against (Section 3.3): Algorithm 2 on X itself,
+ * no compression (rcp_cp_als); its plan sizes the workspace for that. */
+enum { RCP_SOLVER_ALS = 0, RCP_SOLVER_BCD = 1, RCP_SOLVER_CP_ALS = 2 };
 
 /* Device-side status bits: rcp_als_info.status holds those of one CP-ALS
  * run (the first three); the plan's status word (rcp_read_status) collects
@@ -221,6 +223,27 @@ rcp_status rcp_bcd(rcp_plan plan, const float* core, float* const* At,
                    float* lambda, const double* normX2, rcp_als_info* info,
                    int32_t use_given_init);
 
+/* Deterministic CP-ALS on the full tensor X (Section 3.3: Algorithm 2 with
+ * Q_n = I, the Tensor Toolbox's scheme the paper follows), for a plan whose
+ * solver is RCP_SOLVER_CP_ALS (else RCP_ERR_INVALID_ARG).  X: the plan's
+ * dims, C-order float32; outputs A[n] (I_n x R), lambda (R) and info as for
+ * rcp_decompose (ordered by lambda, signs fixed, fit exact on X).
+ * Start (A_init == NULL): for modes 1..N-1 the leading R eigenvectors of
+ * X_(n) X_(n)^T (Algorithm 2 step 2), computed by subspace iteration: the
+ * plan's q power steps of Algorithm 1 on an l_n = min(k + p, I_n) wide block
+ * (the plan's test matrix and seed), then the eigenvectors of the l_n x l_n
+ * Gram Q^T X_(n) X_(n)^T Q (Rayleigh-Ritz); equal to the exact ones up to
+ * (sigma_{l_n + 1} / sigma_R)^(2q + 1), so q sets the accuracy.  Each column
+ * is unit and signed as the oracle's eigenvectors (largest-magnitude entry
+ * positive).  With A_init (host array of N device pointers, I_n x R float32;
+ * A_init[0] is not read) the sweeps start from the caller's factors.
+ * Sweeps: per mode the product X_(n) KR(A_{m != n}) streams X once over the
+ * whole GPU, then one solve with V = *_{m != n} A_m^T A_m (pseudo-inverse
+ * fallback as rcp_als), unit columns, lambda from the last mode; stops after
+ * max_iters sweeps or, with tol > 0, when the fit changes by less than tol. */
+rcp_status rcp_cp_als(rcp_plan plan, const float* X, const float* const* A_init,
+                      float* const* A, float* lambda, rcp_als_info* info);
+
 /* Back-projection A_n = Q_n Ã_n (eq. qbs, Algorithm 2 step 12) and the
  * renormalisation of step 13: unit columns, norms folded into lambda,
  * components sorted by lambda (descending), the largest-magnitude entry of
@@ -233,7 +256,10 @@ rcp_status rcp_expand(rcp_plan plan, const float* const* Q, const float* const* 
 /* The whole path on X (dims = the plan's dims): ||X||^2, the compression of
  * Algorithm 1 (scheme from the plan), CP-ALS on the core and the
  * back-projection.  Outputs A[n] (I_n x R), lambda (R) and info (device).
- * The bases and the core stay in the workspace (rcp_get_bases / rcp_get_core). */
+ * The bases and the core stay in the workspace (rcp_get_bases / rcp_get_core).
+ * A plan with solver RCP_SOLVER_CP_ALS runs rcp_cp_als(plan, X, NULL, ...)
+ * instead (no bases or core: rcp_get_bases / rcp_get_core then return
+ * RCP_ERR_UNSUPPORTED). */
 rcp_status rcp_decompose(rcp_plan plan, const float* X, float* const* A,
                          float* lambda, rcp_als_info* info);
 
@@ -306,7 +332,9 @@ enum {
     RCP_KERNEL_EXPAND = 7,       /* back-projection and renormalisation */
     RCP_KERNEL_OTHER = 8,
     RCP_KERNEL_BCD = 9,          /* block coordinate descent on the core */
-    RCP_KERNEL_COUNT = 10
+    RCP_KERNEL_MTTKRP = 10,      /* X_(n) KR(A_{m != n}) over the full tensor (rcp_cp_als) */
+    RCP_KERNEL_CP_UPDATE = 11,   /* rcp_cp_als: solve, norms, Grams, fit of one mode */
+    RCP_KERNEL_COUNT = 12
 };
 rcp_status rcp_profile(rcp_plan plan, int32_t enable);
 rcp_status rcp_profile_read(rcp_plan plan, int32_t kernel_class, int64_t* launches, double* ms,

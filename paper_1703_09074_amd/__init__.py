@@ -183,6 +183,34 @@ class Plan:
         (factors, lambda, info buffer); arguments as ``als``."""
         return self._core_solver(self.lib.rcp_bcd, "rcp_bcd", core, normX2, init)
 
+    def cp_als(self, X, init: Optional[List] = None):
+        """Deterministic CP-ALS on the full tensor X (rcp_cp_als; the plan's
+        solver must be "cp_als"): (lambda, [A_n], info buffer).  init: N
+        float32 CUDA tensors (I_n x R; init[0] is not read) to start from,
+        else the eigenvector start by subspace iteration."""
+        _f32(X, "X")
+        if list(X.shape) != self.dims:
+            raise ValueError(f"X has shape {list(X.shape)}, plan expects {self.dims}")
+        init_arg = None
+        if init is not None:
+            if len(init) != self.N:
+                raise ValueError(f"init needs {self.N} factors")
+            for n in range(1, self.N):
+                _f32(init[n], f"init[{n}]")
+                if list(init[n].shape) != [self.dims[n], self.R]:
+                    raise ValueError(f"init[{n}] has shape {list(init[n].shape)}, "
+                                     f"expected {[self.dims[n], self.R]}")
+            init_arg = _lib.ptr_array([init[0].data_ptr() if init[0] is not None else 0] +
+                                      [t.data_ptr() for t in init[1:]])
+        A = [self._empty((self.dims[n], self.R)) for n in range(self.N)]
+        lam = self._empty((self.R,))
+        info = self._info_buffer()
+        _lib.check(self.lib.rcp_cp_als(self.handle, ctypes.c_void_p(X.data_ptr()), init_arg,
+                                       _lib.ptr_array([a.data_ptr() for a in A]),
+                                       ctypes.c_void_p(lam.data_ptr()),
+                                       ctypes.c_void_p(info.data_ptr())), "rcp_cp_als")
+        return lam, A, info
+
     def read_status(self) -> int:
         """The plan's device status word (RCP_INFO_* bits raised since the last
         read), cleared by the read; waits for the plan's stream."""

@@ -30,9 +30,9 @@ RCP_INFO_QR_HOUSEHOLDER = 8
 
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
 KERNEL_CLASSES = ["sketch", "power", "contract_in", "contract_out", "reduce", "qr", "als",
-                  "expand", "other", "bcd"]
+                  "expand", "other", "bcd", "mttkrp", "cp_update"]
 SCHEMES = {"sequential": 0, "independent": 1}
-SOLVERS = {"als": 0, "bcd": 1}
+SOLVERS = {"als": 0, "bcd": 1, "cp_als": 2}
 TEST_MATRICES = {"gaussian": 0, "uniform": 1, "halton": 2, "columns": 3}
 
 
@@ -83,6 +83,7 @@ SIGNATURES = {
     "rcp_bcd": (_st, [_vp, _vp, ctypes.POINTER(_vp), _vp, _vp, _vp, ctypes.c_int32]),
     "rcp_expand": (_st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, ctypes.POINTER(_vp), _vp]),
     "rcp_decompose": (_st, [_vp, _vp, ctypes.POINTER(_vp), _vp, _vp]),
+    "rcp_cp_als": (_st, [_vp, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _vp]),
     "rcp_decompose_noalloc": (_st, [ctypes.POINTER(Problem), _vp, ctypes.POINTER(_vp), _vp, _vp, _vp]),
     "rcp_get_bases": (_st, [_vp, ctypes.POINTER(_vp)]),
     "rcp_get_core": (_st, [_vp, ctypes.POINTER(_vp), _i64p]),

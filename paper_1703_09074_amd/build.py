@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librcp.so")
 
 SOURCES = ["stream_kernels.hip", "stream_kernels_lp.hip", "qr_kernel.hip", "als_kernel.hip",
-           "bcd_kernel.hip", "expand_kernel.hip", "rcp_api.cpp"]
+           "bcd_kernel.hip", "cpals_kernel.hip", "expand_kernel.hip", "rcp_api.cpp"]
 
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -240,240 +240,6 @@ __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, c
     }
 }
 
-// Inverse of the pivot block P = A[0..pbs) x [0..pbs) (row stride lda; a
-// 16 x 16 block padded with the identity past pbs) in one wavefront's
-// registers: Gauss-Jordan on [P | I] with lane c holding column c (lanes
-// 0..15 P, 16..31 I) and the rows rotating through the registers so that the
-// pivot row is always register 0; the pivot column is read into scalar
-// registers before each step's updates.  P^{-1} goes to Pinv (16 x 16).
-// Returns 0 if a pivot of the first rreal rows is not above thr (or is NaN).
-__device__ __forceinline__ int invert16_wave(const double* A, int lda, int pbs, int rreal, double thr,
-                                             double* Pinv) {
-    const int c = threadIdx.x & 63;
-    double col[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        double v = 0.0;
-        if (c < 16) v = (i < pbs && c < pbs) ? A[i * lda + c] : ((i == c) ? 1.0 : 0.0);
-        else if (c < 32) v = (c - 16 == i) ? 1.0 : 0.0;
-        col[i] = v;
-    }
-    double pmin = __builtin_huge_val();
-    bool pnan = false;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        double sk[16];
-        sk[0] = readlane_f64(col[0], k);
-        const double u = col[0] / sk[0];
-#pragma unroll
-        for (int i = 1; i < 16; ++i) sk[i] = readlane_f64(col[i], k);
-        __builtin_amdgcn_sched_barrier(0);
-        if (k < rreal) {
-            pmin = fmin(pmin, sk[0]);
-            pnan = pnan || (sk[0] != sk[0]);
-        }
-#pragma unroll
-        for (int i = 1; i < 16; ++i) col[i] -= sk[i] * u;
-#pragma unroll
-        for (int i = 0; i < 15; ++i) col[i] = col[i + 1];
-        col[15] = u;
-    }
-    if (c >= 16 && c < 32) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) Pinv[i * 16 + (c - 16)] = col[i];
-    }
-    return (!pnan && (rreal == 0 || pmin > thr)) ? 1 : 0;
-}
-
-// Blocked Gauss-Jordan elimination without pivoting on the augmented system
-// Aug = [V | Xt] (Rp x W, row stride ldx, V symmetric positive definite and
-// padded with the identity up to Rp): on return columns Rp..W-1 hold
-// V^{-1} Xt.  Pivot blocks of up to 16 rows; per block j0 (pbs rows):
-//   1. wavefront 0 inverts the pivot block P in its registers;
-//   2. the pivot rows become P^{-1} [pivot rows] (float64 matrix cores);
-//   3. every other row block i loses F_i [pivot rows], F_i its entries in the
-//      pivot columns (matrix cores).
-// The pivots of the inverted blocks are the Schur complements, i.e. the
-// pivots of unblocked elimination, and each must exceed rtol times the
-// largest of V's first R diagonal entries for the rows < R.  Columns left of the pivot block are never read again and are not
-// updated; every column block is read whole before it is written, so the
-// updates run in place.  pb holds 258 doubles (P^{-1} and the flag).
-__device__ __forceinline__ int block16_gj(double* Aug, int ldx, int R, int Rp, int W, double rtol,
-                                          double* pb) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int li = lane & 15, lk = lane >> 4;
-    double* Pinv = pb;
-    double* okp = pb + 256;
-    if (threadIdx.x == 0) *okp = 1.0;
-    // the pivot threshold, needed by wavefront 0 only (R <= 64 = one lane per row)
-    double thr = 0.0;
-    if (wave == 0) {
-        double d = (lane < R) ? Aug[lane * ldx + lane] : 0.0;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) d = fmax(d, __shfl_xor(d, o, 64));
-        thr = rtol * d;
-    }
-    const int nrb = (Rp + 15) >> 4;
-    for (int j0 = 0; j0 < Rp; j0 += 16) {
-        const int pbs = min(16, Rp - j0);
-        const int rreal = max(0, min(pbs, R - j0));
-        if (wave == 0) {
-            const int ok = invert16_wave(Aug + j0 * ldx + j0, ldx, pbs, rreal, thr, Pinv);
-            if (lane == 0 && !ok) *okp = 0.0;
-        }
-        __syncthreads();
-        const int c0 = j0 + pbs;                   // first column to update
-        const int ncb = (W - c0 + 15) >> 4;
-        // 2. pivot rows <- P^{-1} pivot rows
-        for (int cb = wave; cb < ncb; cb += ANW) {
-            const int cc = c0 + cb * 16 + li;
-            const bool cv = cc < W;
-            double bop[4], aop[4];
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int sr = 4 * kk + lk;
-                bop[kk] = (sr < pbs && cv) ? Aug[(j0 + sr) * ldx + cc] : 0.0;
-                aop[kk] = Pinv[li * 16 + sr];
-            }
-            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) acc = mfma64(aop[kk], bop[kk], acc);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int t = lk + 4 * v;
-                if (t < pbs && cv) Aug[(j0 + t) * ldx + cc] = acc[v];
-            }
-        }
-        __syncthreads();
-        // 3. other row blocks: A_ic -= F_i [pivot rows]
-        const int units = (nrb - 1) * ncb;
-        for (int u = wave; u < units; u += ANW) {
-            int rb = u / ncb;
-            const int cb = u - rb * ncb;
-            if (rb >= (j0 >> 4)) ++rb;            // skip the pivot block
-            const int i0 = rb * 16;
-            const int cc = c0 + cb * 16 + li;
-            const bool cv = cc < W;
-            double aop[4], bop[4];
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int sr = 4 * kk + lk;
-                const int ri = i0 + li;
-                aop[kk] = (sr < pbs && ri < Rp) ? -Aug[ri * ldx + j0 + sr] : 0.0;
-                bop[kk] = (sr < pbs && cv) ? Aug[(j0 + sr) * ldx + cc] : 0.0;
-            }
-            f64x4 acc;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int ri = i0 + lk + 4 * v;
-                acc[v] = (ri < Rp && cv) ? Aug[ri * ldx + cc] : 0.0;
-            }
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) acc = mfma64(aop[kk], bop[kk], acc);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int ri = i0 + lk + 4 * v;
-                if (ri < Rp && cv) Aug[ri * ldx + cc] = acc[v];
-            }
-        }
-        __syncthreads();
-    }
-    return *okp != 0.0;
-}
-
-
-// Row stride (doubles) of the augmented system [V | Xt]: odd, so that the 16
-// rows one matrix-core operand reads at a time fall in distinct LDS banks.
-__host__ __device__ inline int aug_ld(int Rp, int lmax) { return (Rp + lmax) | 1; }
-
-// doubles of LDS the solvers need beside the augmented system (the blocked
-// one's pivot-block inverse and flag; the one-wavefront one's flag)
-__host__ __device__ inline int gj_buf_doubles(int ldx, int Rp) {
-    (void)ldx;
-    (void)Rp;
-    return 258;
-}
-
-// One-wavefront variant for small systems (Rp <= 32 rows, W <= 64 columns):
-// lane c holds column c in registers and the rows rotate through them so
-// that the pivot row is always register 0 (static indexing): at step k the
-// pivot column comes from lane k by readlane, the pivot row is scaled, the
-// other rows lose their multiples of it and the finished pivot row moves to
-// the back; after Rp steps the rows are in order again (the steps are
-// unrolled, so the rotation is register renaming).  No barriers.
-template <int RP>
-__device__ __forceinline__ int gj_wave(double* Aug, int ldx, int R, int W, double rtol) {
-    const int c = threadIdx.x & 63;
-    const bool cv = c < W;
-    double col[RP];
-#pragma unroll
-    for (int i = 0; i < RP; ++i) col[i] = cv ? Aug[i * ldx + c] : 0.0;
-    const double dg = (c < RP) ? Aug[c * ldx + c] : 0.0;     // V_cc (V itself is not written)
-    // The pivot test does not steer the elimination, so it is taken once at
-    // the end: every pivot of the first R rows must exceed
-    // rtol * max_{r < R} V_rr, i.e. none is NaN and the smallest does.
-    double pmin = __builtin_huge_val();
-    bool pnan = false;
-#pragma unroll
-    for (int k = 0; k < RP; ++k) {
-        // the whole pivot column is read before the first update: readlanes
-        // into distinct scalar registers issue back to back, where one
-        // broadcast per update serialises on a single register pair
-        double s[RP];
-        s[0] = readlane_f64(col[0], k);
-        const double u = col[0] / s[0];
-#pragma unroll
-        for (int i = 1; i < RP; ++i) s[i] = readlane_f64(col[i], k);
-        __builtin_amdgcn_sched_barrier(0);
-        if (k < R) {
-            pmin = fmin(pmin, s[0]);
-            pnan = pnan || (s[0] != s[0]);
-        }
-#pragma unroll
-        for (int i = 1; i < RP; ++i) col[i] -= s[i] * u;
-#pragma unroll
-        for (int i = 0; i < RP - 1; ++i) col[i] = col[i + 1];
-        col[RP - 1] = u;
-    }
-    if (cv && c >= RP) {
-#pragma unroll
-        for (int i = 0; i < RP; ++i) Aug[i * ldx + c] = col[i];
-    }
-    double dmax = 0.0;
-#pragma unroll
-    for (int k = 0; k < RP; ++k) {
-        const double v = readlane_f64(dg, k);
-        if (k < R) dmax = fmax(dmax, v);
-    }
-    return (!pnan && pmin > rtol * dmax) ? 1 : 0;
-}
-
-// V^{-1} Xt in place for Rp (a multiple of 4) rows and W columns; every
-// thread returns the ok flag (0 when a pivot of the first R rows is not above
-// rtol * max_{r < R} V_rr).
-__device__ __forceinline__ int gj_solve(double* Aug, int ldx, int R, int Rp, int W, double rtol,
-                                        double* fbuf) {
-    if (Rp <= 32 && W <= 64) {
-        if ((threadIdx.x >> 6) == 0) {
-            int ok = 0;
-            switch (Rp) {
-                case 4: ok = gj_wave<4>(Aug, ldx, R, W, rtol); break;
-                case 8: ok = gj_wave<8>(Aug, ldx, R, W, rtol); break;
-                case 12: ok = gj_wave<12>(Aug, ldx, R, W, rtol); break;
-                case 16: ok = gj_wave<16>(Aug, ldx, R, W, rtol); break;
-                case 20: ok = gj_wave<20>(Aug, ldx, R, W, rtol); break;
-                case 24: ok = gj_wave<24>(Aug, ldx, R, W, rtol); break;
-                case 28: ok = gj_wave<28>(Aug, ldx, R, W, rtol); break;
-                default: ok = gj_wave<32>(Aug, ldx, R, W, rtol); break;
-            }
-            if (threadIdx.x == 0) fbuf[0] = ok ? 1.0 : 0.0;
-        }
-        __syncthreads();
-        return fbuf[0] != 0.0;
-    }
-    return block16_gj(Aug, ldx, R, Rp, W, rtol, fbuf);
-}
-
 // Left block of the augmented system: V = *_{m != n} G_m, identity padding up
 // to Rp, and zero padding rows in the right block.
 __device__ __forceinline__ void hadamard_grams(const AlsCtx& c, int n, const double* G, double* Aug,

@@ -138,6 +138,11 @@ hipError_t launch_expand(const ExpandArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_expand_finish(const ExpandArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_expand_finish, dim3(1), dim3(ENT), 0, s, a, (const double*)a.raw);
+    return hipGetLastError();
+}
+
 hipError_t launch_expand_batch(const ExpandArgs* dargs, const ExpandArgs* hargs, int count,
                                hipStream_t s) {
     if (count < 1) return hipSuccess;

@@ -33,6 +33,9 @@ struct Layout {
     int LPmax;
     // offsets (bytes)
     int ncompressed;       // modes Algorithm 1 compresses (the others keep Q_n = I)
+    // deterministic CP-ALS (solver RCP_SOLVER_CP_ALS): float32 working
+    // factors, sweep state, the subspace-iteration tensor of the start
+    size_t cfac, cst, cpb;
     size_t part, red1, y64, qt, sq, norm, status, colidx, qb[RCP_MAX_NDIM], tb[2], zbuf, als, alsst,
         at[RCP_MAX_NDIM], lam, raw, egram, total;
     int egram_stride;      // doubles per mode of egram
@@ -61,7 +64,8 @@ bool valid_problem(const rcp_problem* p) {
     if (p->precision != RCP_PREC_FP32 && p->precision != RCP_PREC_BF16 &&
         p->precision != RCP_PREC_FP16)
         return false;
-    if (p->solver != RCP_SOLVER_ALS && p->solver != RCP_SOLVER_BCD) return false;
+    if (p->solver != RCP_SOLVER_ALS && p->solver != RCP_SOLVER_BCD && p->solver != RCP_SOLVER_CP_ALS)
+        return false;
     if (p->test_matrix < RCP_TEST_GAUSSIAN || p->test_matrix > RCP_TEST_COLUMNS) return false;
     if ((p->compress_mask >> p->ndim) != 0) return false;
     if (p->per_mode_p != 0 && p->per_mode_p != 1) return false;
@@ -167,11 +171,21 @@ Layout make_layout(const rcp_problem* p) {
     // the eigenvector start of a core larger than LDS: the Grams of modes
     // 1..N-1 side by side
     L.egram_stride = 0;
-    if (!als_core_in_lds(L.N, L.l, L.R)) {
+    if (!als_core_in_lds(L.N, L.l, L.R) || p->solver == RCP_SOLVER_CP_ALS) {
         int lmax = 0;
         for (int n = 0; n < L.N; ++n) lmax = std::max(lmax, L.l[n]);
         L.egram_stride = lmax * lp_of(lmax);
         L.egram = take((size_t)(L.N - 1) * L.egram_stride * sizeof(double));
+    }
+    L.cfac = L.cst = L.cpb = 0;
+    if (p->solver == RCP_SOLVER_CP_ALS) {
+        L.cfac = take(raw * sizeof(float));
+        L.cst = take(cp_state_doubles(L.N, L.R) * sizeof(double));
+        int64_t S = 1;
+        for (int n = 0; n < L.N; ++n) S *= L.dims[n];
+        size_t bmax = 0;
+        for (int n = 1; n < L.N; ++n) bmax = std::max(bmax, (size_t)(S / L.dims[n]) * L.l[n]);
+        L.cpb = take(bmax * sizeof(float));
     }
     L.total = off;
     return L;
@@ -846,10 +860,152 @@ ExpandArgs core_expand_args(rcp_plan_t* plan, float* const* A, float* lambda) {
 
 namespace {
 
+// Deterministic CP-ALS on X (Algorithm 2 with Q_n = I).  A_init: null (the
+// eigenvector start by subspace iteration) or N device pointers (modes 1..N-1
+// read).
+rcp_status cp_als_impl(rcp_plan_t* pl, const float* X, const float* const* A_init,
+                       float* const* A, float* lambda, rcp_als_info* info) {
+    const Layout& L = pl->L;
+    const int N = L.N, R = L.R;
+    double* st = pl->at<double>(L.cst);
+    double* raw = pl->at<double>(L.raw);
+    float* facs = pl->at<float>(L.cfac);
+    double* rawn[RCP_MAX_NDIM];
+    float* facn[RCP_MAX_NDIM];
+    int dims_i[RCP_MAX_NDIM];
+    int64_t S = 1;
+    {
+        int64_t off = 0;
+        for (int n = 0; n < N; ++n) {
+            rawn[n] = raw + off;
+            facn[n] = facs + off;
+            off += L.dims[n] * R;
+            dims_i[n] = (int)L.dims[n];
+            S *= L.dims[n];
+        }
+    }
+    for (int n = 0; n < N; ++n) {
+        const double Lm = (double)S / (double)L.dims[n];
+        int64_t Rr = 1;
+        for (int m = n + 1; m < N; ++m) Rr *= L.dims[m];
+        if (Lm / (double)Rr > 4294967295.0 || Rr > 4294967295LL) return RCP_ERR_UNSUPPORTED;
+    }
+    CpArgs c{};
+    c.N = N;
+    c.R = R;
+    c.max_iters = pl->prob.max_iters;
+    c.tol = pl->prob.tol;
+    c.state = st;
+    c.Y = pl->at<double>(L.y64);
+    c.ldy = lp_of(R);
+    c.lam_f = pl->at<float>(L.lam);
+    c.info = info;
+    c.status_word = pl->status_word();
+    c.E = pl->at<double>(L.als);
+    RCP_TRY(launch_fill_i32((int*)st, 0, 8, pl->stream));
+    {
+        const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kPmax, (S + 255) / 256));
+        RCP_TRY(launch_sumsq(X, S, pl->at<double>(L.sq), nb, st + 3, pl->stream));
+    }
+    if (A_init == nullptr) {
+        // Algorithm 2 step 2: the leading eigenvectors of X_(n) X_(n)^T by
+        // subspace iteration (Algorithm 1's power steps on an l_n-wide block)
+        // and Rayleigh-Ritz on the Gram of X x_n Q_n^T
+        double* eg = pl->at<double>(L.egram);
+        float* B = pl->at<float>(L.cpb);
+        float* part = pl->at<float>(L.part);
+        for (int n = 1; n < N; ++n) {
+            rcp_status r = sketch_impl(pl, X, L.dims, n, pl->at<float>(L.qb[n]), nullptr);
+            if (r != RCP_OK) return r;
+            r = compress_impl(pl, X, L.dims, n, B);
+            if (r != RCP_OK) return r;
+            int64_t cur[RCP_MAX_NDIM];
+            for (int m = 0; m < N; ++m) cur[m] = L.dims[m];
+            cur[n] = L.l[n];
+            const StreamGeom g = make_geom(B, cur, N, n);
+            const int P = (int)std::max<int64_t>(1, std::min<int64_t>(pl->P, g.ntiles));
+            const int LPn = lp_of(L.l[n]);
+            float* eye = pl->at<float>(L.qt);
+            RCP_TRY(launch_eye(eye, L.l[n], LPn, pl->stream));
+            RCP_TRY(launch_power_fused(g, L.l[n], eye, part, P, pl->stream, RCP_PREC_FP32));
+            RCP_TRY(launch_reduce_partials(part, P, (int64_t)L.l[n] * LPn, pl->at<double>(L.red1),
+                                           eg + (size_t)(n - 1) * L.egram_stride, nullptr, 0,
+                                           nullptr, pl->stream));
+        }
+        AlsArgs ai{};
+        ai.N = N;
+        ai.R = R;
+        for (int n = 0; n < N; ++n) {
+            ai.l[n] = L.l[n];
+            ai.At[n] = pl->at<float>(L.at[n]);
+        }
+        ai.state = st;
+        ai.Y = eg;
+        RCP_TRY(launch_als_wide_init(ai, L.egram_stride, pl->stream));
+        for (int n = 1; n < N; ++n)
+            RCP_TRY(launch_cp_start(pl->at<float>(L.qb[n]), ai.At[n], L.dims[n], L.l[n], R, rawn[n],
+                                    facn[n], pl->stream));
+    } else {
+        for (int n = 1; n < N; ++n)
+            RCP_TRY(launch_cp_load(A_init[n], L.dims[n] * R, rawn[n], facn[n], pl->stream));
+    }
+    for (int n = 1; n < N; ++n) {
+        CpArgs g = c;
+        g.n = n;
+        g.sweep = 0;
+        g.I = L.dims[n];
+        g.raw = rawn[n];
+        g.fac = facn[n];
+        RCP_TRY(launch_cp_gram(g, pl->stream));
+    }
+    const float* fac_c[RCP_MAX_NDIM];
+    for (int n = 0; n < N; ++n) fac_c[n] = facn[n];
+    float* part = pl->at<float>(L.part);
+    const int LPR = lp_of(R);
+    for (int it = 1; it <= pl->prob.max_iters; ++it) {
+        for (int n = 0; n < N; ++n) {
+            const StreamGeom g = make_geom(X, L.dims, N, n);
+            const int P = (int)std::max<int64_t>(1, std::min<int64_t>(pl->P, g.ntiles));
+            KrSpec kr = kr_spec(N, n, dims_i, R, fac_c, (const int*)st);
+            kr.sweep = it;
+            RCP_TRY(timed(pl, RCP_KERNEL_MTTKRP, 4.0 * (double)S, 2.0 * (double)S * R,
+                          [&] { return launch_mttkrp_full(g, kr, part, P, pl->stream); }));
+            RCP_TRY(timed(pl, RCP_KERNEL_REDUCE, (double)P * g.I * LPR * 4.0 + (double)g.I * LPR * 8.0,
+                          (double)P * g.I * LPR, [&] {
+                              return launch_reduce_partials(part, P, g.I * LPR, pl->at<double>(L.red1),
+                                                            pl->at<double>(L.y64), nullptr, 0, nullptr,
+                                                            pl->stream);
+                          }));
+            CpArgs u = c;
+            u.n = n;
+            u.sweep = it;
+            u.I = L.dims[n];
+            u.raw = rawn[n];
+            u.fac = facn[n];
+            RCP_TRY(timed(pl, RCP_KERNEL_CP_UPDATE, (double)g.I * LPR * 8.0 + (double)g.I * R * 12.0,
+                          2.0 * (double)g.I * R * R * 2.0, [&] { return launch_cp_update(u, pl->stream); }));
+        }
+    }
+    ExpandArgs e{};
+    e.N = N;
+    e.R = R;
+    for (int n = 0; n < N; ++n) {
+        e.I[n] = L.dims[n];
+        e.l[n] = (int)L.dims[n];
+        e.A[n] = A[n];
+    }
+    e.lambda_in = pl->at<float>(L.lam);
+    e.lambda_out = lambda;
+    e.raw = raw;
+    RCP_TRY(timed(pl, RCP_KERNEL_EXPAND, 0.0, 0.0, [&] { return launch_expand_finish(e, pl->stream); }));
+    return RCP_OK;
+}
+
 rcp_status decompose_impl(rcp_plan_t* plan, const float* X, float* const* A, float* lambda,
                           rcp_als_info* info) {
     const Layout& L = plan->L;
     const int N = L.N;
+    if (plan->prob.solver == RCP_SOLVER_CP_ALS) return cp_als_impl(plan, X, nullptr, A, lambda, info);
     const float* core = nullptr;
     rcp_status st = compress_all(plan, X, &core);
     if (st != RCP_OK) return st;
@@ -882,6 +1038,17 @@ rcp_status rcp_decompose(rcp_plan plan, const float* X, float* const* A, float* 
                          rcp_als_info* info) {
     if (plan == nullptr || !valid_outputs(plan->L.N, X, A, lambda, info)) return RCP_ERR_INVALID_ARG;
     return decompose_impl(plan, X, A, lambda, info);
+}
+
+rcp_status rcp_cp_als(rcp_plan plan, const float* X, const float* const* A_init, float* const* A,
+                      float* lambda, rcp_als_info* info) {
+    if (plan == nullptr || !valid_outputs(plan->L.N, X, A, lambda, info) ||
+        plan->prob.solver != RCP_SOLVER_CP_ALS)
+        return RCP_ERR_INVALID_ARG;
+    if (A_init != nullptr)
+        for (int n = 1; n < plan->L.N; ++n)
+            if (A_init[n] == nullptr || !aligned(A_init[n], 4)) return RCP_ERR_INVALID_ARG;
+    return cp_als_impl(plan, X, A_init, A, lambda, info);
 }
 
 }  // extern "C"
@@ -1274,12 +1441,14 @@ rcp_status rcp_batch_destroy(rcp_batch batch) {
 
 rcp_status rcp_get_bases(rcp_plan plan, float** Q) {
     if (plan == nullptr || Q == nullptr) return RCP_ERR_INVALID_ARG;
+    if (plan->prob.solver == RCP_SOLVER_CP_ALS) return RCP_ERR_UNSUPPORTED;
     for (int n = 0; n < plan->L.N; ++n) Q[n] = plan->at<float>(plan->L.qb[n]);
     return RCP_OK;
 }
 
 rcp_status rcp_get_core(rcp_plan plan, float** core, int64_t* core_dims) {
     if (plan == nullptr || core == nullptr) return RCP_ERR_INVALID_ARG;
+    if (plan->prob.solver == RCP_SOLVER_CP_ALS) return RCP_ERR_UNSUPPORTED;
     *core = core_location(plan);
     if (core_dims != nullptr)
         for (int n = 0; n < plan->L.N; ++n) core_dims[n] = plan->L.core_dims[n];

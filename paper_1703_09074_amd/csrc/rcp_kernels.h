@@ -60,11 +60,16 @@ struct KrSpec {
     uint32_t mul[RCP_MAX_NDIM];
     uint32_t shr[RCP_MAX_NDIM];
     const float* fac[RCP_MAX_NDIM];     // l_m x R, row-major (device)
-    const int* skip;                    // nonzero: the launch does nothing
+    const int* skip;                    // *skip != 0 and sweep > *skip: the launch does nothing
+    int sweep;                          // the sweep this launch belongs to (INT_MAX: any stop)
 };
 KrSpec kr_spec(int N, int n, const int* l, int R, const float* const* fac, const int* skip);
 // partial M = B_(n) KR (per workgroup, I x 16*ceil(R/16)) for the reduction
 hipError_t launch_mttkrp(const StreamGeom& g, const KrSpec& kr, float* part, int P, hipStream_t s);
+// the same for any mode size (row blocks of up to 512 rows, grid P x blocks),
+// the factors read from global memory: partials P x I x 16*ceil(R/16)
+hipError_t launch_mttkrp_full(const StreamGeom& g, const KrSpec& kr, float* part, int P,
+                              hipStream_t s);
 // p[0..n) <- v (a kernel, not a memset node, so that it can sit in a captured graph)
 hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
 // Qpad (I x ldq) <- the identity padded with zero columns
@@ -123,6 +128,36 @@ struct AlsArgs {
     double* state;
 };
 hipError_t launch_als(const AlsArgs& a, hipStream_t s);
+
+// Deterministic CP-ALS on the full tensor (cpals_kernel.hip): one mode's
+// update after its mode product M_n is in Y, or the Gram of a start.
+struct CpArgs {
+    int N, R, n, sweep;        // mode and sweep (1-based; 0 for the start) of the launch
+    int64_t I;                 // rows of mode n
+    int max_iters;
+    double tol;
+    double* state;             // sweep state (cp_state_doubles)
+    const double* Y;           // M_n, I x ldy float64
+    int ldy;
+    double* raw;               // I x R float64 factor of mode n
+    float* fac;                // I x R float32 copy (the mode products read it)
+    float* lam_f;              // R: lambda as float (for the final ordering)
+    rcp_als_info* info;
+    int* status_word;
+    double* E;                 // 2 x 64 x 64 Jacobi scratch (pseudo-inverse fallback)
+};
+size_t cp_state_doubles(int N, int R);
+int cp_row_blocks(int64_t I);
+// V^-1, raw = Y V^-1, norms, G_n (and for the last mode lambda, fit, stop), A_n
+hipError_t launch_cp_update(const CpArgs& a, hipStream_t s);
+// G_n of the start already in a.raw
+hipError_t launch_cp_gram(const CpArgs& a, hipStream_t s);
+// start of mode n from a subspace basis Q (I x l) and the Gram's leading
+// eigenvectors W (l x R): unit, sign-fixed columns of Q W into raw and fac
+hipError_t launch_cp_start(const float* Q, const float* W, int64_t I, int l, int R, double* raw,
+                           float* fac, hipStream_t s);
+// a caller's start (float32, cnt entries) into raw and fac
+hipError_t launch_cp_load(const float* A, int64_t cnt, double* raw, float* fac, hipStream_t s);
 // Block coordinate descent on the core (bcd_kernel.hip), one workgroup, the
 // same arguments (a.normX2 must be set; At[1..N-1] read when a.warm)
 bool bcd_supported(int N, const int* l, int R);
@@ -163,6 +198,9 @@ struct ExpandArgs {
     double* raw;               // scratch: sum_n I_n x R
 };
 hipError_t launch_expand(const ExpandArgs& a, hipStream_t s);
+// the final step alone on factors already in a.raw (Q_n = I): renormalise,
+// order by lambda, signs
+hipError_t launch_expand_finish(const ExpandArgs& a, hipStream_t s);
 hipError_t launch_expand_batch(const ExpandArgs* dargs, const ExpandArgs* hargs, int count,
                                hipStream_t s);
 

@@ -160,6 +160,7 @@ KrSpec kr_spec(int N, int n, const int* l, int R, const float* const* fac, const
     }
     k.ftotal = off;
     k.skip = skip;
+    k.sweep = 0x7fffffff;
     return k;
 }
 
@@ -172,6 +173,23 @@ hipError_t launch_mttkrp(const StreamGeom& g, const KrSpec& kr, float* part, int
     hipError_t e = hipSuccess;
     RCP_NB_SWITCH(NBv, e = (launch_co<NB, 1, kWKr, kPrecFp32>(grid, smem, s, g, kr.R, nullptr, 0, 0,
                                                               0, part, nullptr, kr)));
+    return e;
+}
+
+hipError_t launch_mttkrp_full(const StreamGeom& g, const KrSpec& kr, float* part, int P,
+                              hipStream_t s) {
+    if (kr.R < 1 || kr.R > RCP_MAX_RANK || g.L > 0xffffffffLL || g.Rr > 0xffffffffLL)
+        return hipErrorInvalidValue;
+    const int NBv = lp_blocks(kr.R);
+    int MBv = (int)((g.I + 63) / 64);
+    if (MBv > 8) MBv = 8;
+    const int IB = 64 * MBv;
+    const dim3 grid((unsigned)P, (unsigned)((g.I + IB - 1) / IB));
+    const size_t smem = contract_out_smem(NBv, MBv);
+    hipError_t e = hipSuccess;
+    RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, e = (launch_co<NB, MB, kWKrG, kPrecFp32>(
+                                               grid, smem, s, g, kr.R, nullptr, 0, 0, 0, part,
+                                               nullptr, kr))));
     return e;
 }
 

@@ -314,13 +314,17 @@ __device__ __forceinline__ void store_partial(const f32x4 (&acc)[MHalf<MB>::v][N
 //   WK = kWOmega:  the Gaussian test matrix, generated in registers,
 //   WK = kWKr:     the Khatri-Rao product of the other modes' factors (the
 //                  mode product of CP-ALS, Algorithm 2 steps 4/6/8), formed
-//                  from a packed copy of the factors in LDS.
+//                  from a packed copy of the factors in LDS,
+//   WK = kWKrG:    the same product with the factor rows read from global
+//                  memory (through the caches): the full tensor's factors,
+//                  too large for LDS.
 // Optional float64 partial sum of squares of T (used for ||X||^2 in the
 // first pass).
 
 constexpr int kWStored = 0;
 constexpr int kWOmega = 1;
 constexpr int kWKr = 2;
+constexpr int kWKrG = 3;
 
 __device__ __forceinline__ uint32_t fast_udiv(uint32_t x, uint32_t mul, uint32_t shr) {
     return (uint32_t)(((uint64_t)__umulhi(x, mul) + x) >> shr);
@@ -346,6 +350,22 @@ __device__ __forceinline__ float kr_entry(const KrSpec& kr, const float* Fs, uin
     return p;
 }
 
+__device__ __forceinline__ float kr_entry_global(const KrSpec& kr, uint32_t a, uint32_t b, int c) {
+    float p = 1.0f;
+#pragma unroll
+    for (int m = RCP_MAX_NDIM - 1; m >= 0; --m) {
+        if (m < kr.N && m != kr.n) {
+            const bool inner = m > kr.n;
+            const uint32_t x = inner ? b : a;
+            const uint32_t q = fast_udiv(x, kr.mul[m], kr.shr[m]);
+            const uint32_t d = x - q * (uint32_t)kr.l[m];
+            if (inner) b = q; else a = q;
+            p *= kr.fac[m][(size_t)d * kr.R + c];
+        }
+    }
+    return p;
+}
+
 template <int NB, int MB, int WK, bool CB, int PR>
 __global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const float* Z,
                                                      uint64_t seed, uint32_t tag, int okind,
@@ -358,8 +378,10 @@ __global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const
     float* Fs = Ws + JT * LPc;              // kWKr: the packed factors
     __shared__ double red[NWS];
 
+    if (WK == kWKr || WK == kWKrG) {
+        if (kr.skip != nullptr && *kr.skip != 0 && kr.sweep > *kr.skip) return;
+    }
     if (WK == kWKr) {
-        if (kr.skip != nullptr && *kr.skip != 0) return;
 #pragma unroll
         for (int m = 0; m < RCP_MAX_NDIM; ++m) {
             if (m < kr.N && m != kr.n) {
@@ -389,7 +411,7 @@ __global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const
         __syncthreads();
         if (CB) sq += load_tile(g, ti, row0, nrows, IB, Ts, want_sq);
         else sq += tile_commit<MB>(pf, Ts, want_sq);
-        if (WK == kWKr) {
+        if (WK == kWKr || WK == kWKrG) {
             const float inv_rr = 1.0f / (float)g.Rr;
             for (int e = threadIdx.x; e < JT * LPc; e += NTS) {
                 const int jj = e / LPc, c = e % LPc;
@@ -404,7 +426,7 @@ __global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const
                         a = (uint32_t)(ti.a0 + q);
                         b = (uint32_t)(jj - q * (int)g.Rr);
                     }
-                    v = kr_entry(kr, Fs, a, b, c);
+                    v = (WK == kWKr) ? kr_entry(kr, Fs, a, b, c) : kr_entry_global(kr, a, b, c);
                 }
                 Ws[jj * LPc + c] = v;
             }

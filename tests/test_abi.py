@@ -94,7 +94,7 @@ def test_workspace_size_valid_and_monotone(lib):
 
 @pytest.mark.parametrize("field,value", [
     ("ndim", 1), ("ndim", 9), ("k", 0), ("p", -1), ("q", -1), ("k", 65), ("p", 60),
-    ("max_iters", 0), ("tol", -1.0), ("precision", 7), ("scheme", 3), ("solver", 2),
+    ("max_iters", 0), ("tol", -1.0), ("precision", 7), ("scheme", 3), ("solver", 3),
 ])
 def test_invalid_problems_rejected(lib, field, value):
     prob = _lib.make_problem((40, 30, 20), 5, 5, 1, 10, 0.0, 1)
@@ -142,6 +142,15 @@ def test_variant_fields_validated(lib):
                                       test_matrix="columns"))[0] == _lib.RCP_OK
 
 
+def test_cp_als_plan_sizes_its_workspace(lib):
+    """A deterministic CP-ALS plan adds the full-size working factors, its
+    sweep state and the subspace-iteration tensor of the start."""
+    als = _ws(lib, _lib.make_problem((120, 100, 80), 8, 6, 3, 20, 0.0, 1))
+    det = _ws(lib, _lib.make_problem((120, 100, 80), 8, 6, 3, 20, 0.0, 1, solver="cp_als"))
+    assert als[0] == det[0] == _lib.RCP_OK
+    assert det[1] >= als[1] + 100 * 80 * 14 * 4
+
+
 def test_init_checks_before_touching_the_gpu(lib):
     prob = _lib.make_problem((40, 30, 20), 5, 5, 1, 10, 0.0, 1)
     h = ctypes.c_void_p(0)
@@ -171,6 +180,7 @@ def test_null_plan_rejected_everywhere(lib):
     assert lib.rcp_norm2(None, None, 0, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_debug_omega(None, 0, 0, 1, 4, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_debug_columns(None, 0, 10, 4, None) == _lib.RCP_ERR_INVALID_ARG
+    assert lib.rcp_cp_als(None, None, None, None, None, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_get_bases(None, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_get_core(None, None, None) == _lib.RCP_ERR_INVALID_ARG
     assert lib.rcp_destroy(None) == _lib.RCP_ERR_INVALID_ARG
