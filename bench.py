@@ -74,6 +74,8 @@ def parse():
                     help="timed solves with bfloat16 and float16 operands (0 skips the comparison)")
     ap.add_argument("--mixed-large-steps", type=int, default=2,
                     help="timed solves per precision of the large mixed-precision workloads (0 skips)")
+    ap.add_argument("--validation-runs", type=int, default=100,
+                    help="runs per point of the Theorem 1 and SNR sweeps (0: skip)")
     ap.add_argument("--det-steps", type=int, default=2,
                     help="timed runs of deterministic CP-ALS on the secondary workload (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -473,6 +475,7 @@ def main():
         torch.cuda.empty_cache()
 
     batched = run_batch(args, torch, rcpgpu, dev) if args.batch > 0 else None
+    validation = run_validation(args, torch, dev) if args.validation_runs > 0 else None
     mixed_big = mixed_large(args, torch, rcpgpu, dev, skip=name) if args.mixed_large_steps > 0 else None
 
     out = {
@@ -499,6 +502,7 @@ def main():
         "secondary": secondary,
         "mixed_vs_fp32_large": mixed_big,
         "batched": batched,
+        "validation": validation,
     }
     if oracle_err is not None:
         out["oracle_rel_err"] = oracle_err
@@ -541,6 +545,35 @@ def deterministic(args, torch, rcpgpu, dev, name, X, base):
         out["mttkrp_full"] = {"launches": mt["launches"], "ms": mt["ms"], "GB_per_s": gbs,
                               "frac_hbm": gbs / PEAK_HBM_GBS}
     return out
+
+
+def run_validation(args, torch, dev):
+    """The paper's validation experiments over many runs on the GPU: the
+    Theorem 1 bound (50^3 and 50^4, rank 25, p = 2, q = 0) and the error
+    against SNR (100^3, rank 50, p = 10, q in {0, 2}, and deterministic
+    CP-ALS).  Per point: the means, the bound, the GPU time per run."""
+    from paper_1703_09074_amd import sweeps
+    runs = args.validation_runs
+    t0 = time.perf_counter()
+    th = {}
+    for dims, ks in (((50, 50, 50), (5, 10, 15, 20)), ((50, 50, 50, 50), (5, 10, 15, 20))):
+        r = sweeps.theorem1(dims, 25, ks, runs=runs, p=2, device=dev)
+        th["x".join(map(str, dims))] = [
+            {k: row[k] for k in ("k", "bound", "mean", "max", "holds", "ms_per_run", "path")}
+            for row in r["rows"]]
+        torch.cuda.empty_cache()
+    t1 = time.perf_counter()
+    snr = sweeps.snr_sweep((100, 100, 100), 50, snrs=(1, 2, 4, 8, 16), runs=runs, qs=(0, 2),
+                           p=10, iters=50, device=dev)
+    torch.cuda.empty_cache()
+    t2 = time.perf_counter()
+    levels = [{"snr": lev["snr"],
+               **{m: {"mean_rel_err": v["mean"], "std": v["std"], "ms_per_run": v["ms_per_run"]}
+                  for m, v in lev["methods"].items()}} for lev in snr["levels"]]
+    return {"runs": runs, "theorem1": th, "theorem1_s": t1 - t0,
+            "snr": {"dims": snr["dims"], "R": snr["R"], "p": snr["p"], "sweeps": snr["iters"],
+                    "levels": levels}, "snr_s": t2 - t1,
+            "data": "synthetic rank-R tensors, Gaussian factors; noise amplitude rms(clean)/SNR"}
 
 
 def concurrent(args, torch, rcpgpu, dev, name, X, base):

@@ -371,6 +371,9 @@ rcp_status rcp_profile_read(rcp_plan plan, int32_t kernel_class, int64_t* launch
  *   outcomes land in info[i].  RCP_ERR_INVALID_ARG: a null or misaligned
  *   pointer.
  * rcp_batch_read_status: the status word (rcp_read_status) of problem index.
+ * rcp_batch_get_core: rcp_get_core of problem index (the core B of its last
+ *   decomposition, l_0 x ... x l_{N-1}, inside the batch workspace; valid
+ *   until the next rcp_batch_decompose).
  * rcp_batch_destroy: waits for the batch stream, frees the host-side state
  *   (the graph included). */
 typedef struct rcp_batch_t* rcp_batch;
@@ -380,6 +383,7 @@ rcp_status rcp_batch_init(rcp_batch* batch, const rcp_problem* probs, int32_t co
 rcp_status rcp_batch_decompose(rcp_batch batch, const float* const* X, float* const* const* A,
                                float* const* lambda, rcp_als_info* info);
 rcp_status rcp_batch_read_status(rcp_batch batch, int32_t index, int32_t* status);
+rcp_status rcp_batch_get_core(rcp_batch batch, int32_t index, float** core, int64_t* core_dims);
 /* Autotuner of the batched launch shape (no counterpart in the paper, which
  * has no batched form).  Times complete batch decompositions of the given
  * inputs into the given outputs (so it also leaves their results there) for

@@ -415,6 +415,22 @@ class Batch:
         return {"streams": shape[0], "workgroups": shape[1], "row_block_rows": 64 * shape[2],
                 "ms_per_batch": ms.value}
 
+    def core(self, index: int):
+        """View of problem ``index``'s core from the last decompose
+        (rcp_batch_get_core; valid until the next decompose)."""
+        p = ctypes.c_void_p(0)
+        dims = (ctypes.c_int64 * _lib.RCP_MAX_NDIM)()
+        _lib.check(self.lib.rcp_batch_get_core(self.handle, int(index), ctypes.byref(p), dims),
+                   "rcp_batch_get_core")
+        shape = tuple(dims[n] for n in range(len(self.dims[index])))
+        n = 1
+        for d in shape:
+            n *= int(d)
+        off = int(p.value) - self.workspace.data_ptr()
+        if off < 0 or off % 4 or off + 4 * n > self.workspace.numel():
+            raise RuntimeError("library returned a pointer outside the workspace")
+        return self.workspace[off:off + 4 * n].view(_torch().float32).view(*shape)
+
     def read_status(self, index: int) -> int:
         """Status word of problem ``index`` (rcp_batch_read_status); blocks."""
         v = ctypes.c_int32(0)

@@ -101,6 +101,7 @@ SIGNATURES = {
     "rcp_batch_decompose": (_st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.POINTER(_vp)),
                                   ctypes.POINTER(_vp), _vp]),
     "rcp_batch_read_status": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "rcp_batch_get_core": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_int64)]),
     "rcp_batch_autotune": (_st, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.POINTER(_vp)),
                                  ctypes.POINTER(_vp), _vp, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_double)]),

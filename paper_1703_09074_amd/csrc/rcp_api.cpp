@@ -1350,6 +1350,11 @@ rcp_status rcp_batch_read_status(rcp_batch batch, int32_t index, int32_t* status
     return rcp_read_status(batch->plans[index], status);
 }
 
+rcp_status rcp_batch_get_core(rcp_batch batch, int32_t index, float** core, int64_t* core_dims) {
+    if (batch == nullptr || index < 0 || index >= batch->count) return RCP_ERR_INVALID_ARG;
+    return rcp_get_core(batch->plans[index], core, core_dims);
+}
+
 constexpr double kAutotuneGain = 0.97;
 
 // Coordinate search over the launch shape: each knob in turn takes every
