@@ -271,10 +271,13 @@ def test_als_grid_wide_matches_oracle(dims, R, iters, tol):
 def test_als_grid_wide_under_graph_capture():
     """The grid-wide ALS (mode products over the whole GPU, float64
     reductions, one-workgroup solves, a device-side stop flag) recorded into a
-    HIP graph: three replays (with eager work in between) each match the
-    oracle like the eager run does.  Eight sweeps from the eigenvector start
-    on this core amplify the float32 rounding of the mode products to a few
-    1e-7 in the fit, hence 5e-7 here."""
+    HIP graph: three replays (with eager work in between) each reproduce the
+    eager run exactly (the reductions have a fixed order) and match the
+    oracle.  Eight sweeps from the eigenvector start stop this core mid-descent
+    (the fit still moves by 1e-2 a sweep), where the float32 rounding of the
+    mode products is amplified to a few 1e-7 in the fit (1.9e-7 and 5.2e-7
+    for two summation orders of the products), hence 1e-6 against the
+    oracle."""
     dims, R, iters = (60, 55, 50), 40, 8
     w, comp = _core_problem(dims, R, 0.05, 29, R, 5, 1)
     core = _dev(comp.core.astype(np.float32))
@@ -287,7 +290,8 @@ def test_als_grid_wide_under_graph_capture():
         At_e, lam_e, info_e = plan.als(core, nx)             # eager
     torch.cuda.synchronize()
     eager = rcpgpu.Plan.read_info(info_e)
-    assert abs(eager["rho"] - ref.rho) <= 5e-7, (eager["rho"], ref.rho)
+    assert abs(eager["rho"] - ref.rho) <= 1e-6, (eager["rho"], ref.rho)
+    lam_eager = _np(lam_e)
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
         At_g, lam_g, info_g = plan.als(core, nx)
@@ -296,7 +300,9 @@ def test_als_grid_wide_under_graph_capture():
         torch.cuda.synchronize()
         got = rcpgpu.Plan.read_info(info_g)
         assert got["iters"] == iters and got["status"] == 0, got
-        assert abs(got["rho"] - ref.rho) <= 5e-7, (rep, got["rho"], ref.rho)
+        assert got["rho"] == eager["rho"], (rep, got["rho"], eager["rho"])
+        np.testing.assert_array_equal(_np(lam_g), lam_eager)
+        assert abs(got["rho"] - ref.rho) <= 1e-6, (rep, got["rho"], ref.rho)
         cong, cmin, perm = evaluate.congruence([_np(a) for a in At_g], ref.factors)
         assert cmin >= 0.999, cmin
         np.testing.assert_allclose(_np(lam_g), ref.lam[perm], rtol=1e-4)
