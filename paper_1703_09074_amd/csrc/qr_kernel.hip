@@ -390,8 +390,8 @@ __device__ __forceinline__ void householder_q(double* A, int lda, int m, int n, 
 }
 
 template <bool USE_LDS, int NB>
-__global__ __launch_bounds__(qr_threads<NB>()) void k_qr(double* Yg, int m, int n, int ldy, float* Qpad, int ldq,
-                                            float* Qout, int second_pass, int* status) {
+__device__ __forceinline__ void qr_body(double* Yg, int m, int n, int ldy, float* Qpad, int ldq,
+                                        float* Qout, int second_pass, int* status) {
     extern __shared__ double qsm[];
     __shared__ double taus[64];
     __shared__ double betas[64];
@@ -510,6 +510,19 @@ __global__ __launch_bounds__(qr_threads<NB>()) void k_qr(double* Yg, int m, int 
     }
 }
 
+template <bool USE_LDS, int NB>
+__global__ __launch_bounds__(qr_threads<NB>()) void k_qr(double* Yg, int m, int n, int ldy, float* Qpad, int ldq,
+                                            float* Qout, int second_pass, int* status) {
+    qr_body<USE_LDS, NB>(Yg, m, n, ldy, Qpad, ldq, Qout, second_pass, status);
+}
+
+// One workgroup per problem of a group (same template instantiation).
+template <bool USE_LDS, int NB>
+__global__ __launch_bounds__(qr_threads<NB>()) void k_qr_grp(const QrDesc* d) {
+    const QrDesc& D = d[blockIdx.x];
+    qr_body<USE_LDS, NB>(D.Y, D.m, D.n, D.ldy, D.Qpad, D.ldq, D.Qout, D.second_pass, D.status);
+}
+
 static size_t qr_lds_bytes(int64_t m, int n) {
     const int np = (n + 15) & ~15;
     return ((size_t)m * (np + 1) + 2 * (size_t)np * np + kQrScratch) * sizeof(double);
@@ -535,6 +548,32 @@ static hipError_t launch_qr_l(double* Y, int m, int n, int ldy, float* Qpad, int
         case 3: return launch_qr_t<L, 3>(Y, m, n, ldy, Qpad, ldq, Qout, sp, status, lds, s);
         default: return launch_qr_t<L, 4>(Y, m, n, ldy, Qpad, ldq, Qout, sp, status, lds, s);
     }
+}
+
+// the dynamic LDS a problem's QR takes (0: too tall for the LDS form)
+size_t qr_group_lds(int64_t m, int n) {
+    const size_t lds = qr_lds_bytes(m, n);
+    return lds <= kQrLds - 4096 ? lds : 0;
+}
+
+hipError_t launch_qr_group(const QrDesc* d, int count, int NBv, bool use_lds, size_t lds,
+                           hipStream_t s) {
+    if (count < 1) return hipSuccess;
+    if (!use_lds) return hipErrorInvalidValue;
+    hipError_t e = hipSuccess;
+    auto go = [&](auto kern, int threads) {
+        e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return;
+        hipLaunchKernelGGL(kern, dim3((unsigned)count), dim3(threads), lds, s, d);
+        e = hipGetLastError();
+    };
+    switch (NBv) {
+        case 1: go(k_qr_grp<true, 1>, qr_threads<1>()); break;
+        case 2: go(k_qr_grp<true, 2>, qr_threads<2>()); break;
+        case 3: go(k_qr_grp<true, 3>, qr_threads<3>()); break;
+        default: go(k_qr_grp<true, 4>, qr_threads<4>()); break;
+    }
+    return e;
 }
 
 hipError_t launch_qr(double* Y, int64_t m, int n, int ldy, float* Qpad, int ldq, float* Qout,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -1116,6 +1117,18 @@ rcp_status rcp_decompose_noalloc(const rcp_problem* prob, const float* X, float*
 
 constexpr int kBatchStreams = 16;       // branches the problems' compressions are spread over
 
+// One launch of the grouped batched form.
+struct GOp {
+    enum Kind { SKETCH, REDUCE, QR, POWER } kind;
+    int NB = 1, MB = 1, prec = 0;
+    bool caseB = false, fused = true;
+    size_t lds = 0;                       // QR: the group's largest dynamic LDS
+    int count = 0;                        // descriptors
+    size_t off = 0;                       // their byte offset in the tables
+    int gx = 1, gy = 1;                   // grid maxima
+    int64_t max_count = 0;                // reductions: largest element count
+};
+
 struct rcp_batch_t {
     int count = 0;
     hipStream_t stream = nullptr;
@@ -1139,14 +1152,48 @@ struct rcp_batch_t {
     int streams = kBatchStreams;
     int workgroups = 0;
     int mb_cap = 8;
+    // grouped form (every problem eligible): each step of the range finder is
+    // one launch over all problems, reading descriptor tables
+    bool grouped = false;
+    unsigned char* d_grp = nullptr;       // descriptor tables (workspace)
+    unsigned char* pin_grp = nullptr;     // pinned staging
+    size_t grp_bytes = 0;
+    std::vector<GOp> ops;                 // the launches, in order
+    std::vector<const float*> grp_X;      // inputs the tables were built for
+    int grp_workgroups = -1, grp_mb_cap = -1;
 };
 
 namespace {
 
 struct BatchLayout {
     std::vector<size_t> off, size;
-    size_t als = 0, exp = 0, total = 0;
+    size_t als = 0, exp = 0, grp = 0, grp_bytes = 0, total = 0;
 };
+
+// Whether a problem can take the grouped batched form: the sequential scheme,
+// every mode compressed by a generated test matrix, every mode's power step
+// in the fused kernel and every QR in its LDS form.  The others keep the
+// per-problem chains.
+bool grouped_eligible(const rcp_problem* p) {
+    if (p->scheme != RCP_SCHEME_SEQUENTIAL || p->test_matrix == RCP_TEST_COLUMNS) return false;
+    int64_t cur[RCP_MAX_NDIM];
+    for (int n = 0; n < p->ndim; ++n) cur[n] = p->dims[n];
+    for (int n = 0; n < p->ndim; ++n) {
+        if (!mode_compressed(p, n)) return false;
+        const int64_t I = cur[n];
+        const int l = (int)mode_width(p, n, I);
+        if (!power_fused_fits(I, l, kLdsBytes) || qr_group_lds(I, l) == 0) return false;
+        cur[n] = l;
+    }
+    return true;
+}
+
+// bytes of descriptor tables one problem needs in the grouped form
+size_t grouped_desc_bytes(const rcp_problem* p) {
+    const size_t q = (size_t)p->q;
+    return (size_t)p->ndim * (sizeof(SketchDesc) + (1 + q) * sizeof(ReduceDesc) +
+                              (q + 1) * sizeof(QrDesc) + (q + 1) * sizeof(PowerDesc));
+}
 
 rcp_status batch_layout(const rcp_problem* probs, int32_t count, BatchLayout* out) {
     if (probs == nullptr || count < 1) return RCP_ERR_INVALID_ARG;
@@ -1165,6 +1212,15 @@ rcp_status batch_layout(const rcp_problem* probs, int32_t count, BatchLayout* ou
     off = align_up(off + (size_t)count * sizeof(AlsArgs));
     B.exp = off;
     off = align_up(off + (size_t)count * sizeof(ExpandArgs));
+    bool grouped = true;
+    size_t gb = 0;
+    for (int i = 0; i < count; ++i) {
+        grouped = grouped && grouped_eligible(&probs[i]);
+        gb += grouped_desc_bytes(&probs[i]);
+    }
+    B.grp = off;
+    B.grp_bytes = grouped ? gb : 0;
+    off = align_up(off + B.grp_bytes);
     B.total = off;
     *out = B;
     return RCP_OK;
@@ -1250,17 +1306,247 @@ rcp_status batch_bind_outputs(rcp_batch_t* b, float* const* const* A, float* con
     return RCP_OK;
 }
 
+// The grouped program: the steps of compress_all (sketch_impl and
+// compress_impl) for every problem, round by round (mode n, then each power
+// iteration), each round's descriptors split by kernel instantiation into
+// one launch each.  Every problem gets the arguments and workgroup partition
+// of its own single-problem launches, so its results are the same bits.
+extern "C++" {
+template <typename D>
+struct GStep {
+    struct Item { int NB, MB, prec; bool caseB, fused; size_t lds; D d; int gx, gy; int64_t cnt; };
+    std::vector<Item> items;
+};
+
+template <typename D>
+void gstep_emit(GStep<D>& st, GOp::Kind kind, std::vector<GOp>& ops, std::vector<unsigned char>& blob) {
+    std::vector<bool> used(st.items.size(), false);
+    for (size_t i = 0; i < st.items.size(); ++i) {
+        if (used[i]) continue;
+        const auto& a = st.items[i];
+        GOp op;
+        op.kind = kind;
+        op.NB = a.NB; op.MB = a.MB; op.prec = a.prec; op.caseB = a.caseB; op.fused = a.fused;
+        op.off = blob.size();
+        for (size_t j = i; j < st.items.size(); ++j) {
+            const auto& c = st.items[j];
+            if (used[j] || c.NB != a.NB || c.MB != a.MB || c.prec != a.prec || c.caseB != a.caseB ||
+                c.fused != a.fused)
+                continue;
+            used[j] = true;
+            const unsigned char* src = (const unsigned char*)&c.d;
+            blob.insert(blob.end(), src, src + sizeof(D));
+            ++op.count;
+            op.gx = std::max(op.gx, c.gx);
+            op.gy = std::max(op.gy, c.gy);
+            op.lds = std::max(op.lds, c.lds);
+            op.max_count = std::max(op.max_count, c.cnt);
+        }
+        ops.push_back(op);
+    }
+    st.items.clear();
+}
+}  // extern "C++"
+
+void batch_build_program(rcp_batch_t* b, const float* const* X, std::vector<unsigned char>& blob) {
+    b->ops.clear();
+    blob.clear();
+    const int count = b->count;
+    std::vector<const float*> T(count);
+    std::vector<std::array<int64_t, RCP_MAX_NDIM>> cur(count);
+    std::vector<int> comp(count, 0);
+    int Nmax = 0, qmax = 0;
+    for (int i = 0; i < count; ++i) {
+        const rcp_plan_t* pl = b->plans[i];
+        T[i] = X[i];
+        for (int n = 0; n < pl->L.N; ++n) cur[i][n] = pl->L.dims[n];
+        Nmax = std::max(Nmax, pl->L.N);
+        qmax = std::max(qmax, pl->prob.q);
+    }
+    GStep<SketchDesc> sk;
+    GStep<ReduceDesc> rd;
+    GStep<QrDesc> qr;
+    GStep<PowerDesc> pw;
+    for (int n = 0; n < Nmax; ++n) {
+        struct ModeGeo { StreamGeom g; int l, LP, NB, P; };
+        std::vector<ModeGeo> mg(count);
+        for (int i = 0; i < count; ++i) {
+            rcp_plan_t* pl = b->plans[i];
+            if (n >= pl->L.N) continue;
+            const Layout& L = pl->L;
+            const int64_t I = cur[i][n];
+            ModeGeo& m = mg[i];
+            m.l = (int)std::min<int64_t>(pl->prob.k + mode_oversampling(&pl->prob, n), I);
+            m.LP = lp_of(m.l);
+            m.NB = m.LP / 16;
+            m.g = make_geom(T[i], cur[i].data(), L.N, n);
+            m.P = (int)std::max<int64_t>(1, std::min<int64_t>(pl->P, m.g.ntiles));
+            // sketch (Algorithm 1 steps 4-6), as launch_contract_out with Z == null
+            int MBv = (int)((I + 63) / 64);
+            if (I <= 512 && MBv > pl->mb_cap) MBv = pl->mb_cap;
+            MBv = std::max(1, std::min(8, MBv));
+            const int nIB = (int)((I + 64 * MBv - 1) / (64 * MBv));
+            SketchDesc d{};
+            d.g = m.g;
+            d.Z = nullptr;
+            d.part = pl->at<float>(L.part);
+            d.sq_part = (n == 0) ? pl->at<double>(L.sq) : nullptr;
+            d.seed = pl->prob.seed;
+            d.tag = omega_stream_tag(0, (uint32_t)n);
+            d.okind = pl->prob.test_matrix;
+            d.l = m.l;
+            d.P = m.P;
+            d.nIB = nIB;
+            sk.items.push_back({m.NB, MBv, pl->prob.precision, m.g.caseB != 0, false, 0, d, m.P, nIB, 0});
+            ReduceDesc r{};
+            r.part = pl->at<float>(L.part);
+            r.red1 = pl->at<double>(L.red1);
+            r.Y = pl->at<double>(L.y64);
+            r.sq_part = d.sq_part;
+            r.sq_out = (n == 0) ? pl->at<double>(L.norm) : nullptr;
+            r.count = I * m.LP;
+            r.P = m.P;
+            r.ny = reduce_split(m.P);
+            r.nsq = m.P * nIB;
+            rd.items.push_back({0, 0, 0, false, false, 0, r, 1, r.ny, r.count});
+        }
+        gstep_emit(sk, GOp::SKETCH, b->ops, blob);
+        gstep_emit(rd, GOp::REDUCE, b->ops, blob);
+        auto add_qr = [&](int i, bool final_basis) {
+            rcp_plan_t* pl = b->plans[i];
+            const Layout& L = pl->L;
+            const ModeGeo& m = mg[i];
+            QrDesc d{};
+            d.Y = pl->at<double>(L.y64);
+            d.m = (int)cur[i][n];
+            d.n = m.l;
+            d.ldy = m.LP;
+            d.Qpad = pl->at<float>(L.qt);
+            d.ldq = m.LP;
+            d.Qout = final_basis ? pl->at<float>(L.qb[n]) : nullptr;
+            d.second_pass = final_basis ? 1 : 0;
+            d.status = pl->status_word();
+            qr.items.push_back({(m.l + 15) >> 4, 0, 0, false, false, qr_group_lds(d.m, d.n), d, 1, 1, 0});
+        };
+        for (int it = 0; it < qmax; ++it) {
+            for (int i = 0; i < count; ++i) {
+                rcp_plan_t* pl = b->plans[i];
+                if (n >= pl->L.N || it >= pl->prob.q) continue;
+                add_qr(i, false);
+                const ModeGeo& m = mg[i];
+                PowerDesc d{};
+                d.g = m.g;
+                d.Qt = pl->at<float>(pl->L.qt);
+                d.part = pl->at<float>(pl->L.part);
+                d.out = nullptr;
+                d.P = m.P;
+                pw.items.push_back({m.NB, (int)((cur[i][n] + 63) / 64), pl->prob.precision,
+                                    m.g.caseB != 0, true, 0, d, m.P, 1, 0});
+                ReduceDesc r{};
+                r.part = pl->at<float>(pl->L.part);
+                r.red1 = pl->at<double>(pl->L.red1);
+                r.Y = pl->at<double>(pl->L.y64);
+                r.count = cur[i][n] * m.LP;
+                r.P = m.P;
+                r.ny = reduce_split(m.P);
+                rd.items.push_back({0, 0, 0, false, false, 0, r, 1, r.ny, r.count});
+            }
+            gstep_emit(qr, GOp::QR, b->ops, blob);
+            gstep_emit(pw, GOp::POWER, b->ops, blob);
+            gstep_emit(rd, GOp::REDUCE, b->ops, blob);
+        }
+        for (int i = 0; i < count; ++i)
+            if (n < b->plans[i]->L.N) add_qr(i, true);
+        gstep_emit(qr, GOp::QR, b->ops, blob);
+        // the mode product T x_n Q^T (Algorithm 1 step 13), float32 operands,
+        // as compress_impl's resident-basis kernel
+        for (int i = 0; i < count; ++i) {
+            rcp_plan_t* pl = b->plans[i];
+            if (n >= pl->L.N) continue;
+            const ModeGeo& m = mg[i];
+            float* out = pl->at<float>(pl->L.tb[comp[i] % 2]);
+            PowerDesc d{};
+            d.g = m.g;
+            d.Qt = pl->at<float>(pl->L.qt);
+            d.part = nullptr;
+            d.out = out;
+            d.P = m.P;
+            d.lout = m.l;
+            pw.items.push_back({m.NB, (int)((cur[i][n] + 63) / 64), RCP_PREC_FP32, m.g.caseB != 0, false,
+                                0, d, m.P, 1, 0});
+            cur[i][n] = m.l;
+            T[i] = out;
+            ++comp[i];
+        }
+        gstep_emit(pw, GOp::POWER, b->ops, blob);
+    }
+}
+
+rcp_status batch_enqueue_grouped(rcp_batch_t* b) {
+    for (const GOp& op : b->ops) {
+        const unsigned char* d = b->d_grp + op.off;
+        switch (op.kind) {
+            case GOp::SKETCH:
+                RCP_TRY(launch_sketch_group((const SketchDesc*)d, op.count, op.gx, op.gy, op.NB, op.MB,
+                                            op.caseB, false, op.prec, b->stream));
+                break;
+            case GOp::REDUCE:
+                RCP_TRY(launch_reduce_group((const ReduceDesc*)d, op.count, op.max_count, op.gy,
+                                            b->stream));
+                break;
+            case GOp::QR:
+                RCP_TRY(launch_qr_group((const QrDesc*)d, op.count, op.NB, true, op.lds, b->stream));
+                break;
+            case GOp::POWER:
+                RCP_TRY(launch_power_group((const PowerDesc*)d, op.count, op.gx, op.NB, op.MB, op.fused,
+                                           op.caseB, op.prec, b->stream));
+                break;
+        }
+    }
+    RCP_TRY(launch_als_batch(b->d_als, b->h_als.data(), b->count, b->stream));
+    RCP_TRY(launch_expand_batch(b->d_exp, b->h_exp.data(), b->count, b->stream));
+    return RCP_OK;
+}
+
+// (Re)builds and uploads the grouped tables when the inputs or the launch
+// shape changed; the batch stream is drained first (a launch in flight may
+// still read them).
+rcp_status batch_bind_grouped(rcp_batch_t* b, const float* const* X) {
+    bool same = (int)b->grp_X.size() == b->count && b->grp_workgroups == b->workgroups &&
+                b->grp_mb_cap == b->mb_cap;
+    for (int i = 0; same && i < b->count; ++i) same = b->grp_X[i] == X[i];
+    if (same) return RCP_OK;
+    std::vector<unsigned char> blob;
+    batch_build_program(b, X, blob);
+    if (blob.size() > b->grp_bytes) return RCP_ERR_WORKSPACE;
+    RCP_TRY(hipStreamSynchronize(b->stream));
+    std::memcpy(b->pin_grp, blob.data(), blob.size());
+    RCP_TRY(hipMemcpyAsync(b->d_grp, b->pin_grp, blob.size(), hipMemcpyHostToDevice, b->stream));
+    RCP_TRY(hipStreamSynchronize(b->stream));
+    b->grp_X.assign(X, X + b->count);
+    b->grp_workgroups = b->workgroups;
+    b->grp_mb_cap = b->mb_cap;
+    return RCP_OK;
+}
+
 rcp_status batch_run(rcp_batch_t* batch, const float* const* X) {
-    if (!batch->use_graph) return batch_enqueue(batch, X);
+    if (batch->grouped) {
+        const rcp_status sb = batch_bind_grouped(batch, X);
+        if (sb != RCP_OK) return sb;
+    }
+    auto enqueue = [&]() {
+        return batch->grouped ? batch_enqueue_grouped(batch) : batch_enqueue(batch, X);
+    };
+    if (!batch->use_graph) return enqueue();
     bool same = batch->exec != nullptr && (int)batch->X.size() == batch->count;
     for (int i = 0; same && i < batch->count; ++i) same = batch->X[i] == X[i];
     if (!same) {
         batch_drop_graph(batch);
         if (hipStreamBeginCapture(batch->stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
             batch->use_graph = false;
-            return batch_enqueue(batch, X);
+            return enqueue();
         }
-        const rcp_status st = batch_enqueue(batch, X);
+        const rcp_status st = enqueue();
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(batch->stream, &g);
         if (st != RCP_OK) {
@@ -1328,6 +1614,15 @@ rcp_status rcp_batch_init(rcp_batch* batch, const rcp_problem* probs, int32_t co
     if (!ok) { rcp_batch_destroy(b); return RCP_ERR_HIP; }
     b->d_als = (AlsArgs*)(ws + B.als);
     b->d_exp = (ExpandArgs*)(ws + B.exp);
+    if (B.grp_bytes > 0) {
+        b->grouped = true;
+        b->d_grp = (unsigned char*)(ws + B.grp);
+        b->grp_bytes = B.grp_bytes;
+        if (hipHostMalloc((void**)&b->pin_grp, B.grp_bytes, hipHostMallocDefault) != hipSuccess) {
+            rcp_batch_destroy(b);
+            return RCP_ERR_HIP;
+        }
+    }
     b->use_graph = hip_stream != nullptr;
     b->workgroups = b->plans[0]->P;
     *batch = b;
@@ -1440,6 +1735,7 @@ rcp_status rcp_batch_destroy(rcp_batch batch) {
     if (batch->fork != nullptr) hipEventDestroy(batch->fork);
     if (batch->pin_als != nullptr) hipHostFree(batch->pin_als);
     if (batch->pin_exp != nullptr) hipHostFree(batch->pin_exp);
+    if (batch->pin_grp != nullptr) hipHostFree(batch->pin_grp);
     delete batch;
     return RCP_OK;
 }

@@ -24,6 +24,60 @@ struct StreamGeom {
 
 StreamGeom make_geom(const float* T, const int64_t* dims, int ndim, int mode);
 
+// Grouped launches: one launch runs the same step for many problems, each
+// workgroup reading its problem's arguments from a device table (blockIdx.z
+// for the streaming kernels and the reductions, blockIdx.x for the QR).
+// Workgroups past a problem's own grid return at once, so every problem
+// gets exactly the partition (P workgroups, nIB row blocks) that its
+// single-problem launch would use.
+struct SketchDesc {            // k_contract_out with a generated test matrix
+    StreamGeom g;
+    const float* Z;            // stored Z (two-pass power step) or null (sketch)
+    float* part;
+    double* sq_part;           // null: no sum of squares
+    uint64_t seed;
+    uint32_t tag;
+    int okind, l, P, nIB;
+};
+struct PowerDesc {             // k_power_fused (fused power step or mode product)
+    StreamGeom g;
+    const float* Qt;
+    float* part;
+    float* out;
+    int P, lout, accumulate, pad_;
+};
+struct ReduceDesc {            // k_reduce_stage1/2
+    const float* part;
+    double* red1;
+    double* Y;
+    const double* sq_part;
+    double* sq_out;
+    int64_t count;
+    int P, ny, nsq, pad_;
+};
+struct QrDesc {                // k_qr
+    double* Y;
+    float* Qpad;
+    float* Qout;
+    int* status;
+    int m, n, ldy, ldq, second_pass, pad_;
+};
+// grid maxima of a group: gx workgroups along the tiles, gy row blocks (or
+// reduction splits), count descriptors; key = the template instantiation
+hipError_t launch_sketch_group(const SketchDesc* d, int count, int gx, int gy, int NB, int MB,
+                               bool caseB, bool stored, int precision, hipStream_t s);
+hipError_t launch_power_group(const PowerDesc* d, int count, int gx, int NB, int MB, bool fused,
+                              bool caseB, int precision, hipStream_t s);
+hipError_t launch_reduce_group(const ReduceDesc* d, int count, int64_t max_count, int max_ny,
+                               hipStream_t s);
+hipError_t launch_qr_group(const QrDesc* d, int count, int NB, bool use_lds, size_t lds,
+                           hipStream_t s);
+size_t qr_group_lds(int64_t m, int n);
+hipError_t launch_sketch_group_lp(const SketchDesc* d, int count, int gx, int gy, int NB, int MB,
+                                  bool caseB, bool stored, int precision, hipStream_t s);
+hipError_t launch_power_group_lp(const PowerDesc* d, int count, int gx, int NB, int MB, bool fused,
+                                 bool caseB, int precision, hipStream_t s);
+
 // streaming contractions (stream_kernels.hip)
 // precision: matrix-core operand type of the contraction (RCP_PREC_*)
 // mb_cap: at most 64 * mb_cap rows per row block for modes of at most 512

@@ -43,6 +43,34 @@ __global__ __launch_bounds__(NT) void k_reduce_stage2(const double* red1, int ny
     }
 }
 
+// Grouped reductions: blockIdx.z picks the problem; each keeps its own split
+// (ny) and element count, so its sums are those of launch_reduce_partials.
+__global__ __launch_bounds__(NT) void k_reduce_stage1_grp(const ReduceDesc* d) {
+    const ReduceDesc& D = d[blockIdx.z];
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e >= D.count || (int)blockIdx.y >= D.ny) return;
+    const int y = blockIdx.y, ny = D.ny, P = D.P;
+    const int p0 = (int)((int64_t)P * y / ny), p1 = (int)((int64_t)P * (y + 1) / ny);
+    double s = 0.0;
+    for (int p = p0; p < p1; ++p) s += (double)D.part[(int64_t)p * D.count + e];
+    D.red1[(int64_t)y * D.count + e] = s;
+}
+
+__global__ __launch_bounds__(NT) void k_reduce_stage2_grp(const ReduceDesc* d) {
+    const ReduceDesc& D = d[blockIdx.z];
+    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (e < D.count) {
+        double s = 0.0;
+        for (int y = 0; y < D.ny; ++y) s += D.red1[(int64_t)y * D.count + e];
+        D.Y[e] = s;
+    }
+    if (D.sq_part != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
+        double s = 0.0;
+        for (int p = 0; p < D.nsq; ++p) s += D.sq_part[p];
+        *D.sq_out = s;
+    }
+}
+
 // Sum of squares of count floats: per-block float64 partials.
 __global__ __launch_bounds__(NT) void k_sumsq(const float* x, int64_t count, double* part) {
     __shared__ double red[NT / 64];
@@ -273,6 +301,33 @@ hipError_t launch_reduce_partials(const float* part, int P, int64_t count, doubl
     hipLaunchKernelGGL(k_reduce_stage2, dim3(blocks > 0 ? blocks : 1), dim3(NT), 0, s, red1, ny,
                        count, Y, sq_part, nsq, sq_out);
     return hipGetLastError();
+}
+
+hipError_t launch_reduce_group(const ReduceDesc* d, int count, int64_t max_count, int max_ny,
+                               hipStream_t s) {
+    if (count < 1) return hipSuccess;
+    const unsigned blocks = (unsigned)((max_count + NT - 1) / NT);
+    hipLaunchKernelGGL(k_reduce_stage1_grp, dim3(blocks > 0 ? blocks : 1, (unsigned)max_ny, (unsigned)count),
+                       dim3(NT), 0, s, d);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_stage2_grp, dim3(blocks > 0 ? blocks : 1, 1, (unsigned)count), dim3(NT),
+                       0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_sketch_group(const SketchDesc* d, int count, int gx, int gy, int NB, int MB,
+                               bool caseB, bool stored, int precision, hipStream_t s) {
+    if (precision == kPrecFp32)
+        return launch_sketch_group_t<kPrecFp32>(d, count, gx, gy, NB, MB, caseB, stored, s);
+    return launch_sketch_group_lp(d, count, gx, gy, NB, MB, caseB, stored, precision, s);
+}
+
+hipError_t launch_power_group(const PowerDesc* d, int count, int gx, int NB, int MB, bool fused,
+                              bool caseB, int precision, hipStream_t s) {
+    if (precision == kPrecFp32)
+        return launch_power_group_t<kPrecFp32>(d, count, gx, NB, MB, fused, caseB, s);
+    return launch_power_group_lp(d, count, gx, NB, MB, fused, caseB, precision, s);
 }
 
 hipError_t launch_sumsq(const float* x, int64_t count, double* part, int nblocks, double* out,

@@ -29,4 +29,18 @@ hipError_t launch_contract_in_lp(int precision, const StreamGeom& g, int l, cons
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_sketch_group_lp(const SketchDesc* d, int count, int gx, int gy, int NB, int MB,
+                                  bool caseB, bool stored, int precision, hipStream_t s) {
+    if (precision == kPrecBf16) return launch_sketch_group_t<kPrecBf16>(d, count, gx, gy, NB, MB, caseB, stored, s);
+    if (precision == kPrecFp16) return launch_sketch_group_t<kPrecFp16>(d, count, gx, gy, NB, MB, caseB, stored, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_power_group_lp(const PowerDesc* d, int count, int gx, int NB, int MB, bool fused,
+                                 bool caseB, int precision, hipStream_t s) {
+    if (precision == kPrecBf16) return launch_power_group_t<kPrecBf16>(d, count, gx, NB, MB, fused, caseB, s);
+    if (precision == kPrecFp16) return launch_power_group_t<kPrecFp16>(d, count, gx, NB, MB, fused, caseB, s);
+    return hipErrorInvalidValue;
+}
+
 }  // namespace rcp

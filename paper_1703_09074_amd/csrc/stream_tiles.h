@@ -366,10 +366,14 @@ __device__ __forceinline__ float kr_entry_global(const KrSpec& kr, uint32_t a, u
     return p;
 }
 
+// The body takes its workgroup's position (bx of nbx along the tiles, row
+// block by) as arguments, so that a grouped launch can run it for many
+// problems at once.
 template <int NB, int MB, int WK, bool CB, int PR>
-__global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const float* Z,
-                                                     uint64_t seed, uint32_t tag, int okind,
-                                                     float* part, double* sq_part, KrSpec kr) {
+__device__ __forceinline__ void contract_out_body(const StreamGeom& g, int l, const float* Z,
+                                                  uint64_t seed, uint32_t tag, int okind,
+                                                  float* part, double* sq_part, const KrSpec& kr,
+                                                  int bx, int nbx, int by) {
     constexpr int LPc = NB * 16;
     constexpr int IB = 64 * MB;
     extern __shared__ __align__(16) float smem[];
@@ -391,7 +395,7 @@ __global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const
         }
     }
 
-    const int64_t row0 = (int64_t)blockIdx.y * IB;
+    const int64_t row0 = (int64_t)by * IB;
     const int64_t rows_left = g.I - row0;
     const int nrows = (int)(rows_left < IB ? rows_left : IB);
 
@@ -404,9 +408,9 @@ __global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const
     double sq = 0.0;
     const bool want_sq = sq_part != nullptr;
     TileRegs<MB> pf;
-    int64_t t = blockIdx.x;
+    int64_t t = bx;
     if (!CB && t < g.ntiles) tile_issue<MB>(g, tile_info(g, t), row0, nrows, pf);
-    for (; t < g.ntiles; t += gridDim.x) {
+    for (; t < g.ntiles; t += nbx) {
         const TileInfo ti = tile_info(g, t);
         __syncthreads();
         if (CB) sq += load_tile(g, ti, row0, nrows, IB, Ts, want_sq);
@@ -466,16 +470,24 @@ __global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const
                 Ws[jj * LPc + c] = v;
             }
         }
-        const int64_t tn = t + gridDim.x;
+        const int64_t tn = t + nbx;
         if (!CB && tn < g.ntiles) tile_issue<MB>(g, tile_info(g, tn), row0, nrows, pf);
         __syncthreads();
         tile_times_w<NB, MB, PR>(Ts, Ws, LPc, acc);
     }
-    store_partial<NB, MB>(acc, part + (int64_t)blockIdx.x * g.I * LPc, g.I, row0);
+    store_partial<NB, MB>(acc, part + (int64_t)bx * g.I * LPc, g.I, row0);
     if (want_sq) {
         const double s = block_sum(sq, red);
-        if (threadIdx.x == 0) sq_part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+        if (threadIdx.x == 0) sq_part[(int64_t)by * nbx + bx] = s;
     }
+}
+
+template <int NB, int MB, int WK, bool CB, int PR>
+__global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const float* Z,
+                                                     uint64_t seed, uint32_t tag, int okind,
+                                                     float* part, double* sq_part, KrSpec kr) {
+    contract_out_body<NB, MB, WK, CB, PR>(g, l, Z, seed, tag, okind, part, sq_part, kr,
+                                          (int)blockIdx.x, (int)gridDim.x, (int)blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -486,8 +498,9 @@ __global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const
 // absorbs, so it is not applied.
 
 template <int NB, int MB, bool FUSED, bool CB, int PR>
-__global__ __launch_bounds__(NTS) void k_power_fused(StreamGeom g, const float* Qt, float* part,
-                                                    int lout, float* out, int accumulate) {
+__device__ __forceinline__ void power_fused_body(const StreamGeom& g, const float* Qt, float* part,
+                                                 int lout, float* out, int accumulate, int bx,
+                                                 int nbx) {
     constexpr int LPc = NB * 16;
     constexpr int IB = 64 * MB;
     extern __shared__ __align__(16) float smem[];
@@ -509,14 +522,14 @@ __global__ __launch_bounds__(NTS) void k_power_fused(StreamGeom g, const float* 
         for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     TileRegs<MB> pf;
-    int64_t t = blockIdx.x;
+    int64_t t = bx;
     if (!CB && t < g.ntiles) tile_issue<MB>(g, tile_info(g, t), 0, I, pf);
-    for (; t < g.ntiles; t += gridDim.x) {
+    for (; t < g.ntiles; t += nbx) {
         const TileInfo ti = tile_info(g, t);
         __syncthreads();
         if (CB) load_tile(g, ti, 0, I, IB, Ts, false);
         else tile_commit<MB>(pf, Ts, false);
-        const int64_t tn = t + gridDim.x;
+        const int64_t tn = t + nbx;
         if (!CB && tn < g.ntiles) tile_issue<MB>(g, tile_info(g, tn), 0, I, pf);
         __syncthreads();
         f32x4 zacc[NB];
@@ -540,7 +553,33 @@ __global__ __launch_bounds__(NTS) void k_power_fused(StreamGeom g, const float* 
             }
         }
     }
-    if (FUSED) store_partial<NB, MB>(acc, part + (int64_t)blockIdx.x * g.I * LPc, g.I, 0);
+    if (FUSED) store_partial<NB, MB>(acc, part + (int64_t)bx * g.I * LPc, g.I, 0);
+}
+
+template <int NB, int MB, bool FUSED, bool CB, int PR>
+__global__ __launch_bounds__(NTS) void k_power_fused(StreamGeom g, const float* Qt, float* part,
+                                                    int lout, float* out, int accumulate) {
+    power_fused_body<NB, MB, FUSED, CB, PR>(g, Qt, part, lout, out, accumulate, (int)blockIdx.x,
+                                            (int)gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped forms: blockIdx.z picks the problem.
+
+template <int NB, int MB, int WK, bool CB, int PR>
+__global__ __launch_bounds__(NTS) void k_contract_out_grp(const SketchDesc* d) {
+    const SketchDesc& D = d[blockIdx.z];
+    if ((int)blockIdx.x >= D.P || (int)blockIdx.y >= D.nIB) return;
+    contract_out_body<NB, MB, WK, CB, PR>(D.g, D.l, D.Z, D.seed, D.tag, D.okind, D.part, D.sq_part,
+                                          KrSpec{}, (int)blockIdx.x, D.P, (int)blockIdx.y);
+}
+
+template <int NB, int MB, bool FUSED, bool CB, int PR>
+__global__ __launch_bounds__(NTS) void k_power_fused_grp(const PowerDesc* d) {
+    const PowerDesc& D = d[blockIdx.z];
+    if ((int)blockIdx.x >= D.P) return;
+    power_fused_body<NB, MB, FUSED, CB, PR>(D.g, D.Qt, D.part, D.lout, D.out, D.accumulate,
+                                            (int)blockIdx.x, D.P);
 }
 
 // ---------------------------------------------------------------------------
@@ -915,5 +954,49 @@ hipError_t launch_contract_in_t(const StreamGeom& g, int l, const float* Qpadded
     return e;
 }
 
+
+template <int PR>
+hipError_t launch_sketch_group_t(const SketchDesc* d, int count, int gx, int gy, int NBv, int MBv,
+                                 bool caseB, bool stored, hipStream_t s) {
+    if (count < 1) return hipSuccess;
+    const size_t smem = contract_out_smem(NBv, MBv);
+    const dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)count);
+    hipError_t e = hipSuccess;
+    RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, {
+        auto k = stored ? (caseB ? k_contract_out_grp<NB, MB, kWStored, true, PR>
+                                 : k_contract_out_grp<NB, MB, kWStored, false, PR>)
+                        : (caseB ? k_contract_out_grp<NB, MB, kWOmega, true, PR>
+                                 : k_contract_out_grp<NB, MB, kWOmega, false, PR>);
+        e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)smem);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k, grid, dim3(NTS), smem, s, d);
+            e = hipGetLastError();
+        }
+    }));
+    return e;
+}
+
+template <int PR>
+hipError_t launch_power_group_t(const PowerDesc* d, int count, int gx, int NBv, int MBv,
+                                bool fused, bool caseB, hipStream_t s) {
+    if (count < 1) return hipSuccess;
+    const size_t smem = power_fused_smem(NBv, MBv);
+    const dim3 grid((unsigned)gx, 1, (unsigned)count);
+    hipError_t e = hipSuccess;
+    RCP_NB_SWITCH(NBv, RCP_MB_SWITCH(MBv, {
+        auto k = fused ? (caseB ? k_power_fused_grp<NB, MB, true, true, PR>
+                                : k_power_fused_grp<NB, MB, true, false, PR>)
+                       : (caseB ? k_power_fused_grp<NB, MB, false, true, PR>
+                                : k_power_fused_grp<NB, MB, false, false, PR>);
+        e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)smem);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k, grid, dim3(NTS), smem, s, d);
+            e = hipGetLastError();
+        }
+    }));
+    return e;
+}
 
 }  // namespace rcp
