@@ -369,7 +369,14 @@ rcp_status rcp_profile_read(rcp_plan plan, int32_t kernel_class, int64_t* launch
  *   pointers re-record it).  On the null stream the kernels are enqueued
  *   directly.  Asynchronous otherwise, like every other call; numeric
  *   outcomes land in info[i].  RCP_ERR_INVALID_ARG: a null or misaligned
- *   pointer.
+ *   pointer.  When every problem uses the sequential scheme, compresses
+ *   every mode with a generated test matrix and has modes that fit the fused
+ *   power kernel and the LDS QR (at most 512 rows), the range finder runs in
+ *   phase order: each step (sketch, reduction, QR, power step, mode product)
+ *   is one launch over all problems (descriptor tables in the workspace,
+ *   rebuilt when X or the launch shape changes); otherwise each problem's
+ *   chain runs on the internal streams.  Either way every problem gets the
+ *   arithmetic of its single-problem rcp_decompose, bit for bit.
  * rcp_batch_read_status: the status word (rcp_read_status) of problem index.
  * rcp_batch_get_core: rcp_get_core of problem index (the core B of its last
  *   decomposition, l_0 x ... x l_{N-1}, inside the batch workspace; valid
@@ -389,8 +396,12 @@ rcp_status rcp_batch_get_core(rcp_batch batch, int32_t index, float** core, int6
  * inputs into the given outputs (so it also leaves their results there) for
  * candidate shapes, searching one knob at a time with the others at their
  * best so far:
- *   shape[0] internal streams the compressions are spread over: 4, 8, 16;
- *   shape[1] workgroups per streaming pass: 64, 128, one per compute unit;
+ *   shape[0] internal streams the compressions are spread over: 4, 8, 16
+ *            (not searched when every problem takes the grouped form, which
+ *            runs each step as one launch over all problems on the batch
+ *            stream);
+ *   shape[1] workgroups per streaming pass (at most one per tile): 16, 32,
+ *            64, 128, one per compute unit;
  *   shape[2] rows per row block of the sketch passes of modes with at most
  *            512 rows, in units of 64: 1, 2, 4, 8.
  * Each candidate is recorded once and timed over two replays with HIP events

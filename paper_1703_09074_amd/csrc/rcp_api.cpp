@@ -1692,11 +1692,12 @@ rcp_status rcp_batch_autotune(rcp_batch batch, const float* const* X, float* con
     };
     st = measure(best, &best_t);
     const int cand_s[] = {4, 8, kBatchStreams};
-    const int cand_p[] = {64, 128, cus_default};
+    const int cand_p[] = {16, 32, 64, 128, cus_default};
     const int cand_m[] = {1, 2, 4, 8};
     const int* cands[3] = {cand_s, cand_p, cand_m};
-    const int ncand[3] = {3, 3, 4};
-    for (int knob = 0; knob < 3 && st == RCP_OK; ++knob) {
+    const int ncand[3] = {3, 5, 4};
+    // the grouped form runs on the batch stream alone: no stream knob
+    for (int knob = batch->grouped ? 1 : 0; knob < 3 && st == RCP_OK; ++knob) {
         for (int c = 0; c < ncand[knob] && st == RCP_OK; ++c) {
             int trial[3] = {best[0], best[1], best[2]};
             if (trial[knob] == cands[knob][c]) continue;
