@@ -523,6 +523,174 @@ __global__ __launch_bounds__(qr_threads<NB>()) void k_qr_grp(const QrDesc* d) {
     qr_body<USE_LDS, NB>(D.Y, D.m, D.n, D.ldy, D.Qpad, D.ldq, D.Qout, D.second_pass, D.status);
 }
 
+// ---------------------------------------------------------------------------
+// Tall bases (Y too large for one workgroup's LDS): the same Cholesky QR
+// passes with the O(m n^2) work spread over row blocks of kTqRows rows.
+// Per pass: partial Grams per row block (k_tqr_gram), their sum in block
+// order with the Cholesky factor and its inverse in one workgroup
+// (k_tqr_chol), and Y <- Y R^{-1} per row block (k_tqr_apply, which also
+// writes the float32 outputs after the last pass).  A failed Cholesky sets
+// the flag at work[0]; the later launches then return and k_tqr_fallback
+// runs the one-workgroup kernel (Householder) on Y as it stands: Y times
+// upper-triangular factors with positive diagonal has the same Q.
+constexpr int kTqRows = 64;
+constexpr int kTqThreads = 512;
+
+__device__ __forceinline__ int* tqr_flag(double* work) { return (int*)work; }
+__device__ __forceinline__ double* tqr_X(double* work) { return work + 8; }
+__device__ __forceinline__ double* tqr_G(double* work, int np) { return work + 8 + np * np; }
+
+template <int NB>
+__global__ __launch_bounds__(kTqThreads) void k_tqr_gram(const double* Y, int m, int n, int ldy,
+                                                         double* work) {
+    extern __shared__ double qsm[];
+    constexpr int np = 16 * NB;
+    if (*tqr_flag(work) != 0) return;
+    const int r0 = blockIdx.x * kTqRows;
+    const int rows = min(kTqRows, m - r0);
+    double* G = qsm;
+    double* part = qsm + np * np;
+    gram64(Y + (size_t)r0 * ldy, ldy, rows, n, np, G, part, 2 * (kTqThreads / 64));
+    double* dst = tqr_G(work, np) + (size_t)blockIdx.x * np * np;
+    for (int e = threadIdx.x; e < np * np; e += kTqThreads) dst[e] = G[e];
+}
+
+template <int NB>
+__global__ __launch_bounds__(qr_threads<NB>()) void k_tqr_chol(int m, int n, int nblk, int pass,
+                                                               double* work) {
+    extern __shared__ double qsm[];
+    __shared__ double dinv[64];
+    __shared__ double red[QNW];
+    constexpr int np = 16 * NB;
+    const int tid = threadIdx.x;
+    if (*tqr_flag(work) != 0) return;
+    double* G = qsm;
+    double* X = G + np * np;
+    double* scratch = X + np * np;
+    const double* Gp = tqr_G(work, np);
+    for (int e = tid; e < np * np; e += qnt()) {
+        double v = 0.0;
+        for (int b = 0; b < nblk; ++b) v += Gp[(size_t)b * np * np + e];
+        G[e] = v;
+    }
+    __syncthreads();
+    bool first_order = false;
+    if (pass == 2) {
+        double e = 0.0;
+        for (int t = tid; t < n * n; t += qnt()) {
+            const int i = t / n, j = t - (t / n) * n;
+            e = fmax(e, fabs(G[i * np + j] - (i == j ? 1.0 : 0.0)));
+        }
+        first_order = qr_block_max(e, red) <= kCqrFirstOrder;
+    }
+    int flag = 1;
+    if (first_order) {
+        for (int t = tid; t < np * np; t += qnt()) {
+            const int i = t / np, j = t - (t / np) * np;
+            double v = 0.0;
+            if (i < n && j < n && i <= j) {
+                const double f = (i == j) ? 0.5 * (G[t] - 1.0) : G[t];
+                v = ((i == j) ? 1.0 : 0.0) - f;
+            }
+            X[t] = v;
+        }
+    } else {
+        const double sc = pass == 0 ? 11.0 * ((double)m * n + (double)n * (n + 1)) * kUnitRoundoff : 0.0;
+        if (np <= 32) {
+            if (tid < 64) {
+                const int okw = (np == 16) ? chol_inverse_wave<16>(G, X, n, sc, dinv)
+                                           : chol_inverse_wave<32>(G, X, n, sc, dinv);
+                if (tid == 0) red[0] = okw ? 1.0 : 0.0;
+            }
+            __syncthreads();
+            flag = red[0] != 0.0;
+            __syncthreads();
+        } else {
+            flag = chol_inverse(G, X, scratch, dinv, red, n, np, sc);
+        }
+    }
+    __syncthreads();
+    if (!flag) {
+        if (tid == 0) *tqr_flag(work) = 1;
+        return;
+    }
+    double* Xg = tqr_X(work);
+    for (int e = tid; e < np * np; e += qnt()) Xg[e] = X[e];
+}
+
+template <int NB>
+__global__ __launch_bounds__(kTqThreads) void k_tqr_apply(double* Y, int m, int n, int ldy,
+                                                          double* work, float* Qpad, int ldq,
+                                                          float* Qout, int last) {
+    __shared__ double Xs[16 * NB * 16 * NB];
+    constexpr int np = 16 * NB;
+    if (*tqr_flag(work) != 0) return;
+    const double* Xg = tqr_X(work);
+    for (int e = threadIdx.x; e < np * np; e += kTqThreads) Xs[e] = Xg[e];
+    __syncthreads();
+    const int r0 = blockIdx.x * kTqRows;
+    const int rows = min(kTqRows, m - r0);
+    double* A = Y + (size_t)r0 * ldy;
+    apply_upper<NB>(A, ldy, rows, n, Xs);
+    if (!last) return;
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows * ldq; e += kTqThreads) {
+        const int i = e / ldq, c = e - (e / ldq) * ldq;
+        const float f = (c < n) ? (float)A[(size_t)i * ldy + c] : 0.0f;
+        if (Qout != nullptr && c < n) Qout[(int64_t)(r0 + i) * n + c] = f;
+        Qpad[(int64_t)(r0 + i) * ldq + c] = f;
+    }
+}
+
+template <int NB>
+__global__ __launch_bounds__(qr_threads<NB>()) void k_tqr_fallback(double* Yg, int m, int n, int ldy,
+                                                                   float* Qpad, int ldq, float* Qout,
+                                                                   int second_pass, int* status,
+                                                                   double* work) {
+    if (*tqr_flag(work) == 0) return;
+    qr_body<false, NB>(Yg, m, n, ldy, Qpad, ldq, Qout, second_pass, status);
+}
+
+template <int NB>
+static hipError_t launch_tqr_t(double* Y, int m, int n, int ldy, float* Qpad, int ldq, float* Qout,
+                               bool final_basis, int* status, double* work, hipStream_t s) {
+    constexpr int np = 16 * NB;
+    const int nblk = (m + kTqRows - 1) / kTqRows;
+    hipError_t e = launch_fill_i32((int*)work, 0, 2, s);
+    if (e != hipSuccess) return e;
+    const size_t gsm = (size_t)(np * np + 2 * (kTqThreads / 64) * 256) * sizeof(double);
+    const size_t csm = (size_t)(2 * np * np + 2 * kQrScratch) * sizeof(double);
+    if ((e = hipFuncSetAttribute((const void*)k_tqr_gram<NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)gsm)) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute((const void*)k_tqr_chol<NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)csm)) != hipSuccess)
+        return e;
+    const int passes = final_basis ? 3 : 2;
+    for (int pass = 0; pass < passes; ++pass) {
+        hipLaunchKernelGGL(k_tqr_gram<NB>, dim3((unsigned)nblk), dim3(kTqThreads), gsm, s, Y, m, n, ldy, work);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_tqr_chol<NB>, dim3(1), dim3(qr_threads<NB>()), csm, s, m, n, nblk, pass, work);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_tqr_apply<NB>, dim3((unsigned)nblk), dim3(kTqThreads), 0, s, Y, m, n, ldy, work,
+                           Qpad, ldq, Qout, pass == passes - 1 ? 1 : 0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const size_t fsm = (2 * (size_t)np * np + 2 * kQrScratch) * sizeof(double);
+    if ((e = hipFuncSetAttribute((const void*)k_tqr_fallback<NB>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)fsm)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_tqr_fallback<NB>, dim3(1), dim3(qr_threads<NB>()), fsm, s, Y, m, n, ldy, Qpad, ldq,
+                       Qout, final_basis ? 1 : 0, status, work);
+    return hipGetLastError();
+}
+
+// doubles of work space the tall form needs
+size_t qr_tall_work_doubles(int64_t m, int n) {
+    const int np = (n + 15) & ~15;
+    return 8 + (size_t)np * np + (size_t)((m + kTqRows - 1) / kTqRows) * np * np;
+}
+
 static size_t qr_lds_bytes(int64_t m, int n) {
     const int np = (n + 15) & ~15;
     return ((size_t)m * (np + 1) + 2 * (size_t)np * np + kQrScratch) * sizeof(double);
@@ -577,13 +745,21 @@ hipError_t launch_qr_group(const QrDesc* d, int count, int NBv, bool use_lds, si
 }
 
 hipError_t launch_qr(double* Y, int64_t m, int n, int ldy, float* Qpad, int ldq, float* Qout,
-                     bool final_basis, int* status, hipStream_t s) {
+                     bool final_basis, int* status, hipStream_t s, double* work) {
     const int np = (n + 15) & ~15;
     if (n < 1 || n > 64 || ldy < np || ldq < n || m < n || m > ((int64_t)1 << 24)) return hipErrorInvalidValue;
     const int sp = final_basis ? 1 : 0;
     const size_t lds = qr_lds_bytes(m, n);
     if (lds <= kQrLds - 4096)
         return launch_qr_l<true>(Y, (int)m, n, ldy, Qpad, ldq, Qout, sp, status, lds, s);
+    if (work != nullptr) {
+        switch (np >> 4) {
+            case 1: return launch_tqr_t<1>(Y, (int)m, n, ldy, Qpad, ldq, Qout, final_basis, status, work, s);
+            case 2: return launch_tqr_t<2>(Y, (int)m, n, ldy, Qpad, ldq, Qout, final_basis, status, work, s);
+            case 3: return launch_tqr_t<3>(Y, (int)m, n, ldy, Qpad, ldq, Qout, final_basis, status, work, s);
+            default: return launch_tqr_t<4>(Y, (int)m, n, ldy, Qpad, ldq, Qout, final_basis, status, work, s);
+        }
+    }
     const size_t small = (2 * (size_t)np * np + 2 * kQrScratch) * sizeof(double);
     return launch_qr_l<false>(Y, (int)m, n, ldy, Qpad, ldq, Qout, sp, status, small, s);
 }

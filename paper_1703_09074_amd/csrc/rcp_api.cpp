@@ -346,7 +346,8 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
     const bool fused = power_fused_fits(I, l, pl->smem_limit);
     for (int it = 0; it < pl->prob.q; ++it) {
         RCP_TRY(timed(pl, RCP_KERNEL_QR, qr_bytes, 2.0 * qr_flops,
-                      [&] { return launch_qr(Y, I, l, LP, Qt, LP, nullptr, false, pl->status_word(), pl->stream); }));
+                      [&] { return launch_qr(Y, I, l, LP, Qt, LP, nullptr, false, pl->status_word(), pl->stream,
+                                             pl->at<double>(pl->L.red1)); }));
         if (fused) {
             RCP_TRY(timed(pl, RCP_KERNEL_POWER, 4.0 * S + 4.0 * I * l, 4.0 * S * l,
                           [&] { return launch_power_fused(g, l, Qt, part, P, pl->stream, pl->prob.precision); }));
@@ -363,7 +364,8 @@ rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int m
         if (st != RCP_OK) return st;
     }
     RCP_TRY(timed(pl, RCP_KERNEL_QR, qr_bytes, 3.0 * qr_flops,
-                  [&] { return launch_qr(Y, I, l, LP, Qt, LP, Q, true, pl->status_word(), pl->stream); }));
+                  [&] { return launch_qr(Y, I, l, LP, Qt, LP, Q, true, pl->status_word(), pl->stream,
+                                         pl->at<double>(pl->L.red1)); }));
     return RCP_OK;
 }
 

@@ -156,8 +156,11 @@ constexpr uint32_t omega_stream_tag(uint32_t batch, uint32_t mode) { return (bat
 // float32 into Qpad (m x ldq, columns >= n zeroed) and, if non-null, into
 // Qout (m x n).  status (device, may be null): RCP_INFO_QR_HOUSEHOLDER is
 // or-ed in when the Householder fallback runs.
+// work: device scratch of qr_tall_work_doubles(m, n) doubles for bases too
+// tall for one workgroup's LDS (the row-block form); null: one workgroup
 hipError_t launch_qr(double* Y, int64_t m, int n, int ldy, float* Qpad, int ldq, float* Qout,
-                     bool final_basis, int* status, hipStream_t s);
+                     bool final_basis, int* status, hipStream_t s, double* work = nullptr);
+size_t qr_tall_work_doubles(int64_t m, int n);
 
 // CP-ALS on the core (als_kernel.hip)
 struct AlsArgs {

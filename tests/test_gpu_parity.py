@@ -80,6 +80,8 @@ SKETCH_CASES = [
     ((16, 16, 16), 1, 10, 10, 1),      # l = I: square basis
     ((600, 20, 9), 0, 8, 8, 1),        # I > 512: two row blocks, two-pass power step
     ((3, 530, 70), 1, 3, 9, 2),        # tall middle mode: 3 a-slabs, unaligned rows
+    ((1500, 30, 20), 0, 6, 4, 2),      # basis too tall for one workgroup's LDS: row-block QR
+    ((1300, 50, 40), 0, 20, 20, 1),    # the same with 40 columns (the 1024-thread Cholesky)
 ]
 
 
@@ -374,6 +376,29 @@ def test_decompose_noise_free_rank_deficient_sketch():
     assert e < 1e-5
     cong = evaluate.congruence([_np(a) for a in A], w.factors)[0]
     assert cong > 0.99999
+
+
+def test_tall_rank_deficient_sketch():
+    """A rank-2 noise-free tensor with a 1200-row mode sketched 10 wide (the
+    row-block QR): an orthonormal basis whose span holds the mode's range."""
+    w = synth.low_rank((1200, 20, 16), 2, 0.0, 43)
+    plan = rcpgpu.Plan((1200, 20, 16), 4, 6, 1, 5, 0.0, 3)
+    Q = _np(plan.sketch(_dev(w.X), 0))
+    np.testing.assert_allclose(Q.T @ Q, np.eye(Q.shape[1]), atol=1e-5)
+    X0 = rcp.unfold(w.X.astype(np.float64), 0)
+    resid = np.linalg.norm(X0 - Q @ (Q.T @ X0)) / np.linalg.norm(X0)
+    assert resid < 1e-5, resid
+
+
+def test_tall_zero_sketch_falls_back_to_householder():
+    """An all-zero tensor with a 1200-row mode: every Cholesky pivot of the
+    row-block QR is zero, the one-workgroup Householder fallback runs on the
+    (unchanged) sketch and returns an orthonormal basis, raising its bit."""
+    plan = rcpgpu.Plan((1200, 20, 16), 4, 6, 1, 5, 0.0, 3)
+    assert plan.read_status() == 0
+    Q = _np(plan.sketch(_dev(np.zeros((1200, 20, 16))), 0))
+    np.testing.assert_allclose(Q.T @ Q, np.eye(Q.shape[1]), atol=1e-6)
+    assert plan.read_status() & rcpgpu._lib.RCP_INFO_QR_HOUSEHOLDER
 
 
 def test_decompose_rcp400_full_size():
