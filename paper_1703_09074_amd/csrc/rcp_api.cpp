@@ -38,7 +38,7 @@ struct Layout {
     // factors, sweep state, the subspace-iteration tensor of the start
     size_t cfac, cst, cpb;
     size_t part, red1, y64, qt, sq, norm, status, colidx, qb[RCP_MAX_NDIM], tb[2], zbuf, als, alsst,
-        at[RCP_MAX_NDIM], lam, raw, egram, total;
+        at[RCP_MAX_NDIM], lam, raw, estats, egram, total;
     int egram_stride;      // doubles per mode of egram
     size_t part_elems, tb_elems[2], zbuf_elems, als_doubles;
     int64_t core_dims[RCP_MAX_NDIM];
@@ -169,6 +169,7 @@ Layout make_layout(const rcp_problem* p) {
     size_t raw = 0;
     for (int n = 0; n < L.N; ++n) raw += (size_t)L.dims[n] * L.R;
     L.raw = take(raw * sizeof(double));
+    L.estats = take((size_t)(2 * L.N * L.R + L.R) * sizeof(double));
     // the eigenvector start of a core larger than LDS: the Grams of modes
     // 1..N-1 side by side
     L.egram_stride = 0;
@@ -536,6 +537,7 @@ rcp_status expand_impl(rcp_plan_t* pl, const float* const* Q, const float* const
     e.lambda_in = lam_in;
     e.lambda_out = lam_out;
     e.raw = pl->at<double>(L.raw);
+    e.stats = pl->at<double>(L.estats);
     double flops = 0.0, bytes = 0.0;
     for (int n = 0; n < L.N; ++n) {
         flops += 2.0 * (double)L.dims[n] * L.l[n] * L.R;
@@ -854,6 +856,7 @@ ExpandArgs core_expand_args(rcp_plan_t* plan, float* const* A, float* lambda) {
     e.lambda_in = plan->at<float>(L.lam);
     e.lambda_out = lambda;
     e.raw = plan->at<double>(L.raw);
+    e.stats = plan->at<double>(L.estats);
     return e;
 }
 
@@ -1000,6 +1003,7 @@ rcp_status cp_als_impl(rcp_plan_t* pl, const float* X, const float* const* A_ini
     e.lambda_in = pl->at<float>(L.lam);
     e.lambda_out = lambda;
     e.raw = raw;
+    e.stats = pl->at<double>(L.estats);
     RCP_TRY(timed(pl, RCP_KERNEL_EXPAND, 0.0, 0.0, [&] { return launch_expand_finish(e, pl->stream); }));
     return RCP_OK;
 }

@@ -253,6 +253,7 @@ struct ExpandArgs {
     float* A[RCP_MAX_NDIM];
     float* lambda_out;
     double* raw;               // scratch: sum_n I_n x R
+    double* stats;             // scratch: column norms, signs (N x R each), ranks (R)
 };
 hipError_t launch_expand(const ExpandArgs& a, hipStream_t s);
 // the final step alone on factors already in a.raw (Q_n = I): renormalise,
