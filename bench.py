@@ -47,7 +47,7 @@ ROOFLINES = {
     "power": ("hbm", PEAK_HBM_GBS, "GB/s", "bytes", "k_power_fused", None),
     "contract_in": ("hbm", PEAK_HBM_GBS, "GB/s", "bytes", "k_power_fused (resident-Q mode product)", None),
     "contract_out": ("hbm", PEAK_HBM_GBS, "GB/s", "bytes", "k_contract_out", None),
-    "reduce": ("hbm", PEAK_HBM_GBS, "GB/s", "bytes", "k_reduce_stage1/2", None),
+    "reduce": ("hbm", PEAK_HBM_GBS, "GB/s", "bytes", "k_reduce", None),
     "qr": ("mfma", PEAK_FP64_MFMA_TFLOPS, "TFLOP/s", "flops", "k_qr", 1),
     "als": ("mfma", PEAK_FP32_MFMA_TFLOPS, "TFLOP/s", "flops", "k_als", 1),
     "expand": ("hbm", PEAK_HBM_GBS, "GB/s", "bytes", "k_expand_raw/finish", None),

@@ -292,9 +292,8 @@ rcp_status reduce_y(rcp_plan_t* pl, int P, int64_t I, int LP, const double* sq, 
                     double* sq_out) {
     const double bytes = (double)P * I * LP * 4.0 + (double)I * LP * 8.0;
     RCP_TRY(timed(pl, RCP_KERNEL_REDUCE, bytes, (double)P * I * LP, [&] {
-        return launch_reduce_partials(pl->at<float>(pl->L.part), P, I * LP,
-                                      pl->at<double>(pl->L.red1), pl->at<double>(pl->L.y64), sq,
-                                      nsq, sq_out, pl->stream);
+        return launch_reduce_partials(pl->at<float>(pl->L.part), P, I * LP, pl->at<double>(pl->L.y64),
+                                      sq, nsq, sq_out, pl->stream);
     }));
     return RCP_OK;
 }
@@ -428,7 +427,7 @@ hipError_t als_wide(rcp_plan_t* pl, AlsArgs a) {
             hipError_t e = launch_eye(eye, L.l[n], LPn, pl->stream);
             if (e == hipSuccess) e = launch_power_fused(g, L.l[n], eye, part, P, pl->stream, RCP_PREC_FP32);
             if (e == hipSuccess)
-                e = launch_reduce_partials(part, P, (int64_t)L.l[n] * LPn, red1,
+                e = launch_reduce_partials(part, P, (int64_t)L.l[n] * LPn,
                                            eg + (size_t)(n - 1) * L.egram_stride, nullptr, 0,
                                            nullptr, pl->stream);
             if (e != hipSuccess) return e;
@@ -450,7 +449,7 @@ hipError_t als_wide(rcp_plan_t* pl, AlsArgs a) {
             const KrSpec kr = kr_spec(N, n, L.l, R, facs, (const int*)state);
             hipError_t e = launch_mttkrp(g, kr, part, P, pl->stream);
             if (e == hipSuccess)
-                e = launch_reduce_partials(part, P, (int64_t)L.l[n] * LPR, red1, Y, nullptr, 0,
+                e = launch_reduce_partials(part, P, (int64_t)L.l[n] * LPR, Y, nullptr, 0,
                                            nullptr, pl->stream);
             if (e == hipSuccess) e = launch_als_wide_step(a, n, pl->stream);
             if (e != hipSuccess) return e;
@@ -934,7 +933,7 @@ rcp_status cp_als_impl(rcp_plan_t* pl, const float* X, const float* const* A_ini
             float* eye = pl->at<float>(L.qt);
             RCP_TRY(launch_eye(eye, L.l[n], LPn, pl->stream));
             RCP_TRY(launch_power_fused(g, L.l[n], eye, part, P, pl->stream, RCP_PREC_FP32));
-            RCP_TRY(launch_reduce_partials(part, P, (int64_t)L.l[n] * LPn, pl->at<double>(L.red1),
+            RCP_TRY(launch_reduce_partials(part, P, (int64_t)L.l[n] * LPn,
                                            eg + (size_t)(n - 1) * L.egram_stride, nullptr, 0,
                                            nullptr, pl->stream));
         }
@@ -978,9 +977,8 @@ rcp_status cp_als_impl(rcp_plan_t* pl, const float* X, const float* const* A_ini
                           [&] { return launch_mttkrp_full(g, kr, part, P, pl->stream); }));
             RCP_TRY(timed(pl, RCP_KERNEL_REDUCE, (double)P * g.I * LPR * 4.0 + (double)g.I * LPR * 8.0,
                           (double)P * g.I * LPR, [&] {
-                              return launch_reduce_partials(part, P, g.I * LPR, pl->at<double>(L.red1),
-                                                            pl->at<double>(L.y64), nullptr, 0, nullptr,
-                                                            pl->stream);
+                              return launch_reduce_partials(part, P, g.I * LPR, pl->at<double>(L.y64),
+                                                            nullptr, 0, nullptr, pl->stream);
                           }));
             CpArgs u = c;
             u.n = n;
@@ -1131,8 +1129,7 @@ struct GOp {
     size_t lds = 0;                       // QR: the group's largest dynamic LDS
     int count = 0;                        // descriptors
     size_t off = 0;                       // their byte offset in the tables
-    int gx = 1, gy = 1;                   // grid maxima
-    int64_t max_count = 0;                // reductions: largest element count
+    int gx = 1, gy = 1;                   // grid maxima (reductions: gx = total workgroups)
 };
 
 struct rcp_batch_t {
@@ -1320,7 +1317,7 @@ rcp_status batch_bind_outputs(rcp_batch_t* b, float* const* const* A, float* con
 extern "C++" {
 template <typename D>
 struct GStep {
-    struct Item { int NB, MB, prec; bool caseB, fused; size_t lds; D d; int gx, gy; int64_t cnt; };
+    struct Item { int NB, MB, prec; bool caseB, fused; size_t lds; D d; int gx, gy; };
     std::vector<Item> items;
 };
 
@@ -1346,7 +1343,6 @@ void gstep_emit(GStep<D>& st, GOp::Kind kind, std::vector<GOp>& ops, std::vector
             op.gx = std::max(op.gx, c.gx);
             op.gy = std::max(op.gy, c.gy);
             op.lds = std::max(op.lds, c.lds);
-            op.max_count = std::max(op.max_count, c.cnt);
         }
         ops.push_back(op);
     }
@@ -1403,10 +1399,9 @@ void batch_build_program(rcp_batch_t* b, const float* const* X, std::vector<unsi
             d.l = m.l;
             d.P = m.P;
             d.nIB = nIB;
-            sk.items.push_back({m.NB, MBv, pl->prob.precision, m.g.caseB != 0, false, 0, d, m.P, nIB, 0});
+            sk.items.push_back({m.NB, MBv, pl->prob.precision, m.g.caseB != 0, false, 0, d, m.P, nIB});
             ReduceDesc r{};
             r.part = pl->at<float>(L.part);
-            r.red1 = pl->at<double>(L.red1);
             r.Y = pl->at<double>(L.y64);
             r.sq_part = d.sq_part;
             r.sq_out = (n == 0) ? pl->at<double>(L.norm) : nullptr;
@@ -1414,7 +1409,7 @@ void batch_build_program(rcp_batch_t* b, const float* const* X, std::vector<unsi
             r.P = m.P;
             r.ny = reduce_split(m.P);
             r.nsq = m.P * nIB;
-            rd.items.push_back({0, 0, 0, false, false, 0, r, 1, r.ny, r.count});
+            rd.items.push_back({0, 0, 0, false, false, 0, r, 1, 1});
         }
         gstep_emit(sk, GOp::SKETCH, b->ops, blob);
         gstep_emit(rd, GOp::REDUCE, b->ops, blob);
@@ -1432,7 +1427,7 @@ void batch_build_program(rcp_batch_t* b, const float* const* X, std::vector<unsi
             d.Qout = final_basis ? pl->at<float>(L.qb[n]) : nullptr;
             d.second_pass = final_basis ? 1 : 0;
             d.status = pl->status_word();
-            qr.items.push_back({(m.l + 15) >> 4, 0, 0, false, false, qr_group_lds(d.m, d.n), d, 1, 1, 0});
+            qr.items.push_back({(m.l + 15) >> 4, 0, 0, false, false, qr_group_lds(d.m, d.n), d, 1, 1});
         };
         for (int it = 0; it < qmax; ++it) {
             for (int i = 0; i < count; ++i) {
@@ -1447,15 +1442,14 @@ void batch_build_program(rcp_batch_t* b, const float* const* X, std::vector<unsi
                 d.out = nullptr;
                 d.P = m.P;
                 pw.items.push_back({m.NB, (int)((cur[i][n] + 63) / 64), pl->prob.precision,
-                                    m.g.caseB != 0, true, 0, d, m.P, 1, 0});
+                                    m.g.caseB != 0, true, 0, d, m.P, 1});
                 ReduceDesc r{};
                 r.part = pl->at<float>(pl->L.part);
-                r.red1 = pl->at<double>(pl->L.red1);
                 r.Y = pl->at<double>(pl->L.y64);
                 r.count = cur[i][n] * m.LP;
                 r.P = m.P;
                 r.ny = reduce_split(m.P);
-                rd.items.push_back({0, 0, 0, false, false, 0, r, 1, r.ny, r.count});
+                rd.items.push_back({0, 0, 0, false, false, 0, r, 1, 1});
             }
             gstep_emit(qr, GOp::QR, b->ops, blob);
             gstep_emit(pw, GOp::POWER, b->ops, blob);
@@ -1479,12 +1473,26 @@ void batch_build_program(rcp_batch_t* b, const float* const* X, std::vector<unsi
             d.P = m.P;
             d.lout = m.l;
             pw.items.push_back({m.NB, (int)((cur[i][n] + 63) / 64), RCP_PREC_FP32, m.g.caseB != 0, false,
-                                0, d, m.P, 1, 0});
+                                0, d, m.P, 1});
             cur[i][n] = m.l;
             T[i] = out;
             ++comp[i];
         }
         gstep_emit(pw, GOp::POWER, b->ops, blob);
+    }
+    // the grouped reductions number their problems' workgroups consecutively
+    for (GOp& op : b->ops) {
+        if (op.kind != GOp::REDUCE) continue;
+        int64_t blocks = 0;
+        for (int i = 0; i < op.count; ++i) {
+            unsigned char* at = blob.data() + op.off + (size_t)i * sizeof(ReduceDesc);
+            ReduceDesc r;
+            std::memcpy(&r, at, sizeof r);
+            r.blk0 = (int)blocks;
+            blocks += reduce_blocks(r.count);
+            std::memcpy(at, &r, sizeof r);
+        }
+        op.gx = (int)blocks;
     }
 }
 
@@ -1497,7 +1505,7 @@ rcp_status batch_enqueue_grouped(rcp_batch_t* b) {
                                             op.caseB, false, op.prec, b->stream));
                 break;
             case GOp::REDUCE:
-                RCP_TRY(launch_reduce_group((const ReduceDesc*)d, op.count, op.max_count, op.gy,
+                RCP_TRY(launch_reduce_group((const ReduceDesc*)d, op.count, op.gx,
                                             b->stream));
                 break;
             case GOp::QR:

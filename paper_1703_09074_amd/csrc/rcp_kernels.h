@@ -46,14 +46,14 @@ struct PowerDesc {             // k_power_fused (fused power step or mode produc
     float* out;
     int P, lout, accumulate, pad_;
 };
-struct ReduceDesc {            // k_reduce_stage1/2
+struct ReduceDesc {            // k_reduce_grp
     const float* part;
-    double* red1;
     double* Y;
     const double* sq_part;
     double* sq_out;
     int64_t count;
-    int P, ny, nsq, pad_;
+    int P, ny, nsq;
+    int blk0;                  // grouped launch: the problem's first workgroup
 };
 struct QrDesc {                // k_qr
     double* Y;
@@ -68,8 +68,8 @@ hipError_t launch_sketch_group(const SketchDesc* d, int count, int gx, int gy, i
                                bool caseB, bool stored, int precision, hipStream_t s);
 hipError_t launch_power_group(const PowerDesc* d, int count, int gx, int NB, int MB, bool fused,
                               bool caseB, int precision, hipStream_t s);
-hipError_t launch_reduce_group(const ReduceDesc* d, int count, int64_t max_count, int max_ny,
-                               hipStream_t s);
+// blocks = the sum of reduce_blocks(d[i].count), d[i].blk0 the running sum
+hipError_t launch_reduce_group(const ReduceDesc* d, int count, int64_t blocks, hipStream_t s);
 hipError_t launch_qr_group(const QrDesc* d, int count, int NB, bool use_lds, size_t lds,
                            hipStream_t s);
 size_t qr_group_lds(int64_t m, int n);
@@ -129,9 +129,11 @@ hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
 // Qpad (I x ldq) <- the identity padded with zero columns
 hipError_t launch_eye(float* Qpad, int64_t I, int ldq, hipStream_t s);
 int reduce_split(int P);
-hipError_t launch_reduce_partials(const float* part, int P, int64_t count, double* red1,
-                                  double* Y, const double* sq_part, int nsq, double* sq_out,
-                                  hipStream_t s);
+int64_t reduce_blocks(int64_t count);
+// Y[e] = sum over the P partials (rows of count floats) in float64, in a fixed
+// order; optionally *sq_out = the sum of the nsq sum-of-squares partials
+hipError_t launch_reduce_partials(const float* part, int P, int64_t count, double* Y,
+                                  const double* sq_part, int nsq, double* sq_out, hipStream_t s);
 hipError_t launch_sumsq(const float* x, int64_t count, double* part, int nblocks, double* out,
                         hipStream_t s);
 hipError_t launch_omega(uint64_t seed, uint32_t tag, int okind, int64_t row0, int64_t nrows,

@@ -8,67 +8,63 @@
 namespace rcp {
 
 // ---------------------------------------------------------------------------
-// Deterministic reduction of the per-workgroup partials, in two stages so
-// that enough workgroups stream the partial buffer:
-//   stage 1: red1[y, e] = sum_{p in split y} part[p, e]        (float64)
-//   stage 2: Y[e] = sum_y red1[y, e]
-// Block 0 of stage 2 also sums the optional sum-of-squares partials.
+// Deterministic reduction of the per-workgroup partials in one launch.  The
+// partials are cut into ny = min(P, 16) consecutive groups; a workgroup
+// takes 64 consecutive elements, wavefront y sums group y's partials of its
+// element in partial order (float64, from 0), and the group sums are added
+// in group order:  Y[e] = sum_y (sum_{p in group y} part[p, e]).
+// Workgroup 0 of a reduction also sums the optional sum-of-squares partials.
 
 constexpr int kRedSplit = 16;
+constexpr int kRedCols = 64;                  // elements per workgroup
+constexpr int kRedThreads = 64 * kRedSplit;   // one wavefront per group
 
-__global__ __launch_bounds__(NT) void k_reduce_stage1(const float* part, int P, int64_t count,
-                                                      double* red1) {
-    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (e >= count) return;
-    const int y = blockIdx.y, ny = gridDim.y;
-    const int p0 = (int)((int64_t)P * y / ny), p1 = (int)((int64_t)P * (y + 1) / ny);
+__device__ __forceinline__ void reduce_body(const float* part, int P, int ny, int64_t count,
+                                            int64_t blk, double* Y, const double* sq_part, int nsq,
+                                            double* sq_out) {
+    __shared__ double gs[kRedSplit][kRedCols];
+    const int c = threadIdx.x & 63, y = threadIdx.x >> 6;
+    const int64_t e = blk * kRedCols + c;
     double s = 0.0;
-    for (int p = p0; p < p1; ++p) s += (double)part[(int64_t)p * count + e];
-    red1[(int64_t)y * count + e] = s;
+    if (y < ny && e < count) {
+        const int p0 = (int)((int64_t)P * y / ny), p1 = (int)((int64_t)P * (y + 1) / ny);
+        const float* src = part + e;
+#pragma unroll 4
+        for (int p = p0; p < p1; ++p) s += (double)src[(int64_t)p * count];
+    }
+    gs[y][c] = s;
+    __syncthreads();
+    if (y == 0 && e < count) {
+        double t = 0.0;
+        for (int g = 0; g < ny; ++g) t += gs[g][c];
+        Y[e] = t;
+    }
+    if (sq_part != nullptr && blk == 0 && threadIdx.x == 0) {
+        double t = 0.0;
+        for (int p = 0; p < nsq; ++p) t += sq_part[p];
+        *sq_out = t;
+    }
 }
 
-__global__ __launch_bounds__(NT) void k_reduce_stage2(const double* red1, int ny, int64_t count,
-                                                      double* Y, const double* sq_part, int nsq,
-                                                      double* sq_out) {
-    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (e < count) {
-        double s = 0.0;
-        for (int y = 0; y < ny; ++y) s += red1[(int64_t)y * count + e];
-        Y[e] = s;
-    }
-    if (sq_part != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
-        double s = 0.0;
-        for (int p = 0; p < nsq; ++p) s += sq_part[p];
-        *sq_out = s;
-    }
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const float* part, int P, int64_t count,
+                                                        double* Y, const double* sq_part, int nsq,
+                                                        double* sq_out) {
+    reduce_body(part, P, P < kRedSplit ? P : kRedSplit, count, blockIdx.x, Y, sq_part, nsq, sq_out);
 }
 
-// Grouped reductions: blockIdx.z picks the problem; each keeps its own split
-// (ny) and element count, so its sums are those of launch_reduce_partials.
-__global__ __launch_bounds__(NT) void k_reduce_stage1_grp(const ReduceDesc* d) {
-    const ReduceDesc& D = d[blockIdx.z];
-    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (e >= D.count || (int)blockIdx.y >= D.ny) return;
-    const int y = blockIdx.y, ny = D.ny, P = D.P;
-    const int p0 = (int)((int64_t)P * y / ny), p1 = (int)((int64_t)P * (y + 1) / ny);
-    double s = 0.0;
-    for (int p = p0; p < p1; ++p) s += (double)D.part[(int64_t)p * D.count + e];
-    D.red1[(int64_t)y * D.count + e] = s;
-}
-
-__global__ __launch_bounds__(NT) void k_reduce_stage2_grp(const ReduceDesc* d) {
-    const ReduceDesc& D = d[blockIdx.z];
-    const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (e < D.count) {
-        double s = 0.0;
-        for (int y = 0; y < D.ny; ++y) s += D.red1[(int64_t)y * D.count + e];
-        D.Y[e] = s;
+// Grouped form: the problems' workgroups are numbered consecutively
+// (d[i].blk0 is problem i's first), so the grid holds only real work; a
+// workgroup finds its problem by binary search over blk0.
+__global__ __launch_bounds__(kRedThreads) void k_reduce_grp(const ReduceDesc* d, int count) {
+    const int bx = (int)blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].blk0 <= bx) lo = mid;
+        else hi = mid - 1;
     }
-    if (D.sq_part != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
-        double s = 0.0;
-        for (int p = 0; p < D.nsq; ++p) s += D.sq_part[p];
-        *D.sq_out = s;
-    }
+    const ReduceDesc& D = d[lo];
+    reduce_body(D.part, D.P, D.ny, D.count, bx - D.blk0, D.Y, D.sq_part, D.nsq, D.sq_out);
 }
 
 // Sum of squares of count floats: per-block float64 partials.
@@ -289,30 +285,19 @@ hipError_t launch_contract_in(const StreamGeom& g, int l, const float* Qpadded, 
 
 int reduce_split(int P) { return P < kRedSplit ? P : kRedSplit; }
 
-hipError_t launch_reduce_partials(const float* part, int P, int64_t count, double* red1,
-                                  double* Y, const double* sq_part, int nsq, double* sq_out,
-                                  hipStream_t s) {
-    const unsigned blocks = (unsigned)((count + NT - 1) / NT);
-    const int ny = reduce_split(P);
-    hipLaunchKernelGGL(k_reduce_stage1, dim3(blocks > 0 ? blocks : 1, (unsigned)ny), dim3(NT), 0, s,
-                       part, P, count, red1);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_stage2, dim3(blocks > 0 ? blocks : 1), dim3(NT), 0, s, red1, ny,
-                       count, Y, sq_part, nsq, sq_out);
+int64_t reduce_blocks(int64_t count) { return (count + kRedCols - 1) / kRedCols; }
+
+hipError_t launch_reduce_partials(const float* part, int P, int64_t count, double* Y,
+                                  const double* sq_part, int nsq, double* sq_out, hipStream_t s) {
+    const int64_t blocks = reduce_blocks(count);
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(kRedThreads), 0, s,
+                       part, P, count, Y, sq_part, nsq, sq_out);
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_group(const ReduceDesc* d, int count, int64_t max_count, int max_ny,
-                               hipStream_t s) {
-    if (count < 1) return hipSuccess;
-    const unsigned blocks = (unsigned)((max_count + NT - 1) / NT);
-    hipLaunchKernelGGL(k_reduce_stage1_grp, dim3(blocks > 0 ? blocks : 1, (unsigned)max_ny, (unsigned)count),
-                       dim3(NT), 0, s, d);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce_stage2_grp, dim3(blocks > 0 ? blocks : 1, 1, (unsigned)count), dim3(NT),
-                       0, s, d);
+hipError_t launch_reduce_group(const ReduceDesc* d, int count, int64_t blocks, hipStream_t s) {
+    if (count < 1 || blocks < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_grp, dim3((unsigned)blocks), dim3(kRedThreads), 0, s, d, count);
     return hipGetLastError();
 }
 
