@@ -251,7 +251,7 @@ hipError_t launch_pad_q(const float* Q, int64_t I, int l, float* Qpad, int ldq, 
 int contract_out_row_blocks(int64_t I, int mb_cap) {
     int MBv = (int)((I + 63) / 64);
     if (I <= 512 && MBv > mb_cap) MBv = mb_cap;
-    if (MBv > 8) MBv = 8;
+    if (I > 512) MBv = kTallMB;
     if (MBv < 1) MBv = 1;
     const int IB = 64 * MBv;
     return (int)((I + IB - 1) / IB);

@@ -35,6 +35,13 @@ constexpr int TS = JT + 4;        // LDS row stride of a tile (16-byte aligned r
 constexpr int NT = 256;           // threads per workgroup of the small kernels
 constexpr int NTS = 512;          // threads per workgroup of the streaming kernels (8 wavefronts)
 constexpr int NWS = NTS / 64;
+// Row-block height (64-row units) of the sketch and stored-Z passes on
+// modes taller than 512 rows: 256 rows keep two workgroups resident per CU
+// (124 VGPRs, 45 KB of LDS), so one workgroup's barriers, test-matrix
+// generation and tile commits overlap the other's matrix-core work; 512-row
+// blocks (195 VGPRs, one workgroup per CU) were 8-24% slower on
+// 2048x2048x512.
+constexpr int kTallMB = 4;
 
 struct TileInfo {
     int64_t j0;      // first unfolding column of the tile
@@ -850,7 +857,7 @@ hipError_t launch_contract_out_t(const StreamGeom& g, int l, const float* Z, uin
     const int NBv = lp_blocks(l);
     int MBv = (int)((g.I + 63) / 64);
     if (g.I <= 512 && MBv > mb_cap) MBv = mb_cap;    // the cap applies to short modes only
-    if (MBv > 8) MBv = 8;
+    if (g.I > 512) MBv = kTallMB;
     if (MBv < 1) MBv = 1;
     const int IB = 64 * MBv;
     const unsigned nIB = (unsigned)((g.I + IB - 1) / IB);
