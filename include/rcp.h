@@ -416,7 +416,8 @@ rcp_status rcp_batch_autotune(rcp_batch batch, const float* const* X, float* con
                               double* best_ms);
 rcp_status rcp_batch_destroy(rcp_batch batch);
 
-/* Static description of a status code. */
+/* Static description of a status code; any other int value gives
+ * "unknown rcp_status". */
 const char* rcp_status_string(rcp_status status);
 
 /* Library version string. */

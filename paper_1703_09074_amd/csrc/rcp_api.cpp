@@ -551,7 +551,12 @@ rcp_status expand_impl(rcp_plan_t* pl, const float* const* Q, const float* const
 extern "C" {
 
 const char* rcp_status_string(rcp_status s) {
-    switch (s) {
+    // a C caller may pass any int: read it as one (an rcp_status holding a
+    // value outside the enumerators is not a valid C++ enum value)
+    int v;
+    static_assert(sizeof v == sizeof s, "rcp_status is int-sized");
+    std::memcpy(&v, &s, sizeof v);
+    switch (v) {
         case RCP_OK: return "RCP_OK: success";
         case RCP_ERR_INVALID_ARG: return "RCP_ERR_INVALID_ARG: invalid argument";
         case RCP_ERR_WORKSPACE: return "RCP_ERR_WORKSPACE: workspace missing or too small";

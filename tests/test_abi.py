@@ -18,7 +18,8 @@ from paper_1703_09074_amd import _lib  # noqa: E402
 
 @pytest.fixture(scope="module")
 def lib():
-    return _lib.load()
+    # RCP_TEST_LIBRARY: another build of the same sources (the sanitized one)
+    return _lib.load(os.environ.get("RCP_TEST_LIBRARY", _lib.LIB_PATH))
 
 
 def _declared_functions():
