@@ -262,49 +262,62 @@ __device__ __forceinline__ void gram_mfma(const float* F, int ln, int R, double*
 // Gauss-Jordan solves of the symmetric positive definite systems V X = Y of
 // the least-squares updates.
 
-// Inverse of the pivot block P = A[0..pbs) x [0..pbs) (row stride lda; a
-// 16 x 16 block padded with the identity past pbs) in one wavefront's
-// registers: Gauss-Jordan on [P | I] with lane c holding column c (lanes
-// 0..15 P, 16..31 I) and the rows rotating through the registers so that the
-// pivot row is always register 0; the pivot column is read into scalar
-// registers before each step's updates.  P^{-1} goes to Pinv (16 x 16).
+// Inverse of the pivot block P = A[0..NP) x [0..NP) (row stride lda; NP a
+// multiple of 4, at most 16) in one wavefront's registers: Gauss-Jordan on
+// [P | I] with lane c holding column c (lanes 0..NP-1 P, 16..16+NP-1 I) and
+// the rows rotating through the registers so that the pivot row is always
+// register 0; the pivot column is read into scalar registers before each
+// step's updates.  P^{-1} goes to Pinv (16 x 16, zero outside NP x NP): NP
+// steps, so a short last block of the system costs only its own rows.
 // Returns 0 if a pivot of the first rreal rows is not above thr (or is NaN).
-__device__ __forceinline__ int invert16_wave(const double* A, int lda, int pbs, int rreal, double thr,
-                                             double* Pinv) {
+template <int NP>
+__device__ __forceinline__ int invert_wave(const double* A, int lda, int rreal, double thr,
+                                           double* Pinv) {
     const int c = threadIdx.x & 63;
-    double col[16];
+    double col[NP];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < NP; ++i) {
         double v = 0.0;
-        if (c < 16) v = (i < pbs && c < pbs) ? A[i * lda + c] : ((i == c) ? 1.0 : 0.0);
-        else if (c < 32) v = (c - 16 == i) ? 1.0 : 0.0;
+        if (c < NP) v = A[i * lda + c];
+        else if (c >= 16 && c < 16 + NP) v = (c - 16 == i) ? 1.0 : 0.0;
         col[i] = v;
     }
     double pmin = __builtin_huge_val();
     bool pnan = false;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        double sk[16];
+    for (int k = 0; k < NP; ++k) {
+        double sk[NP];
         sk[0] = readlane_f64(col[0], k);
         const double u = col[0] / sk[0];
 #pragma unroll
-        for (int i = 1; i < 16; ++i) sk[i] = readlane_f64(col[i], k);
+        for (int i = 1; i < NP; ++i) sk[i] = readlane_f64(col[i], k);
         __builtin_amdgcn_sched_barrier(0);
         if (k < rreal) {
             pmin = fmin(pmin, sk[0]);
             pnan = pnan || (sk[0] != sk[0]);
         }
 #pragma unroll
-        for (int i = 1; i < 16; ++i) col[i] -= sk[i] * u;
+        for (int i = 1; i < NP; ++i) col[i] -= sk[i] * u;
 #pragma unroll
-        for (int i = 0; i < 15; ++i) col[i] = col[i + 1];
-        col[15] = u;
+        for (int i = 0; i < NP - 1; ++i) col[i] = col[i + 1];
+        col[NP - 1] = u;
     }
     if (c >= 16 && c < 32) {
+        const bool cin = c - 16 < NP;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) Pinv[i * 16 + (c - 16)] = col[i];
+        for (int i = 0; i < 16; ++i) Pinv[i * 16 + (c - 16)] = (i < NP && cin) ? col[i < NP ? i : 0] : 0.0;
     }
     return (!pnan && (rreal == 0 || pmin > thr)) ? 1 : 0;
+}
+
+__device__ __forceinline__ int invert16_wave(const double* A, int lda, int pbs, int rreal, double thr,
+                                             double* Pinv) {
+    switch (pbs) {
+        case 4: return invert_wave<4>(A, lda, rreal, thr, Pinv);
+        case 8: return invert_wave<8>(A, lda, rreal, thr, Pinv);
+        case 12: return invert_wave<12>(A, lda, rreal, thr, Pinv);
+        default: return invert_wave<16>(A, lda, rreal, thr, Pinv);
+    }
 }
 
 // Blocked Gauss-Jordan elimination without pivoting on the augmented system

@@ -242,20 +242,67 @@ __device__ __forceinline__ void mttkrp(const AlsCtx& c, int n, const float* B, c
 
 // Left block of the augmented system: V = *_{m != n} G_m, identity padding up
 // to Rp, and zero padding rows in the right block.
+// With the Grams in global memory (G_GLOBAL) a thread holds its at most KE
+// entries (Rp <= 64) in registers and issues each Gram's loads together, so
+// a Gram costs one memory latency, not one per entry; with the Grams in LDS
+// the plain loop is faster.  Either way the product runs over m in
+// increasing order.
+constexpr int KE = (RCP_MAX_RANK * RCP_MAX_RANK + ANT - 1) / ANT;
+
+template <bool G_GLOBAL>
 __device__ __forceinline__ void hadamard_grams(const AlsCtx& c, int n, const double* G, double* Aug,
                                                int ldx, int Rp, int ln) {
     const int R = c.R;
-    for (int e = threadIdx.x; e < Rp * Rp; e += ANT) {
-        const int r = e / Rp, s = e - (e / Rp) * Rp;
-        double v;
-        if (r < R && s < R) {
-            v = 1.0;
-            for (int m = 0; m < c.N; ++m)
-                if (m != n) v *= G[m * R * R + r * R + s];
-        } else {
-            v = (r == s) ? 1.0 : 0.0;
+    if constexpr (!G_GLOBAL) {
+        for (int e = threadIdx.x; e < Rp * Rp; e += ANT) {
+            const int r = e / Rp, s = e - (e / Rp) * Rp;
+            double v;
+            if (r < R && s < R) {
+                v = 1.0;
+                for (int m = 0; m < c.N; ++m)
+                    if (m != n) v *= G[m * R * R + r * R + s];
+            } else {
+                v = (r == s) ? 1.0 : 0.0;
+            }
+            Aug[r * ldx + s] = v;
         }
-        Aug[r * ldx + s] = v;
+        for (int e = threadIdx.x; e < (Rp - R) * ln; e += ANT) {
+            const int r = R + e / ln, i = e - (e / ln) * ln;
+            Aug[r * ldx + Rp + i] = 0.0;
+        }
+        return;
+    }
+    double v[KE];
+#pragma unroll
+    for (int k = 0; k < KE; ++k) v[k] = 1.0;
+    // the Grams m != n two at a time (the q-th is q, or q + 1 past n)
+    for (int q = 0; q < c.N - 1; q += 2) {
+        const int ma = q < n ? q : q + 1, mb = q + 1 < n ? q + 1 : q + 2;
+        const bool has_b = q + 1 < c.N - 1;
+        const double* Ga = G + ma * R * R;
+        const double* Gb = G + (has_b ? mb : ma) * R * R;
+        double ga[KE], gb[KE];
+#pragma unroll
+        for (int k = 0; k < KE; ++k) {
+            const int e = threadIdx.x + k * ANT;
+            const int r = e / Rp, s = e - r * Rp;
+            const bool in = e < Rp * Rp && r < R && s < R;
+            ga[k] = in ? Ga[r * R + s] : 1.0;
+            gb[k] = (in && has_b) ? Gb[r * R + s] : 1.0;
+        }
+#pragma unroll
+        for (int k = 0; k < KE; ++k) {
+            v[k] *= ga[k];
+            v[k] *= gb[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KE; ++k) {
+        const int e = threadIdx.x + k * ANT;
+        if (e < Rp * Rp) {
+            const int r = e / Rp, s = e - r * Rp;
+            Aug[r * ldx + s] = (r < R && s < R) ? v[k] : ((r == s) ? 1.0 : 0.0);
+        }
     }
     for (int e = threadIdx.x; e < (Rp - R) * ln; e += ANT) {
         const int r = R + e / ln, i = e - (e / ln) * ln;
@@ -461,7 +508,7 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
     int it;
     for (it = 1; it <= a.max_iters; ++it) {
         for (int n = 0; n < N; ++n) {
-            hadamard_grams(c, n, G, Aug, ldx, Rp, c.l[n]);
+            hadamard_grams<false>(c, n, G, Aug, ldx, Rp, c.l[n]);
             mttkrp<NN>(c, n, Bs, sst, ones, P, pfl, M, Aug + Rp, ldx);
             __syncthreads();
             status |= solve_update(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs,
@@ -622,12 +669,26 @@ __global__ __launch_bounds__(ANT) void k_als_wide_step(AlsArgs a, int n) {
     double* Es = a.Ebuf;
     double* Evs = a.Ebuf + kEigLd * kEigLd;
 
-    hadamard_grams(c, n, G, Aug, ldx, Rp, ln);
-    for (int e = tid; e < ln * R; e += ANT) {
-        const int i = e / R, r = e - (e / R) * R;
-        const double v = a.Y[i * a.ldy + r];
-        M[e] = v;
-        Aug[r * ldx + Rp + i] = v;
+    {
+        // ln * R <= 4096: all of a thread's loads of M in flight at once,
+        // and still in flight while the Grams' are issued
+        double v[KE];
+#pragma unroll
+        for (int k = 0; k < KE; ++k) {
+            const int e = tid + k * ANT;
+            const int i = e / R, r = e - (e / R) * R;
+            v[k] = (e < ln * R) ? a.Y[i * a.ldy + r] : 0.0;
+        }
+        hadamard_grams<true>(c, n, G, Aug, ldx, Rp, ln);
+#pragma unroll
+        for (int k = 0; k < KE; ++k) {
+            const int e = tid + k * ANT;
+            if (e < ln * R) {
+                const int i = e / R, r = e - (e / R) * R;
+                M[e] = v[k];
+                Aug[r * ldx + Rp + i] = v[k];
+            }
+        }
     }
     __syncthreads();
     int status = solve_update(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs, lam);

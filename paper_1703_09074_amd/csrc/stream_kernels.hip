@@ -29,7 +29,7 @@ __device__ __forceinline__ void reduce_body(const float* part, int P, int ny, in
     if (y < ny && e < count) {
         const int p0 = (int)((int64_t)P * y / ny), p1 = (int)((int64_t)P * (y + 1) / ny);
         const float* src = part + e;
-#pragma unroll 4
+#pragma unroll 8
         for (int p = p0; p < p1; ++p) s += (double)src[(int64_t)p * count];
     }
     gs[y][c] = s;

@@ -393,11 +393,24 @@ __device__ __forceinline__ void contract_out_body(const StreamGeom& g, int l, co
         if (kr.skip != nullptr && *kr.skip != 0 && kr.sweep > *kr.skip) return;
     }
     if (WK == kWKr) {
+        // l_m * R <= 4096 floats per factor: a thread's loads of one factor
+        // are issued together (one memory latency per factor)
+        constexpr int KF = (RCP_MAX_L * RCP_MAX_RANK + NTS - 1) / NTS;
 #pragma unroll
         for (int m = 0; m < RCP_MAX_NDIM; ++m) {
             if (m < kr.N && m != kr.n) {
                 const int cnt = kr.l[m] * kr.R;
-                for (int e = threadIdx.x; e < cnt; e += NTS) Fs[kr.foff[m] + e] = kr.fac[m][e];
+                float f[KF];
+#pragma unroll
+                for (int k = 0; k < KF; ++k) {
+                    const int e = threadIdx.x + k * NTS;
+                    f[k] = (e < cnt) ? kr.fac[m][e] : 0.0f;
+                }
+#pragma unroll
+                for (int k = 0; k < KF; ++k) {
+                    const int e = threadIdx.x + k * NTS;
+                    if (e < cnt) Fs[kr.foff[m] + e] = f[k];
+                }
             }
         }
     }
