@@ -262,23 +262,24 @@ __device__ __forceinline__ void gram_mfma(const float* F, int ln, int R, double*
 // Gauss-Jordan solves of the symmetric positive definite systems V X = Y of
 // the least-squares updates.
 
-// Inverse of the pivot block P = A[0..NP) x [0..NP) (row stride lda; NP a
-// multiple of 4, at most 16) in one wavefront's registers: Gauss-Jordan on
-// [P | I] with lane c holding column c (lanes 0..NP-1 P, 16..16+NP-1 I) and
-// the rows rotating through the registers so that the pivot row is always
-// register 0; the pivot column is read into scalar registers before each
-// step's updates.  P^{-1} goes to Pinv (16 x 16, zero outside NP x NP): NP
-// steps, so a short last block of the system costs only its own rows.
-// Returns 0 if a pivot of the first rreal rows is not above thr (or is NaN).
+// Inverse of the pivot block P = A[0..pbs) x [0..pbs) (row stride lda;
+// pbs <= NP <= 16, NP a multiple of 4; P padded with the identity up to NP)
+// in one wavefront's registers: Gauss-Jordan on [P | I] with lane c holding
+// column c (lanes 0..NP-1 P, 16..16+NP-1 I) and the rows rotating through
+// the registers so that the pivot row is always register 0; the pivot
+// column is read into scalar registers before each step's updates.  NP
+// steps: sized to the block, a short last block costs only its own rows.
+// P^{-1} goes to Pinv (16 x 16, identity outside NP x NP).  Returns 0 if a
+// pivot of the first rreal rows is not above thr (or is NaN).
 template <int NP>
-__device__ __forceinline__ int invert_wave(const double* A, int lda, int rreal, double thr,
+__device__ __forceinline__ int invert_wave(const double* A, int lda, int pbs, int rreal, double thr,
                                            double* Pinv) {
     const int c = threadIdx.x & 63;
     double col[NP];
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
         double v = 0.0;
-        if (c < NP) v = A[i * lda + c];
+        if (c < NP) v = (i < pbs && c < pbs) ? A[i * lda + c] : ((i == c) ? 1.0 : 0.0);
         else if (c >= 16 && c < 16 + NP) v = (c - 16 == i) ? 1.0 : 0.0;
         col[i] = v;
     }
@@ -303,36 +304,51 @@ __device__ __forceinline__ int invert_wave(const double* A, int lda, int rreal, 
         col[NP - 1] = u;
     }
     if (c >= 16 && c < 32) {
-        const bool cin = c - 16 < NP;
+        const int cj = c - 16;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) Pinv[i * 16 + (c - 16)] = (i < NP && cin) ? col[i < NP ? i : 0] : 0.0;
+        for (int i = 0; i < 16; ++i)
+            Pinv[i * 16 + cj] = (i < NP && cj < NP) ? col[i < NP ? i : 0] : ((i == cj) ? 1.0 : 0.0);
     }
     return (!pnan && (rreal == 0 || pmin > thr)) ? 1 : 0;
 }
 
+// SIZED: one register inverse per block size (4, 8, 12, 16 rows); else the
+// 16-row one for every block (less code in kernels short of registers).
+template <bool SIZED>
 __device__ __forceinline__ int invert16_wave(const double* A, int lda, int pbs, int rreal, double thr,
                                              double* Pinv) {
-    switch (pbs) {
-        case 4: return invert_wave<4>(A, lda, rreal, thr, Pinv);
-        case 8: return invert_wave<8>(A, lda, rreal, thr, Pinv);
-        case 12: return invert_wave<12>(A, lda, rreal, thr, Pinv);
-        default: return invert_wave<16>(A, lda, rreal, thr, Pinv);
+    if constexpr (SIZED) {
+        switch (pbs) {
+            case 4: return invert_wave<4>(A, lda, pbs, rreal, thr, Pinv);
+            case 8: return invert_wave<8>(A, lda, pbs, rreal, thr, Pinv);
+            case 12: return invert_wave<12>(A, lda, pbs, rreal, thr, Pinv);
+            default: break;
+        }
     }
+    return invert_wave<16>(A, lda, pbs, rreal, thr, Pinv);
 }
 
 // Blocked Gauss-Jordan elimination without pivoting on the augmented system
 // Aug = [V | Xt] (Rp x W, row stride ldx, V symmetric positive definite and
-// padded with the identity up to Rp): on return columns Rp..W-1 hold
-// V^{-1} Xt.  Pivot blocks of up to 16 rows; per block j0 (pbs rows):
+// padded with the identity up to Rp, Rp a multiple of 4): on return columns
+// Rp..W-1 hold V^{-1} Xt.  Pivot blocks of up to 16 rows; per block j0 (pbs
+// rows):
 //   1. wavefront 0 inverts the pivot block P in its registers;
 //   2. the pivot rows become P^{-1} [pivot rows] (float64 matrix cores);
 //   3. every other row block i loses F_i [pivot rows], F_i its entries in the
 //      pivot columns (matrix cores).
-// The pivots of the inverted blocks are the Schur complements, i.e. the
-// pivots of unblocked elimination, and each must exceed rtol times the
-// largest of V's first R diagonal entries for the rows < R.  Columns left of the pivot block are never read again and are not
-// updated; every column block is read whole before it is written, so the
-// updates run in place.  pb holds 258 doubles (P^{-1} and the flag).
+// Step 3 looks ahead: wavefront 0 first updates the next pivot block and
+// inverts it (step 1 of the next block) while the other wavefronts update the
+// rest, so the register inverse, the serial part, overlaps the matrix-core
+// work.  The pivots of the inverted blocks are the Schur complements, i.e.
+// the pivots of unblocked elimination, and each must exceed rtol times the
+// largest of V's first R diagonal entries for the rows < R.  Columns left of
+// the pivot block are never read again and are not updated; every column
+// block is read whole before it is written, so the updates run in place.
+// pb holds 258 doubles (P^{-1} and the flag).  SIZED: the register inverse
+// sized to each block (see invert16_wave) and the lookahead; without it, the
+// 16-row inverse and no lookahead (less code in kernels short of registers).
+template <bool SIZED>
 __device__ __forceinline__ int block16_gj(double* Aug, int ldx, int R, int Rp, int W, double rtol,
                                           double* pb) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -348,15 +364,18 @@ __device__ __forceinline__ int block16_gj(double* Aug, int ldx, int R, int Rp, i
         for (int o = 32; o > 0; o >>= 1) d = fmax(d, __shfl_xor(d, o, 64));
         thr = rtol * d;
     }
+    // step 1 for the block at jb (wavefront 0)
+    auto invert = [&](int jb) {
+        const int pbs = min(16, Rp - jb);
+        const int rreal = max(0, min(pbs, R - jb));
+        const int ok = invert16_wave<SIZED>(Aug + jb * ldx + jb, ldx, pbs, rreal, thr, Pinv);
+        if (lane == 0 && !ok) *okp = 0.0;
+    };
     const int nrb = (Rp + 15) >> 4;
+    if (wave == 0) invert(0);
+    __syncthreads();
     for (int j0 = 0; j0 < Rp; j0 += 16) {
         const int pbs = min(16, Rp - j0);
-        const int rreal = max(0, min(pbs, R - j0));
-        if (wave == 0) {
-            const int ok = invert16_wave(Aug + j0 * ldx + j0, ldx, pbs, rreal, thr, Pinv);
-            if (lane == 0 && !ok) *okp = 0.0;
-        }
-        __syncthreads();
         const int c0 = j0 + pbs;                   // first column to update
         const int ncb = (W - c0 + 15) >> 4;
         // 2. pivot rows <- P^{-1} pivot rows
@@ -380,9 +399,10 @@ __device__ __forceinline__ int block16_gj(double* Aug, int ldx, int R, int Rp, i
             }
         }
         __syncthreads();
-        // 3. other row blocks: A_ic -= F_i [pivot rows]
+        // 3. other row blocks: A_ic -= F_i [pivot rows]; unit u is row block
+        // u / ncb (the pivot block skipped) and column block u % ncb
         const int units = (nrb - 1) * ncb;
-        for (int u = wave; u < units; u += ANW) {
+        auto trail = [&](int u) {
             int rb = u / ncb;
             const int cb = u - rb * ncb;
             if (rb >= (j0 >> 4)) ++rb;            // skip the pivot block
@@ -410,6 +430,21 @@ __device__ __forceinline__ int block16_gj(double* Aug, int ldx, int R, int Rp, i
                 const int ri = i0 + lk + 4 * v;
                 if (ri < Rp && cv) Aug[ri * ldx + cc] = acc[v];
             }
+        };
+        if (SIZED && c0 < Rp) {
+            // the next pivot block is row block j0/16 + 1, column block 0:
+            // unit (j0/16) * ncb, which no other unit reads or writes; P^{-1}
+            // of this block was last read in step 2
+            const int un = (j0 >> 4) * ncb;
+            if (wave == 0) {
+                trail(un);
+                invert(c0);
+            } else {
+                for (int u = wave - 1; u < units; u += ANW - 1)
+                    if (u != un) trail(u);
+            }
+        } else {
+            for (int u = wave; u < units; u += ANW) trail(u);
         }
         __syncthreads();
     }
@@ -486,6 +521,7 @@ __device__ __forceinline__ int gj_wave(double* Aug, int ldx, int R, int W, doubl
 // V^{-1} Xt in place for Rp (a multiple of 4) rows and W columns; every
 // thread returns the ok flag (0 when a pivot of the first R rows is not above
 // rtol * max_{r < R} V_rr).
+template <bool SIZED = true>
 __device__ __forceinline__ int gj_solve(double* Aug, int ldx, int R, int Rp, int W, double rtol,
                                         double* fbuf) {
     if (Rp <= 32 && W <= 64) {
@@ -506,7 +542,7 @@ __device__ __forceinline__ int gj_solve(double* Aug, int ldx, int R, int Rp, int
         __syncthreads();
         return fbuf[0] != 0.0;
     }
-    return block16_gj(Aug, ldx, R, Rp, W, rtol, fbuf);
+    return block16_gj<SIZED>(Aug, ldx, R, Rp, W, rtol, fbuf);
 }
 
 }  // namespace rcp

@@ -378,13 +378,14 @@ __device__ __forceinline__ void unit_factor_gram(const double* Xt, int ldx, int 
 // columns: lambda_r = ||column r||, the float32 factor in c.fac(n) and
 // G_n = Ã_n^T Ã_n of exactly that float32 factor (matrix cores).  Returns
 // RCP_INFO_* bits.
+template <bool SIZED>
 __device__ __forceinline__ int solve_update(const AlsCtx& c, int n, double* G, const double* M,
                                             double* Aug, int ldx, int Rp, double* pb, double* E,
                                             double* Ev, double* lam) {
     const int tid = threadIdx.x, R = c.R, ln = c.l[n];
     double* Xt = Aug + Rp;
     int status = 0;
-    const int ok = gj_solve(Aug, ldx, R, Rp, Rp + ln, kPivotRtol, pb);
+    const int ok = gj_solve<SIZED>(Aug, ldx, R, Rp, Rp + ln, kPivotRtol, pb);
     if (!ok) {
         // Moore-Penrose pseudo-inverse through the eigen-decomposition
         status |= RCP_INFO_PINV_FALLBACK;
@@ -511,7 +512,7 @@ __device__ __forceinline__ void als_body(const AlsArgs& a) {
             hadamard_grams<false>(c, n, G, Aug, ldx, Rp, c.l[n]);
             mttkrp<NN>(c, n, Bs, sst, ones, P, pfl, M, Aug + Rp, ldx);
             __syncthreads();
-            status |= solve_update(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs,
+            status |= solve_update<false>(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs,
                                    (n == N - 1) ? lam : lam_tmp);
         }
         // ---- fit (Section 3.3): rho = 1 - (||X||^2 + ||Xhat||^2 - 2 <Xhat, X>) / ||X||^2,
@@ -691,7 +692,7 @@ __global__ __launch_bounds__(ANT) void k_als_wide_step(AlsArgs a, int n) {
         }
     }
     __syncthreads();
-    int status = solve_update(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs, lam);
+    int status = solve_update<true>(c, n, G, M, Aug, ldx, Rp, pb, Es, Evs, lam);
     for (int e = tid; e < ln * R; e += ANT) a.At[n][e] = c.fac(n)[e];
     if (n < N - 1) {
         if (tid == 0 && status != 0) fl[2] |= status;
