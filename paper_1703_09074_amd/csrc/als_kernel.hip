@@ -310,20 +310,35 @@ __device__ __forceinline__ void hadamard_grams(const AlsCtx& c, int n, const dou
     }
 }
 
-// Unit columns of the solution and their Gram in one pass: Xt holds the
-// solution transposed (R rows of length l_n, float64, stride ldx).  Every
-// wavefront takes 16 x 16 blocks (bi, bj) of the upper triangle of
-// G_n = F^T F, F the float32 factor with columns Xt_r / ||Xt_r||; it first
-// forms the norms of its own rows (each lane sums a quarter of the row, the
-// four quarters meet by shuffles), then feeds the matrix cores with exactly
-// the float32 values of F, so G_n is the float64 Gram of the stored factor.
-// The wavefronts of diagonal blocks also store F (l_n x R) and
-// lambda_r = ||Xt_r||.
+// Unit columns of the solution and their Gram: Xt holds the solution
+// transposed (R rows of length l_n, float64, stride ldx).  First wavefront b
+// forms the norms of rows 16b .. 16b + 15 (each lane sums a quarter of a
+// row, the four quarters meet by shuffles): lambda_r = ||Xt_r||, in lam
+// (LDS).  Then every wavefront takes 16 x 16 blocks (bi, bj) of the upper
+// triangle of G_n = F^T F, F the float32 factor with columns
+// Xt_r / ||Xt_r||, and feeds the matrix cores with exactly the float32
+// values of F, so G_n is the float64 Gram of the stored factor; the
+// wavefronts of diagonal blocks also store F (l_n x R).
 __device__ __forceinline__ void unit_factor_gram(const double* Xt, int ldx, int ln, int R, float* F,
                                                  double* G, double* lam) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int nb = (R + 15) >> 4;
+    for (int b = wave; b < nb; b += ANW) {
+        const int c1 = b * 16 + li;
+        const bool v1 = c1 < R;
+        const double* x1 = Xt + (v1 ? c1 : 0) * ldx;
+        double s1 = 0.0;
+#pragma unroll 4
+        for (int k = lk; k < ln; k += 4) {
+            const double p = x1[k];
+            s1 += p * p;
+        }
+        s1 += __shfl_xor(s1, 16, 64);
+        s1 += __shfl_xor(s1, 32, 64);
+        if (lk == 0 && v1) lam[c1] = sqrt(s1);
+    }
+    __syncthreads();
     const int U = nb * (nb + 1) / 2;
     for (int u = wave; u < U; u += ANW) {
         int bi = 0, rem = u;
@@ -334,20 +349,8 @@ __device__ __forceinline__ void unit_factor_gram(const double* Xt, int ldx, int 
         const bool v1 = c1 < R, v2 = c2 < R;
         const double* x1 = Xt + (v1 ? c1 : 0) * ldx;
         const double* x2 = Xt + (v2 ? c2 : 0) * ldx;
-        double s1 = 0.0, s2 = 0.0;
-#pragma unroll 4
-        for (int k = lk; k < ln; k += 4) {
-            const double p = x1[k], q = x2[k];
-            s1 += p * p;
-            s2 += q * q;
-        }
-        s1 += __shfl_xor(s1, 16, 64);
-        s1 += __shfl_xor(s1, 32, 64);
-        s2 += __shfl_xor(s2, 16, 64);
-        s2 += __shfl_xor(s2, 32, 64);
-        const double nu1 = sqrt(s1), nu2 = sqrt(s2);
+        const double nu1 = v1 ? lam[c1] : 0.0, nu2 = v2 ? lam[c2] : 0.0;
         const double i1 = (nu1 > 0.0) ? 1.0 / nu1 : 1.0, i2 = (nu2 > 0.0) ? 1.0 / nu2 : 1.0;
-        if (diag && lk == 0 && v1) lam[c1] = nu1;
         f64x4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
         for (int k0 = 0; k0 < ln; k0 += 8) {
             const int k = k0 + lk, kb = k + 4;
