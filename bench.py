@@ -612,8 +612,10 @@ def concurrent(args, torch, rcpgpu, dev, name, X, base):
 
 # the sources each kernel class is compiled from (besides the shared headers)
 STREAM_SOURCES = ("stream_kernels.hip", "stream_tiles.h")
-KERNEL_SOURCES = {"als": ("als_kernel.hip",), "qr": ("qr_kernel.hip",),
-                  "expand": ("expand_kernel.hip",)}
+# the ALS class also runs the streaming kernels (the Khatri-Rao mode product
+# and its reduction of the grid-wide form)
+KERNEL_SOURCES = {"als": ("als_kernel.hip", "als_common.h") + STREAM_SOURCES,
+                  "qr": ("qr_kernel.hip",), "expand": ("expand_kernel.hip",)}
 
 
 def _source_hash(kernel_class):
