@@ -123,106 +123,30 @@ __device__ __forceinline__ void gram64(const double* A, int lda, int m, int n, i
     __syncthreads();
 }
 
-// Upper Cholesky factor of G + shift I (n x n, stride np), shift =
-// shift_coef * trace(G), and its inverse, by all threads, one barrier per
-// pivot.  Right-looking: step j subtracts g_ji g_jk / g_jj from the trailing
-// entries (i, k), j < i <= k, reading only row j, which the previous step
-// finished; afterwards row j of G holds sqrt(d_j) R[j][.].  The thread that
-// finishes the next pivot also publishes its reciprocal.  Then
-// R^{-1} = D^{-1/2}-scaled back substitution, again one row per step:
-// X[j][.] = B[j][.] / R_jj and B[i][.] -= R_ij X[j][.] for i < j, with B = I
-// initially (B kept apart from X so that a step only reads what the
-// previous one wrote).  On return X = R^{-1} (upper, zero elsewhere); G and
-// B are destroyed.  Returns 0 when a pivot is not above kCqrPivot times the
-// largest diagonal entry.  Callers synchronise the workgroup before using X.
-__device__ __forceinline__ int chol_inverse(double* G, double* X, double* B, double* pinv,
-                                            double* red, int n, int np, double shift_coef) {
-    const int tid = threadIdx.x;
-    double gm = 0.0, tr = 0.0;
-    for (int j = tid; j < n; j += qnt()) { gm = fmax(gm, G[j * np + j]); tr += G[j * np + j]; }
-    tr = block_sum(tr, red);
-    gm = qr_block_max(gm, red);
-    const double shift = shift_coef * tr;
-    const double thr = kCqrPivot * (gm + shift);
-    for (int j = tid; j < n; j += qnt()) G[j * np + j] += shift;
-    for (int e = tid; e < np * np; e += qnt()) {
-        const int i = e / np, c = e - (e / np) * np;
-        X[e] = 0.0;
-        B[e] = (i == c) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    if (tid == 0) pinv[0] = 1.0 / fmax(G[0], thr);
-    __syncthreads();
-    int ok = 1;
-    for (int j = 0; j < n; ++j) {
-        const double d = G[j * np + j];
-        ok &= (d > thr) ? 1 : 0;
-        const double id = pinv[j];
-        const int w = n - j - 1;
-        if (w > 0) {
-            const float inv_w = __builtin_amdgcn_rcpf((float)w);
-            for (int e = tid; e < w * w; e += qnt()) {
-                const int ii = small_div(e, w, inv_w), kk = e - ii * w;
-                if (kk < ii) continue;
-                const int i = j + 1 + ii, k = j + 1 + kk;
-                const double v = G[i * np + k] - G[j * np + i] * G[j * np + k] * id;
-                G[i * np + k] = v;
-                if (ii == 0 && kk == 0) pinv[j + 1] = 1.0 / fmax(v, thr);
-            }
-        }
-        __syncthreads();
-    }
-    // R_jj = sqrt(d_j), R_jk = g_jk / sqrt(d_j); keep 1 / R_jj in pinv
-    for (int j = tid; j < n; j += qnt()) pinv[j] = 1.0 / sqrt(fmax(G[j * np + j], thr));
-    __syncthreads();
-    for (int e = tid; e < n * n; e += qnt()) {
-        const int i = e / n, k = e - (e / n) * n;
-        if (k > i) G[i * np + k] *= pinv[i];
-    }
-    __syncthreads();
-    // back substitution for R^{-1}, rows from the last
-    for (int j = n - 1; j >= 0; --j) {
-        const double ir = pinv[j];
-        for (int e = tid; e < (j + 1) * (n - j); e += qnt()) {
-            const int i = e / (n - j), c = j + (e - (e / (n - j)) * (n - j));
-            if (i == j) X[j * np + c] = B[j * np + c] * ir;
-            else B[i * np + c] -= G[i * np + j] * B[j * np + c] * ir;
-        }
-        __syncthreads();
-    }
-    return ok;
-}
-
-// The same result for n <= NP <= 32 in one wavefront, from registers: lane c
-// holds column c of [G + shift I | I] (2 NP <= 64 columns, identity beyond
-// n), and the rows rotate through the registers so that the pivot row is
+// The upper Cholesky factor R of G + shift I (n x n, n <= NP <= 32, G row
+// stride ldg) and its inverse X = R^{-1} (stride ldx, upper, zero
+// elsewhere), in one wavefront from registers: lane c holds column c of
+// [G + shift I | I] (2 NP <= 64 columns, identity beyond n), and the rows
+// rotate through the registers so that the pivot row is
 // always register 0 (steps unrolled: static indices).  Step k subtracts
 // multiples of the pivot row from the rows below it (their entries in the
 // pivot column come from lane k by readlane) and moves it to the back; after
 // NP steps the rows read [U | L^{-1}] with G + shift I = L U, U = D L^T.  Then
 // R = D^{1/2} L^T, so R^{-1}[i][j] = L^{-1}[j][i] / sqrt(d_j): lane NP + i
-// holds column i of L^{-1} and writes row i of X.  Wavefront 0 runs it; it
-// returns 0 when a pivot is not above kCqrPivot times the largest diagonal
-// entry (shift included).  Callers synchronise the workgroup before using X.
+// holds column i of L^{-1} and writes row i of X; isd (NP doubles, LDS)
+// receives 1 / R_jj.  Wavefront 0 runs it; it returns 0 when a pivot is not
+// above thr.  Callers synchronise the workgroup before using X.
 template <int NP>
-__device__ __forceinline__ int chol_inverse_wave(const double* G, double* X, int n,
-                                                 double shift_coef, double* isd) {
+__device__ __forceinline__ int chol_inverse_wave_s(const double* G, int ldg, double* X, int ldx, int n,
+                                                   double shift, double thr, double* isd) {
     const int lane = threadIdx.x & 63;
-    double gm = 0.0, tr = 0.0;
-    for (int j = 0; j < n; ++j) {
-        const double d = G[j * NP + j];
-        gm = fmax(gm, d);
-        tr += d;
-    }
-    const double shift = shift_coef * tr;
-    const double thr = kCqrPivot * (gm + shift);
     double col[NP];
     const int c = lane;
 #pragma unroll
     for (int i = 0; i < NP; ++i) {
         double v;
         if (c < NP) {
-            v = (i < n && c < n) ? G[i * NP + c] : 0.0;
+            v = (i < n && c < n) ? G[i * ldg + c] : 0.0;
             if (i == c) v = (i < n) ? v + shift : 1.0;
         } else {
             v = (i == c - NP) ? 1.0 : 0.0;
@@ -259,9 +183,107 @@ __device__ __forceinline__ int chol_inverse_wave(const double* G, double* X, int
         const int i = c - NP;
 #pragma unroll
         for (int j = 0; j < NP; ++j)
-            X[i * NP + j] = (i < n && j < n && j >= i) ? col[j] * isd[j] : 0.0;
+            X[i * ldx + j] = (i < n && j < n && j >= i) ? col[j] * isd[j] : 0.0;
     }
     return ok;
+}
+
+
+// chol_inverse_wave_s on G (stride NP) with the shift and pivot floor of
+// G's own first n rows, X stride NP.
+template <int NP>
+__device__ __forceinline__ int chol_inverse_wave(const double* G, double* X, int n,
+                                                 double shift_coef, double* isd) {
+    double gm = 0.0, tr = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double d = G[j * NP + j];
+        gm = fmax(gm, d);
+        tr += d;
+    }
+    const double shift = shift_coef * tr;
+    const double thr = kCqrPivot * (gm + shift);
+    return chol_inverse_wave_s<NP>(G, NP, X, NP, n, shift, thr, isd);
+}
+
+// The same result (up to rounding) for 32 < n <= np <= 64 as a 2 x 2 block
+// Cholesky, the diagonal blocks factored and inverted by the register
+// elimination above (wavefront 0), the off-diagonal products over the
+// workgroup:  G + sI = [A B; B^T C],  A = R1^T R1,  R12 = R1^{-T} B,
+// S = C + sI - R12^T R12 = R2^T R2,  R^{-1} = [R1^{-1}, -R1^{-1} R12 R2^{-1};
+// 0, R2^{-1}].  The shift s = shift_coef trace(G) and the pivot floor are
+// those of the whole matrix; S's pivots are the whole elimination's trailing
+// ones.  Two register eliminations and four barriers in place of one
+// barrier per pivot.  scratch: 4096 doubles.  On return X = R^{-1} (upper,
+// zero elsewhere, stride np); G is left as it was.  Returns 0 when a pivot
+// is not above the floor.  Callers synchronise the workgroup before using X.
+__device__ __forceinline__ int chol_inverse_blk(const double* G, double* X, double* scratch,
+                                                double* isd, double* red, int n, int np,
+                                                double shift_coef) {
+    __shared__ int okf[2];
+    const int tid = threadIdx.x;
+    const int n2 = n > 32 ? n - 32 : 0;
+    double gm = 0.0, tr = 0.0;
+    for (int j = tid; j < n; j += qnt()) { gm = fmax(gm, G[j * np + j]); tr += G[j * np + j]; }
+    tr = block_sum(tr, red);
+    gm = qr_block_max(gm, red);
+    const double shift = shift_coef * tr;
+    const double thr = kCqrPivot * (gm + shift);
+    double* R12 = scratch;          // 32 x 32
+    double* S = R12 + 1024;         // 32 x 32
+    double* X22 = S + 1024;         // 32 x 32
+    double* W = X22 + 1024;         // 32 x 32
+    if (tid < 64) {
+        const int ok = chol_inverse_wave_s<32>(G, np, X, np, n < 32 ? n : 32, shift, thr, isd);
+        if (tid == 0) okf[0] = ok;
+    }
+    __syncthreads();
+    // R12 = R1^{-T} B (X holds R1^{-1}, upper)
+    for (int e = tid; e < 1024; e += qnt()) {
+        const int i = e >> 5, j = e & 31;
+        double v = 0.0;
+        if (j < n2)
+            for (int k = 0; k <= i; ++k) v += X[k * np + i] * G[k * np + 32 + j];
+        R12[e] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < 1024; e += qnt()) {
+        const int i = e >> 5, j = e & 31;
+        double v = 0.0;
+        if (i < n2 && j < n2) {
+            v = G[(32 + i) * np + 32 + j] + ((i == j) ? shift : 0.0);
+            for (int k = 0; k < 32; ++k) v -= R12[k * 32 + i] * R12[k * 32 + j];
+        }
+        S[e] = v;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const int ok = chol_inverse_wave_s<32>(S, 32, X22, 32, n2, 0.0, thr, isd);
+        if (tid == 0) okf[1] = ok;
+    }
+    __syncthreads();
+    // W = R12 R2^{-1}
+    for (int e = tid; e < 1024; e += qnt()) {
+        const int i = e >> 5, j = e & 31;
+        double v = 0.0;
+        if (j < n2)
+            for (int k = 0; k <= j; ++k) v += R12[i * 32 + k] * X22[k * 32 + j];
+        W[e] = v;
+    }
+    __syncthreads();
+    // X12 = -R1^{-1} W, X22 into place, zero below
+    for (int e = tid; e < 32 * (np - 32); e += qnt()) {
+        const int i = e / (np - 32), j = e - i * (np - 32);
+        double v = 0.0;
+        if (j < n2)
+            for (int k = i; k < 32; ++k) v -= X[i * np + k] * W[k * 32 + j];
+        X[i * np + 32 + j] = v;
+    }
+    for (int e = tid; e < (np - 32) * np; e += qnt()) {
+        const int i = e / np, c = e - i * np;
+        X[(32 + i) * np + c] = (c < 32) ? 0.0 : X22[i * 32 + (c - 32)];
+    }
+    __syncthreads();
+    return okf[0] && okf[1];
 }
 
 // A <- A X for upper triangular X (n x n, stride np = 16 NB), on the matrix
@@ -471,7 +493,7 @@ __device__ __forceinline__ void qr_body(double* Yg, int m, int n, int ldy, float
                 flag = red[0] != 0.0;
                 __syncthreads();
             } else {
-                flag = chol_inverse(G, X, scratch, dinv, red, n, np, sc);
+                flag = chol_inverse_blk(G, X, scratch, dinv, red, n, np, sc);
             }
             if (!flag) {
                 householder_q(A, lda, m, n, scratch, taus, betas, red);
@@ -606,7 +628,7 @@ __global__ __launch_bounds__(qr_threads<NB>()) void k_tqr_chol(int m, int n, int
             flag = red[0] != 0.0;
             __syncthreads();
         } else {
-            flag = chol_inverse(G, X, scratch, dinv, red, n, np, sc);
+            flag = chol_inverse_blk(G, X, scratch, dinv, red, n, np, sc);
         }
     }
     __syncthreads();
