@@ -590,10 +590,36 @@ __global__ __launch_bounds__(qr_threads<NB>()) void k_tqr_chol(int m, int n, int
     double* X = G + np * np;
     double* scratch = X + np * np;
     const double* Gp = tqr_G(work, np);
-    for (int e = tid; e < np * np; e += qnt()) {
-        double v = 0.0;
-        for (int b = 0; b < nblk; ++b) v += Gp[(size_t)b * np * np + e];
-        G[e] = v;
+    // G = sum of the nblk partial Grams in block order; a thread's loads of
+    // eight blocks for four elements are in flight together
+    for (int e0 = 0; e0 < np * np; e0 += 4 * qnt()) {
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        int b = 0;
+        for (; b + 8 <= nblk; b += 8) {
+            double g[8][4];
+#pragma unroll
+            for (int bb = 0; bb < 8; ++bb)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int e = e0 + tid + j * qnt();
+                    g[bb][j] = (e < np * np) ? Gp[(size_t)(b + bb) * np * np + e] : 0.0;
+                }
+#pragma unroll
+            for (int bb = 0; bb < 8; ++bb)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] += g[bb][j];
+        }
+        for (; b < nblk; ++b)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int e = e0 + tid + j * qnt();
+                if (e < np * np) v[j] += Gp[(size_t)b * np * np + e];
+            }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int e = e0 + tid + j * qnt();
+            if (e < np * np) G[e] = v[j];
+        }
     }
     __syncthreads();
     bool first_order = false;
