@@ -378,11 +378,19 @@ def test_decompose_noise_free_rank_deficient_sketch():
     assert cong > 0.99999
 
 
-def test_tall_rank_deficient_sketch():
-    """A rank-2 noise-free tensor with a 1200-row mode sketched 10 wide (the
-    row-block QR): an orthonormal basis whose span holds the mode's range."""
-    w = synth.low_rank((1200, 20, 16), 2, 0.0, 43)
-    plan = rcpgpu.Plan((1200, 20, 16), 4, 6, 1, 5, 0.0, 3)
+# (dims, k, p): sketch widths 10 (the one-wavefront Cholesky), 40 and 60 (the
+# 2 x 2 block Cholesky over 32-row register eliminations); 1200 rows take the
+# row-block QR, 400 rows the one-workgroup QR
+QR_WIDTH_CASES = [((1200, 20, 16), 4, 6), ((1200, 64, 40), 30, 10), ((1200, 64, 64), 50, 10),
+                  ((400, 64, 40), 30, 10), ((400, 64, 64), 50, 10)]
+
+
+@pytest.mark.parametrize("dims,k,p", QR_WIDTH_CASES)
+def test_tall_rank_deficient_sketch(dims, k, p):
+    """A rank-2 noise-free tensor sketched 10 to 60 wide: an orthonormal basis
+    whose span holds the mode's range."""
+    w = synth.low_rank(dims, 2, 0.0, 43)
+    plan = rcpgpu.Plan(dims, k, p, 1, 5, 0.0, 3)
     Q = _np(plan.sketch(_dev(w.X), 0))
     np.testing.assert_allclose(Q.T @ Q, np.eye(Q.shape[1]), atol=1e-5)
     X0 = rcp.unfold(w.X.astype(np.float64), 0)
@@ -390,13 +398,14 @@ def test_tall_rank_deficient_sketch():
     assert resid < 1e-5, resid
 
 
-def test_tall_zero_sketch_falls_back_to_householder():
-    """An all-zero tensor with a 1200-row mode: every Cholesky pivot of the
-    row-block QR is zero, the one-workgroup Householder fallback runs on the
-    (unchanged) sketch and returns an orthonormal basis, raising its bit."""
-    plan = rcpgpu.Plan((1200, 20, 16), 4, 6, 1, 5, 0.0, 3)
+@pytest.mark.parametrize("dims,k,p", QR_WIDTH_CASES)
+def test_tall_zero_sketch_falls_back_to_householder(dims, k, p):
+    """An all-zero tensor: every Cholesky pivot is zero, the Householder
+    fallback runs on the (unchanged) sketch and returns an orthonormal basis,
+    raising its bit."""
+    plan = rcpgpu.Plan(dims, k, p, 1, 5, 0.0, 3)
     assert plan.read_status() == 0
-    Q = _np(plan.sketch(_dev(np.zeros((1200, 20, 16))), 0))
+    Q = _np(plan.sketch(_dev(np.zeros(dims)), 0))
     np.testing.assert_allclose(Q.T @ Q, np.eye(Q.shape[1]), atol=1e-6)
     assert plan.read_status() & rcpgpu._lib.RCP_INFO_QR_HOUSEHOLDER
 
