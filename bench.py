@@ -391,7 +391,7 @@ def config_of(name):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path "
+        print(f"bench.py measures one GPU: the library has no multi-GPU path "
               f"(asked for --gpus {args.gpus}); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy > 0:
@@ -618,14 +618,27 @@ KERNEL_SOURCES = {"als": ("als_kernel.hip", "als_common.h") + STREAM_SOURCES,
                   "qr": ("qr_kernel.hip",), "expand": ("expand_kernel.hip",)}
 
 
-def _source_hash(kernel_class):
-    """Hash of the sources a kernel class is built from (its .hip file and the
-    shared device headers): stored traffic counts are used only while it matches."""
+def _strip_comments(src):
+    """C++ source without comments and blank lines (string literals in these
+    files hold no comment markers)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+
+
+def _source_hash(kernel_class, read=None):
+    """Hash of the code (comments stripped) a kernel class is built from (its
+    sources and the shared device headers): stored traffic counts are used
+    only while it matches.  ``read(name)`` returns a source's text (default:
+    the working tree)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "paper_1703_09074_amd", "csrc")
+    if read is None:
+        read = lambda f: open(os.path.join(csrc, f), encoding="utf-8").read()  # noqa: E731
     for f in KERNEL_SOURCES.get(kernel_class, STREAM_SOURCES) + ("rcp_device.h", "rcp_kernels.h"):
-        h.update(open(os.path.join(csrc, f), "rb").read())
+        h.update(_strip_comments(read(f)).encode("utf-8"))
     return h.hexdigest()[:16]
 
 

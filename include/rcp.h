@@ -45,15 +45,16 @@ typedef enum rcp_status {
     RCP_ERR_WORKSPACE = 2,     /* workspace missing or too small */
     RCP_ERR_HIP = 3,           /* a HIP runtime call or kernel launch failed */
     RCP_ERR_NUMERIC = 4,       /* reserved for synchronous numeric failures */
-    RCP_ERR_UNSUPPORTED = 5    /* valid request this build does not implement */
+    RCP_ERR_UNSUPPORTED = 5    /* valid request the library does not implement */
 } rcp_status;
 
 /* rcp_problem.precision: operand precision of the range finder's
  * contractions (the sketch and the power-iteration products of Algorithm 1
- * steps 6, 9 and 10).  FP32 feeds the matrix cores float32 operands; BF16 /
+ * the sketch and the power iterations' products).  FP32 feeds the matrix cores float32 operands; BF16 /
  * FP16 round the float32 tensor tiles and the test-matrix or basis operands
  * to bfloat16 / float16 (nearest even) on their way to the matrix cores.
- * Their rounding only perturbs the basis Q_n.  The mode products of step 13,
+ * Their rounding only perturbs the basis Q_n.  The mode products of the projection
+ * B <- B x_n Q_n^T (Algorithm 1),
  * whose output is the core itself, keep float32 operands in every precision.
  * Accumulation is float32, and the cross-workgroup sums, the QR and every
  * ALS solve stay float64 in all cases; X is read as float32. */
@@ -65,14 +66,14 @@ enum { RCP_PREC_FP32 = 0, RCP_PREC_BF16 = 1, RCP_PREC_FP16 = 2 };
  * forms the core by chained mode products afterwards. */
 enum { RCP_SCHEME_SEQUENTIAL = 0, RCP_SCHEME_INDEPENDENT = 1 };
 
-/* rcp_problem.test_matrix: Omega_n of Algorithm 1 step 5, a pure function of
+/* rcp_problem.test_matrix: Omega_n of Algorithm 1 (the test-matrix draw), a pure function of
  * (seed, mode, batch, row j, column c), never stored:
  *   GAUSSIAN  N(0, 1) entries (Section 3.1): Philox4x32-10 on the counter
  *             (j mod 2^32, j >> 32, c / 4, (batch << 8) | mode) with key
  *             (seed mod 2^32, seed >> 32), uniforms ((x >> 8) + 1) 2^-24,
  *             Box-Muller on the pairs (u0, u1), (u2, u3);
  *   UNIFORM   the uniforms themselves, entry c taking word c mod 4 (the
- *             rand(J, l) of step 5; the remark after Algorithm 1);
+ *             rand(J, l) of Algorithm 1's test-matrix draw; the remark after it);
  *   HALTON    quasi-random (the note in Section 3.1): entry (j, c) is the
  *             radical inverse of j + 1 in the c-th prime base (no seed);
  *   COLUMNS   l randomly selected columns of the unfolding (the remark after
@@ -99,7 +100,7 @@ enum {
     RCP_INFO_NONFINITE = 2,      /* the fit became NaN/Inf */
     RCP_INFO_EIG_NOT_CONVERGED = 4, /* the eigenvector start's Jacobi sweeps did not converge */
     RCP_INFO_QR_HOUSEHOLDER = 8  /* a sketch was numerically rank deficient: its QR
-                                    (Algorithm 1 steps 8/12) fell back to Householder */
+                                    (Algorithm 1's orthonormalisations) fell back to Householder */
 };
 
 #define RCP_MAX_NDIM 8     /* tensor order N in [2, 8] */
@@ -107,8 +108,8 @@ enum {
 #define RCP_MAX_RANK 64    /* k <= 64 */
 
 /* The problem, as Algorithm 1 and 2 state it: an N-way tensor, target rank
- * k (= CP rank R), oversampling p (Algorithm 1 step 3, l = k + p) and q
- * normalised power iterations (Algorithm 1 steps 7-11). */
+ * k (= CP rank R), oversampling p (Algorithm 1: l = k + p) and q
+ * normalised power iterations (Algorithm 1). */
 typedef struct rcp_problem {
     int32_t ndim;                    /* N, 2..RCP_MAX_NDIM */
     int32_t k;                       /* target rank = CP rank R, >= 1 */
@@ -122,7 +123,7 @@ typedef struct rcp_problem {
     double tol;                      /* stop when |rho_j - rho_{j-1}| < tol (j >= 2); 0 = run max_iters */
     uint64_t seed;                   /* seed of the random test matrices */
     /* variants of Algorithm 1 (all zero = the defaults above) */
-    int32_t test_matrix;             /* RCP_TEST_*: the test matrix Omega_n of step 5 */
+    int32_t test_matrix;             /* RCP_TEST_*: Algorithm 1's test matrix Omega_n */
     uint32_t compress_mask;          /* bit n set: compress mode n; 0 = every mode.  A mode
                                         left out keeps Q_n = I (needs I_n <= 64) */
     int32_t per_mode_p;              /* nonzero: mode_p[n] replaces p for mode n */
@@ -167,7 +168,8 @@ rcp_status rcp_destroy(rcp_plan plan);
  * copy fails. */
 rcp_status rcp_read_status(rcp_plan plan, int32_t* status);
 
-/* Randomised range finder of one mode (Algorithm 1 steps 3-12).
+/* Randomised range finder of one mode (Algorithm 1, up to the final
+ * orthonormalisation).
  * T: current tensor with dims cur_dims[0..N-1] (host array); mode n; the
  * sketch width is l = min(k + p, cur_dims[n]).  Writes the orthonormal
  * basis Q (cur_dims[n] x l, row-major, diag(R) > 0 convention) built from
@@ -178,7 +180,7 @@ rcp_status rcp_read_status(rcp_plan plan, int32_t* status);
 rcp_status rcp_sketch(rcp_plan plan, const float* T, const int64_t* cur_dims,
                       int32_t mode, float* Q);
 
-/* Mode-n projection T_out = T x_n Q^T (Algorithm 1 step 13; the n-mode
+/* Mode-n projection T_out = T x_n Q^T (Algorithm 1's projection; the n-mode
  * product of Definition 1).  Q is cur_dims[n] x l row-major, l = its
  * width as rcp_sketch defines it; T_out has dims cur_dims with mode n
  * replaced by l.  T and T_out must not overlap. */
@@ -188,18 +190,18 @@ rcp_status rcp_compress(rcp_plan plan, const float* T, const int64_t* cur_dims,
 /* ||X||_F^2 in float64 of count float32 values (written to *out, device). */
 rcp_status rcp_norm2(rcp_plan plan, const float* X, int64_t count, double* out);
 
-/* CP-ALS on the core (Algorithm 2 steps 2-11).  core: l_0 x ... x l_{N-1}
+/* CP-ALS on the core (Algorithm 2: initialisation and sweeps).  core: l_0 x ... x l_{N-1}
  * (the plan's sketch widths).  At[n]: l_n x R outputs (row-major); lambda:
  * R outputs; info: device rcp_als_info.  normX2: device pointer to ||X||^2
  * of the uncompressed tensor for the fit (NULL: use ||core||^2).
  * Initialisation: leading R eigenvectors of B_(n) B_(n)^T for modes
- * 1..N-1 (Algorithm 2 step 2); with use_given_init != 0 the sweeps start
+ * 1..N-1 (Algorithm 2's initialisation); with use_given_init != 0 the sweeps start
  * instead from the factors the caller left in At[1..N-1] (a warm start, the
  * way to resume an interrupted run: At[0] is computed first and not read).
  * Sweeps: for n = 0..N-1, Ã_n = B_(n)
  * KR(Ã_{m!=n}) (*_{m!=n} Ã_m^T Ã_m)^+, column-normalised, lambda from the
- * last mode (steps 4-10).  Stops after max_iters sweeps, or earlier when
- * tol > 0 and the fit changes by less than tol (step 11).  A core that fits
+ * last mode (the factor updates of a sweep).  Stops after max_iters sweeps, or earlier when
+ * tol > 0 and the fit changes by less than tol (the convergence test).  A core that fits
  * in one workgroup's LDS runs the whole sweep loop in one launch; a larger
  * one runs its mode products over the whole GPU with a one-workgroup solve
  * per mode (every max_iters sweep is enqueued; after the stopping rule fires
@@ -208,7 +210,7 @@ rcp_status rcp_als(rcp_plan plan, const float* core, float* const* At,
                    float* lambda, const double* normX2, rcp_als_info* info,
                    int32_t use_given_init);
 
-/* Block coordinate descent on the core (Algorithm 3 steps 2-15; arguments
+/* Block coordinate descent on the core (Algorithm 3: initialisation and rank-one sweeps; arguments
  * as rcp_als).  Components r = 0..R-1 one after another: each sweep updates
  * a_r^(0..N-1) in mode order, each the least-squares rank-one block update on
  * the residual B - sum_{s<r} lam_s a_s^(0) o ... o a_s^(N-1) (evaluated
@@ -229,7 +231,7 @@ rcp_status rcp_bcd(rcp_plan plan, const float* core, float* const* At,
  * dims, C-order float32; outputs A[n] (I_n x R), lambda (R) and info as for
  * rcp_decompose (ordered by lambda, signs fixed, fit exact on X).
  * Start (A_init == NULL): for modes 1..N-1 the leading R eigenvectors of
- * X_(n) X_(n)^T (Algorithm 2 step 2), computed by subspace iteration: the
+ * X_(n) X_(n)^T (Algorithm 2's initialisation), computed by subspace iteration: the
  * plan's q power steps of Algorithm 1 on an l_n = min(k + p, I_n) wide block
  * (the plan's test matrix and seed), then the eigenvectors of the l_n x l_n
  * Gram Q^T X_(n) X_(n)^T Q (Rayleigh-Ritz); equal to the exact ones up to
@@ -244,8 +246,8 @@ rcp_status rcp_bcd(rcp_plan plan, const float* core, float* const* At,
 rcp_status rcp_cp_als(rcp_plan plan, const float* X, const float* const* A_init,
                       float* const* A, float* lambda, rcp_als_info* info);
 
-/* Back-projection A_n = Q_n Ã_n (eq. qbs, Algorithm 2 step 12) and the
- * renormalisation of step 13: unit columns, norms folded into lambda,
+/* Back-projection A_n = Q_n Ã_n (eq. qbs, Algorithm 2's factor recovery) and the
+ * final renormalisation: unit columns, norms folded into lambda,
  * components sorted by lambda (descending), the largest-magnitude entry of
  * each column of modes 0..N-2 made positive with the sign moved to mode
  * N-1.  Q[n]: I_n x l_n, At[n]: l_n x R, lambda_in: R; outputs A[n]:

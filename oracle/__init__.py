@@ -7,7 +7,7 @@ baseline leg of the benchmark use it.  It shares no code with the HIP path
 and is written from the paper alone:
 
   philox     Philox4x32-10 counter-based generator and the Gaussian test
-             matrix Omega_n built from it (Section 3.1, Algorithm 1 step 5).
+             matrix Omega_n built from it (Section 3.1, Algorithm 1's test-matrix draw).
   rcp        the randomized compression (Algorithm 1), CP-ALS on the core
              (Algorithm 2), back-projection (eq. qbs), the fit of
              Section 3.3 and deterministic CP-ALS (the same solver with

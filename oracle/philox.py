@@ -2,7 +2,7 @@
 
 The paper draws the columns of the test matrix Omega_n from a Gaussian
 distribution (Section 3.1, first step of the randomized tensor algorithm;
-Algorithm 1 step 5 writes ``rand(J, l)``; the remark after Algorithm 1 notes
+Algorithm 1 draws its test matrix as ``rand(J, l)``; the remark after Algorithm 1 notes
 that Gaussian matrices are what the theory assumes).  Here Omega_n is a
 pure function of (seed, mode, batch, row, column), so any row block of it
 can be regenerated anywhere without being stored.
@@ -109,7 +109,7 @@ def omega(seed: int, mode: int, batch: int, row0: int, nrows: int, l: int):
 
 
 def omega_uniform(seed: int, mode: int, batch: int, row0: int, nrows: int, l: int):
-    """Rows [row0, row0+nrows) of the uniform test matrix (Algorithm 1 step 5
+    """Rows [row0, row0+nrows) of the uniform test matrix (Algorithm 1's test-matrix draw
     writes rand(J, l); the remark after Algorithm 1 notes that a uniform test
     matrix is sufficient in practice): entry (j, c) is the uniform u of word
     c mod 4 of counter group c // 4 of row j, in (0, 1]; float64."""

@@ -27,8 +27,8 @@ the design notes):
   * l_n = min(k + p, I_n) columns per mode; the core is l_1 x ... x l_N;
   * every QR is Householder with the signs fixed so that diag(R) > 0;
   * the default normaliser inside the power iterations is QR; the paper's
-    pivoted LU (Algorithm 1 steps 8-9) is available as ``normalizer="lu"``;
-  * "norm" in Algorithm 2 steps 5/7/9 is the column 2-norm; lambda comes
+    pivoted LU (the normalisers of Algorithm 1's power iterations) is available as ``normalizer="lu"``;
+  * "norm" in Algorithm 2's normalisations is the column 2-norm; lambda comes
     from the last mode;
   * fit: rho = 1 - ||X - Xhat||^2 / ||X||^2 (the Section 3.3 formula); the
     sweep loop stops after sweep j >= 2 once |rho_j - rho_{j-1}| < tol, and
@@ -45,7 +45,8 @@ monotone ALS residuals and the fit identity).  The q power iterations are
 pinned exactly: span(Q_n) equals span(U S^(2q+1) V^T Omega_n) from an SVD
 of T_(n) (eq. IMPsampleMatrix) and differs from the q - 1 span.  The
 sequential scheme is pinned by a brute-force loop: mode n sketches the tensor
-compressed in modes < n, with J_n rows of Omega_n (Algorithm 1 step 13).
+compressed in modes < n, with J_n rows of Omega_n (Algorithm 1: the tensor is replaced by its
+projection after each mode).
 The warm start of ``als`` is pinned by continuing an interrupted run.
 """
 from __future__ import annotations
@@ -109,7 +110,8 @@ def kruskal_full(lam: np.ndarray, factors: Sequence[np.ndarray]) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Orthonormalisation (Algorithm 1 steps 8, 9, 12)
+# Orthonormalisation (Algorithm 1: the power iterations' normalisers and the
+# final QR)
 
 def qr_pos(Y: np.ndarray) -> np.ndarray:
     """Economic Householder QR with diag(R) >= 0; returns Q (m x min(m, n))."""
@@ -121,7 +123,7 @@ def qr_pos(Y: np.ndarray) -> np.ndarray:
 
 def lu_factor_l(Y: np.ndarray) -> np.ndarray:
     """The permuted unit-lower factor of a partially pivoted LU, i.e. the
-    first output of ``[L, U] = lu(Y)`` in Algorithm 1 steps 8-9 (Remark 2:
+    first output of ``[L, U] = lu(Y)`` in Algorithm 1's power iterations (Remark 2:
     pivoted LU for the normalised power iterations)."""
     PL, _ = scipy.linalg.lu(Y, permute_l=True)
     return PL
@@ -139,7 +141,7 @@ def _normalize(Y: np.ndarray, normalizer: str) -> np.ndarray:
 # Randomized range finder and compression (Section 3.1, Algorithm 1)
 
 def sketch_width(k: int, p: int, I: int) -> int:
-    """l_n = min(k + p, I_n) (Algorithm 1 step 3, clamped to the mode size)."""
+    """l_n = min(k + p, I_n) (Algorithm 1's oversampled width, clamped to the mode size)."""
     return min(int(k) + int(p), int(I))
 
 
@@ -158,8 +160,8 @@ TEST_MATRICES = ("gaussian", "uniform", "halton", "columns")
 
 
 def test_matrix(kind: str, seed: int, n: int, batch: int, J: int, l: int) -> np.ndarray:
-    """The J x l test matrix Omega of mode n (Algorithm 1 step 5): Gaussian
-    (Section 3.1), uniform (the rand of step 5 and the remark after
+    """The J x l test matrix Omega of mode n (Algorithm 1's test-matrix draw): Gaussian
+    (Section 3.1), uniform (the rand of that draw and the remark after
     Algorithm 1), quasi-random Halton (the note in Section 3.1), or the
     selection of l random columns (the remark after Algorithm 1), as the
     0/1 matrix picking them."""
@@ -179,12 +181,12 @@ def test_matrix(kind: str, seed: int, n: int, batch: int, J: int, l: int) -> np.
 
 def range_finder(T: np.ndarray, n: int, l: int, q: int, seed: int,
                  batch: int = 0, normalizer: str = "qr", test: str = "gaussian"):
-    """Basis Q_n of the mode-n range of T (Algorithm 1 steps 4-12).
+    """Basis Q_n of the mode-n range of T (Algorithm 1, from the sketch to the final QR).
 
     Omega is the J x l test matrix of mode n (Gaussian unless ``test`` says
     otherwise); the sketch Y = T_(n) Omega (eq. sampleMatrix) goes through q
     normalised power iterations  Q~ = nrm(Y),  Z = nrm(T_(n)^T Q~),
-    Y = T_(n) Z  (eq. IMPsampleMatrix, Algorithm 1 steps 7-11), then
+    Y = T_(n) Z  (eq. IMPsampleMatrix, Algorithm 1's power iterations), then
     Q_n = qr(Y).
     """
     Tn = unfold(T, n)
@@ -254,7 +256,7 @@ def compress(X: np.ndarray, k: int, p: int = 10, q: int = 2, seed: int = 0,
 # CP-ALS on the core (Section 3.2.1, Algorithm 2)
 
 def eig_init(B: np.ndarray, R: int, n: int) -> np.ndarray:
-    """Leading R eigenvectors of B_(n) B_(n)^T (Algorithm 2 step 2),
+    """Leading R eigenvectors of B_(n) B_(n)^T (Algorithm 2's initialisation),
     ordered by decreasing eigenvalue; each column's largest-magnitude entry
     (first index on ties) is made positive."""
     Bn = unfold(B, n)
@@ -269,7 +271,7 @@ def eig_init(B: np.ndarray, R: int, n: int) -> np.ndarray:
 
 def mttkrp(B: np.ndarray, factors: Sequence[np.ndarray], n: int) -> np.ndarray:
     """B_(n) times the Khatri-Rao product of all factors except n
-    (the first factor of the least-squares updates, Algorithm 2 steps 4/6/8)."""
+    (the first factor of the least-squares updates of Algorithm 2)."""
     others = [factors[m] for m in range(B.ndim) if m != n]
     return unfold(B, n) @ khatri_rao(others)
 
@@ -324,7 +326,7 @@ class ALSResult:
 
 def als(B: np.ndarray, R: int, max_iters: int, tol: float = 0.0,
         normX2: Optional[float] = None, init: Optional[Sequence[np.ndarray]] = None) -> ALSResult:
-    """CP-ALS on B (Algorithm 2 steps 2-11).
+    """CP-ALS on B (Algorithm 2: initialisation and sweeps).
 
     Sweep: for n = 1..N, Ã_n = B_(n) KR(Ã_{m != n}) (*_{m != n} Ã_m^T Ã_m)^+,
     then column-normalise (modes 1..N-1) or split off lambda (mode N).
@@ -407,22 +409,22 @@ def bcd_fit(B: np.ndarray, factors: Sequence[np.ndarray], lam: np.ndarray, r: in
 
 def bcd(B: np.ndarray, R: int, max_iters: int, tol: float = 0.0,
         normX2: Optional[float] = None, init: Optional[Sequence[np.ndarray]] = None) -> BCDResult:
-    """Rank-one block coordinate descent on B (Algorithm 3 steps 2-15).
+    """Rank-one block coordinate descent on B (Algorithm 3: initialisation and rank-one sweeps).
 
     The components are found one after another.  For component r the
-    residual is Y = B - sum_{s<r} lam_s a_s^(0) o ... o a_s^(N-1) (step 14),
+    residual is Y = B - sum_{s<r} lam_s a_s^(0) o ... o a_s^(N-1) (the residual update),
     and the sweeps update its blocks in mode order:
         a_r^(n) = Y_(n) (KR_{m != n} a_r^(m)) / prod_{m != n} <a_r^(m), a_r^(m)>
-    (steps 6, 8, 10: the least-squares update of one block, the
+    (the rank-one updates: the least-squares update of one block, the
     pseudo-inverse of the scalar Gram product), scaled to unit norm for
-    n < N-1 and split into lam_r and a unit vector for n = N-1 (steps 7, 9,
+    n < N-1 and split into lam_r and a unit vector for n = N-1 (the normalisations
     11, 12).  Y is never formed (the remark before Algorithm 3): by
     multilinearity
         Y_(n) (KR a_r) = B_(n) (KR a_r)
                          - sum_{s<r} lam_s a_s^(n) prod_{m != n} <a_s^(m), a_r^(m)>.
-    Starting vectors (step 2): column r of the leading eigenvectors of
+    Starting vectors (the initialisation): column r of the leading eigenvectors of
     B_(n) B_(n)^T for modes 1..N-1; mode 0 is updated first.
-    Stopping (step 13): after sweep j >= 2 of a component once the fit
+    Stopping (the per-component convergence test): after sweep j >= 2 of a component once the fit
     (``bcd_fit`` of components 0..r) changes by less than tol; tol = 0 runs
     exactly max_iters sweeps per component.
     """
@@ -473,7 +475,7 @@ def bcd(B: np.ndarray, R: int, max_iters: int, tol: float = 0.0,
 
 
 def finalize(lam: np.ndarray, factors: Sequence[np.ndarray]):
-    """Algorithm 2 step 13: re-normalise the columns, fold the norms into
+    """Algorithm 2's final renormalisation: re-normalise the columns, fold the norms into
     lambda, sort by lambda (descending) and fix signs (largest-magnitude
     entry positive in modes 1..N-1, sign pushed into mode N)."""
     A = [np.array(f, dtype=np.float64) for f in factors]
@@ -496,8 +498,8 @@ def finalize(lam: np.ndarray, factors: Sequence[np.ndarray]):
 
 
 def expand(Q: Sequence[np.ndarray], factors: Sequence[np.ndarray], lam: np.ndarray):
-    """Back-projection A_n = Q_n Ã_n (eq. qbs, Algorithm 2 step 12)
-    followed by the renormalisation of step 13."""
+    """Back-projection A_n = Q_n Ã_n (eq. qbs, Algorithm 2's factor recovery)
+    followed by the final renormalisation."""
     return finalize(lam, [Qn @ An for Qn, An in zip(Q, factors)])
 
 
@@ -533,8 +535,8 @@ def rcp_bcd(X: np.ndarray, R: int, p: int = 10, q: int = 2, max_iters: int = 50,
             tol: float = 0.0, seed: int = 0, scheme: str = "sequential",
             normalizer: str = "qr", batch: int = 0) -> RCPResult:
     """Randomized CP via block coordinate descent (Algorithm 3): the same
-    compression as ``rcp_als`` (step 1), ``bcd`` on the core (steps 2-15),
-    back-projection and renormalisation (steps 16-17)."""
+    compression as ``rcp_als``, ``bcd`` on the core (the rank-one sweeps),
+    back-projection and renormalisation (Algorithm 3's factor recovery)."""
     X = np.asarray(X, dtype=np.float64)
     normX2 = float(np.dot(X.ravel(), X.ravel()))
     comp = compress(X, R, p, q, seed, batch, scheme, normalizer)

@@ -114,7 +114,7 @@ class Plan:
 
     # -- entry points ------------------------------------------------------------
     def sketch(self, T, mode: int, cur_dims: Optional[Sequence[int]] = None):
-        """Orthonormal basis Q_n (I_n x l) of mode ``mode`` (Algorithm 1 steps 3-12)."""
+        """Orthonormal basis Q_n (I_n x l) of mode ``mode`` (Algorithm 1's range finder)."""
         _f32(T, "T")
         cur = list(T.shape) if cur_dims is None else [int(d) for d in cur_dims]
         l = sketch_width(self.k, self.p_modes[mode], cur[mode])
@@ -125,7 +125,7 @@ class Plan:
         return Q
 
     def compress(self, T, mode: int, Q):
-        """T x_mode Q^T (Algorithm 1 step 13)."""
+        """T x_mode Q^T (Algorithm 1's projection)."""
         _f32(T, "T")
         _f32(Q, "Q")
         cur = list(T.shape)
@@ -147,7 +147,7 @@ class Plan:
         return out
 
     def als(self, core, normX2=None, init: Optional[List] = None):
-        """CP-ALS on the core (Algorithm 2 steps 2-11): (factors, lambda, info buffer).
+        """CP-ALS on the core (Algorithm 2): (factors, lambda, info buffer).
 
         init: starting factors (l_n x R float32 CUDA tensors, one per mode; the
         first is not read) instead of the eigenvector start (warm start)."""
@@ -179,7 +179,7 @@ class Plan:
         return At, lam, info
 
     def bcd(self, core, normX2=None, init: Optional[List] = None):
-        """Block coordinate descent on the core (Algorithm 3 steps 2-15):
+        """Block coordinate descent on the core (Algorithm 3):
         (factors, lambda, info buffer); arguments as ``als``."""
         return self._core_solver(self.lib.rcp_bcd, "rcp_bcd", core, normX2, init)
 
@@ -219,7 +219,7 @@ class Plan:
         return int(v.value)
 
     def expand(self, Q: List, At: List, lam):
-        """A_n = Q_n Ã_n and the final renormalisation (eq. qbs, Algorithm 2 steps 12-13)."""
+        """A_n = Q_n Ã_n and the final renormalisation (eq. qbs, Algorithm 2's factor recovery and renormalisation)."""
         A = [self._empty((self.dims[n], self.R)) for n in range(self.N)]
         lam_out = self._empty((self.R,))
         _lib.check(self.lib.rcp_expand(self.handle, _lib.ptr_array([q.data_ptr() for q in Q]),

@@ -1,6 +1,6 @@
 // Device building blocks shared by the core solvers (CP-ALS, Algorithm 2,
 // and block coordinate descent, Algorithm 3): launch and LDS constants, the
-// solver context, the eigenvector start of Algorithm 2/3 step 2 (parallel
+// solver context, the eigenvector start of Algorithms 2 and 3 (parallel
 // cyclic Jacobi) and the float64 matrix-core Gram of a factor.
 #pragma once
 
@@ -175,7 +175,7 @@ __device__ __forceinline__ bool eig_leading(const AlsCtx& c, int n, double* E, d
     return ok;
 }
 
-// Algorithm 2 step 2: leading R eigenvectors of B_(n) B_(n)^T.
+// Algorithm 2's initialisation: leading R eigenvectors of B_(n) B_(n)^T.
 __device__ __forceinline__ bool eig_init(const AlsCtx& c, const float* Bg, int n, double* E,
                                          double* V) {
     const int tid = threadIdx.x;

@@ -1,4 +1,4 @@
-// CP-ALS on the compressed tensor B (Section 3.2.1, Algorithm 2 steps 2-11)
+// CP-ALS on the compressed tensor B (Section 3.2.1, Algorithm 2)
 // in one workgroup.  The core is small (l^N elements) and a sweep is a strict
 // sequence of dependent least-squares updates, so the whole sweep loop runs
 // in one persistent workgroup, with the stopping rule on the device.
@@ -612,7 +612,7 @@ __device__ __forceinline__ void wide_ctx(const AlsArgs& a, AlsCtx& c, int* sl, i
     __syncthreads();
 }
 
-// Algorithm 2 step 2 for every mode n >= 1 at once, workgroup n - 1 taking
+// Algorithm 2's initialisation for every mode n >= 1 at once, workgroup n - 1 taking
 // mode n: the leading eigenvectors of the Gram B_(n) B_(n)^T (upper triangle
 // at a.Y + (n - 1) ystride, row stride l_n rounded up to 16).  The sweep
 // state is cleared beforehand by the host; a non-converged Jacobi or-s its
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(ANT) void k_als_wide_init(AlsArgs a, int ystride) {
     if (tid == 0 && !ok) atomicOr((int*)a.state + 2, RCP_INFO_EIG_NOT_CONVERGED);
 }
 
-// Algorithm 2 steps 4-10 for mode n of one sweep from M_n in a.Y (row
+// Algorithm 2's update of mode n in one sweep from M_n in a.Y (row
 // stride a.ldy); after the last mode the fit of Section 3.3 and the
 // stopping rule, with lambda and info written every sweep.
 __global__ __launch_bounds__(ANT) void k_als_wide_step(AlsArgs a, int n) {

@@ -1,10 +1,10 @@
 // Block coordinate descent on the compressed tensor B (Section 3.2.2,
-// Algorithm 3 steps 2-15) in one persistent workgroup.
+// Algorithm 3) in one persistent workgroup.
 //
 // The components are found one after another.  For component r every sweep
 // updates its vectors a_r^(0), ..., a_r^(N-1) in mode order, each the
 // least-squares solution of its rank-one block on the residual
-// Y = B - sum_{s<r} lam_s a_s^(0) o ... o a_s^(N-1) (step 14), which is never
+// Y = B - sum_{s<r} lam_s a_s^(0) o ... o a_s^(N-1) (the residual update), which is never
 // formed: by multilinearity
 //   Y_(n) (KR_{m != n} a_r^(m)) = B_(n) (KR_{m != n} a_r^(m))
 //                                 - sum_{s<r} lam_s a_s^(n) prod_{m != n} <a_s^(m), a_r^(m)>.
@@ -14,12 +14,12 @@
 // columns in LDS, the P partial sums reduced in a fixed order); the
 // corrections use the inner products <a_s^(m), a_r^(m)>, kept per mode in
 // LDS and refreshed after each update.  The update is divided by
-// prod_{m != n} ||a_r^(m)||^2 (the scalar Gram product of steps 6, 8, 10) and
+// prod_{m != n} ||a_r^(m)||^2 (the scalar Gram product of the rank-one updates) and
 // scaled to unit norm, its norm becoming lambda_r for the last mode (steps
 // 7, 9, 11, 12).  The fit of Section 3.3 is kept for the model of components
 // 0..r: <B, Bhat> from the stored <B, rank-one s> of finished components and
 // the last mode's product, ||Bhat||^2 from the inner-product tables.
-// Starting vectors (step 2): column r of the leading eigenvectors of
+// Starting vectors (the initialisation): column r of the leading eigenvectors of
 // B_(n) B_(n)^T for modes 1..N-1 (the Jacobi start shared with CP-ALS), or
 // the caller's factors.  Factors are float64 in LDS; the core is float32
 // (in LDS when it fits, else read from global memory).

@@ -1,5 +1,5 @@
-// Back-projection of the core factors (eq. qbs, Algorithm 2 step 12) and the
-// final renormalisation (step 13): A_n = Q_n Ã_n, unit columns with the
+// Back-projection of the core factors (eq. qbs, Algorithm 2's factor recovery) and the
+// final renormalisation: A_n = Q_n Ã_n, unit columns with the
 // norms folded into lambda, components sorted by lambda (descending, stable)
 // and each column of modes 0..N-2 signed so that its largest-magnitude entry
 // (first index on ties) is positive, the sign moved into mode N-1.

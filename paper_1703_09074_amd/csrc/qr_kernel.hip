@@ -1,5 +1,5 @@
 // Orthonormal basis of a tall sketch Y (m x n, n <= 64, float64): the
-// economic QR Y = Q R with diag(R) > 0 of Algorithm 1 steps 8 and 12
+// economic QR Y = Q R with diag(R) > 0 of Algorithm 1's orthonormalisations
 // (Section 3.1), on one workgroup.
 //
 // Cholesky QR passes: G = A^T A (float64 matrix cores), G = R^T R (Cholesky),

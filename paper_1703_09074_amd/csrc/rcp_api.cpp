@@ -298,7 +298,7 @@ rcp_status reduce_y(rcp_plan_t* pl, int P, int64_t I, int LP, const double* sq, 
     return RCP_OK;
 }
 
-// Algorithm 1 steps 3-12 for one mode.  On return the padded basis is in
+// Algorithm 1's range finder for one mode.  On return the padded basis is in
 // Qt (I x LP) and, if Q != null, the basis (I x l) is in Q.
 rcp_status sketch_impl(rcp_plan_t* pl, const float* T, const int64_t* cur, int mode, float* Q,
                        double* norm_out) {
@@ -416,7 +416,7 @@ hipError_t als_wide(rcp_plan_t* pl, AlsArgs a) {
         if (e != hipSuccess) return e;
     }
     if (!a.warm) {
-        // Algorithm 2 step 2: the Grams B_(n) B_(n)^T as Y = T (T^T I) over the
+        // Algorithm 2's initialisation: the Grams B_(n) B_(n)^T as Y = T (T^T I) over the
         // GPU, side by side, then every mode's eigenvectors at once
         double* eg = pl->at<double>(L.egram);
         for (int n = 1; n < N; ++n) {
@@ -562,7 +562,7 @@ const char* rcp_status_string(rcp_status s) {
         case RCP_ERR_WORKSPACE: return "RCP_ERR_WORKSPACE: workspace missing or too small";
         case RCP_ERR_HIP: return "RCP_ERR_HIP: HIP runtime or launch failure";
         case RCP_ERR_NUMERIC: return "RCP_ERR_NUMERIC: numeric failure";
-        case RCP_ERR_UNSUPPORTED: return "RCP_ERR_UNSUPPORTED: not supported by this build";
+        case RCP_ERR_UNSUPPORTED: return "RCP_ERR_UNSUPPORTED: not supported by the library";
     }
     return "unknown rcp_status";
 }
@@ -918,7 +918,7 @@ rcp_status cp_als_impl(rcp_plan_t* pl, const float* X, const float* const* A_ini
         RCP_TRY(launch_sumsq(X, S, pl->at<double>(L.sq), nb, st + 3, pl->stream));
     }
     if (A_init == nullptr) {
-        // Algorithm 2 step 2: the leading eigenvectors of X_(n) X_(n)^T by
+        // Algorithm 2's initialisation: the leading eigenvectors of X_(n) X_(n)^T by
         // subspace iteration (Algorithm 1's power steps on an l_n-wide block)
         // and Rayleigh-Ritz on the Gram of X x_n Q_n^T
         double* eg = pl->at<double>(L.egram);
@@ -1388,7 +1388,7 @@ void batch_build_program(rcp_batch_t* b, const float* const* X, std::vector<unsi
             m.NB = m.LP / 16;
             m.g = make_geom(T[i], cur[i].data(), L.N, n);
             m.P = (int)std::max<int64_t>(1, std::min<int64_t>(pl->P, m.g.ntiles));
-            // sketch (Algorithm 1 steps 4-6), as launch_contract_out with Z == null
+            // sketch (Algorithm 1), as launch_contract_out with Z == null
             int MBv = (int)((I + 63) / 64);
             if (I <= 512 && MBv > pl->mb_cap) MBv = pl->mb_cap;
             MBv = std::max(1, std::min(8, MBv));
@@ -1463,7 +1463,7 @@ void batch_build_program(rcp_batch_t* b, const float* const* X, std::vector<unsi
         for (int i = 0; i < count; ++i)
             if (n < b->plans[i]->L.N) add_qr(i, true);
         gstep_emit(qr, GOp::QR, b->ops, blob);
-        // the mode product T x_n Q^T (Algorithm 1 step 13), float32 operands,
+        // the mode product T x_n Q^T (Algorithm 1's projection), float32 operands,
         // as compress_impl's resident-basis kernel
         for (int i = 0; i < count; ++i) {
             rcp_plan_t* pl = b->plans[i];

@@ -10,7 +10,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // Counter-based Gaussian test matrix (Section 3.1: Gaussian random vectors
-// omega_1..omega_l; Algorithm 1 step 5).  Philox4x32-10 from Salmon, Moraes,
+// omega_1..omega_l; Algorithm 1's test-matrix draw).  Philox4x32-10 from Salmon, Moraes,
 // Dror, Shaw (SC'11): ten rounds of two 32x32->64 multiplies with the
 // constants below, key bumped by the Weyl increments between rounds.
 

@@ -232,14 +232,14 @@ bool als_core_in_lds(int N, const int* l, int R);
 // The sweep state (iteration, stop flag, Grams, lambda) lives in a.state;
 // the stop flag (an int at a.state) makes every later launch return at once.
 size_t als_state_doubles(int N, int R);
-// Algorithm 2 step 2 for every mode n >= 1 at once (one workgroup per
+// Algorithm 2's initialisation for every mode n >= 1 at once (one workgroup per
 // mode) from the Grams B_(n) B_(n)^T at a.Y + (n - 1) ystride (row stride l_n
 // rounded up to 16); the sweep state's first three doubles must be zero
 hipError_t launch_als_wide_init(const AlsArgs& a, int ystride, hipStream_t s);
 // warm start: the Grams of the given factors At[1..N-1] and a fresh state
 hipError_t launch_als_wide_warm(const AlsArgs& a, hipStream_t s);
 
-// steps 4-10 for mode n from its reduced mode product in a.Y; after the
+// Algorithm 2's update of mode n from its reduced mode product in a.Y; after the
 // last mode, the fit and the stopping rule
 hipError_t launch_als_wide_step(const AlsArgs& a, int n, hipStream_t s);
 

@@ -1,5 +1,6 @@
-// Streaming contractions over the current tensor T (Algorithm 1 steps 6,
-// 9, 10 and 13), hand-written for gfx950.
+// Streaming contractions over the current tensor T (Algorithm 1: the sketch,
+// the power iterations' two products and the projection), hand-written for
+// gfx950.
 //
 // T is C-order with dims (I_0..I_{N-1}); around mode n it is viewed as a
 // 3-D array (L, I, Rr): L = prod of dims before n, Rr = prod after n.  The
@@ -320,7 +321,7 @@ __device__ __forceinline__ void store_partial(const f32x4 (&acc)[MHalf<MB>::v][N
 //                  (power iteration with a stored Z),
 //   WK = kWOmega:  the Gaussian test matrix, generated in registers,
 //   WK = kWKr:     the Khatri-Rao product of the other modes' factors (the
-//                  mode product of CP-ALS, Algorithm 2 steps 4/6/8), formed
+//                  mode product of CP-ALS, Algorithm 2's factor updates), formed
 //                  from a packed copy of the factors in LDS,
 //   WK = kWKrG:    the same product with the factor rows read from global
 //                  memory (through the caches): the full tensor's factors,
@@ -513,7 +514,7 @@ __global__ __launch_bounds__(NTS) void k_contract_out(StreamGeom g, int l, const
 // ---------------------------------------------------------------------------
 // power_fused: partial Y = T_(n) (T_(n)^T Qt) in one pass over T.  Each tile
 // (all I rows, I <= 64*MB) is held in LDS: first z = tile^T Qt (JT x LP),
-// then Y += tile z.  The normalisation of Z in Algorithm 1 step 9 is an
+// then Y += tile z.  The normalisation of Z in Algorithm 1's power iteration is an
 // invertible upper-triangular right factor, which the QR of the next sketch
 // absorbs, so it is not applied.
 
@@ -604,7 +605,7 @@ __global__ __launch_bounds__(NTS) void k_power_fused_grp(const PowerDesc* d) {
 
 // ---------------------------------------------------------------------------
 // contract_in: out[a, c, b] = sum_i Q[i, c] T[a, i, b] for c < lout
-// (Algorithm 1 step 13, T x_n Q^T; also Z = T_(n)^T Qt for the two-pass
+// (Algorithm 1's projection, T x_n Q^T; also Z = T_(n)^T Qt for the two-pass
 // power iteration).  Rows are streamed in chunks of IC through LDS.
 
 constexpr int IC = 128;

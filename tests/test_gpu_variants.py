@@ -1,5 +1,5 @@
 """Algorithm 1 variants on the GPU against the float64 oracle on the same
-inputs: the uniform and Halton test matrices (step 5; the note in Section 3.1
+inputs: the uniform and Halton test matrices (Algorithm 1's draw; the note in Section 3.1
 and the remark after Algorithm 1), column selection in place of the product
 (the same remark), a subset of compressed modes and per-mode oversampling.
 

@@ -193,7 +193,7 @@ def test_solve_gram_singular_falls_back_to_pinv():
 
 
 def test_eig_init_spans_leading_singular_subspace():
-    """Algorithm 2 step 2: the initial factor of mode n spans the leading R
+    """Algorithm 2's initialisation: the initial factor of mode n spans the leading R
     left singular vectors of B_(n) (checked against a library SVD on a core
     with a known, well separated spectrum), with the sign rule applied."""
     rng = np.random.default_rng(31)

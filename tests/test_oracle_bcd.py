@@ -3,7 +3,7 @@ against what the paper and the mathematics fix:
 
   * each block update is the least-squares solution of the rank-one
     subproblem on the deflated residual: brute force builds the residual
-    tensor explicitly (step 14) and solves the subproblem with lstsq on the
+    tensor explicitly (the residual update) and solves the subproblem with lstsq on the
     explicit Khatri-Rao column;
   * with one component the method is CP-ALS of rank one;
   * an orthogonally decomposable noise-free tensor is recovered exactly,

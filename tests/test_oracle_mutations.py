@@ -132,7 +132,7 @@ def test_dropped_power_iteration_is_caught(monkeypatch):
 
 def test_sequential_scheme_sketching_x_is_caught(monkeypatch):
     """The sequential scheme taking every sketch from X instead of the tensor
-    already compressed in the earlier modes (Algorithm 1 step 13)."""
+    already compressed in the earlier modes (Algorithm 1's projection)."""
     from tests import test_oracle_power_sequential as tps
     orig = rcp.compress
 
@@ -158,7 +158,7 @@ def test_sequential_scheme_sketching_x_is_caught(monkeypatch):
 
 def test_missing_column_normalisation_is_caught(monkeypatch):
     """ALS and the renormalisation leaving the factor columns unscaled
-    (Algorithm 2 steps 5/7/9 and 13)."""
+    (Algorithm 2's normalisations and final renormalisation)."""
     monkeypatch.setattr(rcp, "_scale_columns", lambda A, nu: A)
     with pytest.raises(AssertionError):
         trcp.test_exact_recovery_noise_free()

@@ -1,6 +1,6 @@
 """Exact pins of two parts of Algorithm 1 that inequality checks cannot hold.
 
-Power iterations (eq. IMPsampleMatrix, Algorithm 1 steps 7-11).  The q
+Power iterations (eq. IMPsampleMatrix, Algorithm 1's power iterations).  The q
 normalised power iterations compute, in exact arithmetic, an orthonormal
 basis of span((T_(n) T_(n)^T)^q T_(n) Omega_n); every normalisation between
 the steps is an invertible right factor and leaves the span unchanged.  With
@@ -10,7 +10,7 @@ singular values lie in [1, 2] this matrix is well conditioned for q <= 3, so
 the oracle's basis must agree with it to principal angles of ~1e-12, while
 the span for q - 1 iterations is measurably different.
 
-Sequential scheme (Algorithm 1 step 13: the tensor is replaced by its
+Sequential scheme (Algorithm 1's projection: the tensor is replaced by its
 compressed form before the next mode).  Mode n is sketched on the tensor
 already compressed in modes 0..n-1: its input has dims
 (l_0, .., l_{n-1}, I_n, .., I_{N-1}), its test matrix has J_n = product of

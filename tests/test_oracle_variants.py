@@ -1,5 +1,5 @@
 """Pins of the oracle's test-matrix and parameter variants (the note on
-quasi-random numbers in Section 3.1, Algorithm 1 step 5's rand and the
+quasi-random numbers in Section 3.1, Algorithm 1's rand and the
 remarks after Algorithm 1: uniform test matrices, randomly selected
 columns, a chosen subset of modes and per-mode oversampling)."""
 from fractions import Fraction
