@@ -289,7 +289,7 @@ __device__ __forceinline__ int invert_wave(const double* A, int lda, int pbs, in
     for (int k = 0; k < NP; ++k) {
         double sk[NP];
         sk[0] = readlane_f64(col[0], k);
-        const double u = col[0] / sk[0];
+        const double u = div_pivot(col[0], sk[0]);
 #pragma unroll
         for (int i = 1; i < NP; ++i) sk[i] = readlane_f64(col[i], k);
         __builtin_amdgcn_sched_barrier(0);
@@ -491,7 +491,7 @@ __device__ __forceinline__ int gj_wave(double* Aug, int ldx, int R, int W, doubl
         // broadcast per update serialises on a single register pair
         double s[RP];
         s[0] = readlane_f64(col[0], k);
-        const double u = col[0] / s[0];
+        const double u = div_pivot(col[0], s[0]);
 #pragma unroll
         for (int i = 1; i < RP; ++i) s[i] = readlane_f64(col[i], k);
         __builtin_amdgcn_sched_barrier(0);

@@ -160,7 +160,7 @@ __device__ __forceinline__ int chol_inverse_wave_s(const double* G, int ldg, dou
         // pivot column first, into distinct scalar registers, then the updates
         double s[NP];
         s[0] = readlane_f64(col[0], k);
-        const double u = col[0] / s[0];
+        const double u = div_pivot(col[0], s[0]);
 #pragma unroll
         for (int i = 1; i < NP - k; ++i) s[i] = readlane_f64(col[i], k);
         __builtin_amdgcn_sched_barrier(0);

@@ -165,6 +165,21 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return t;
 }
 
+
+// x / d on the serial path of an elimination, where the IEEE division
+// sequence (about ten dependent float64 operations) is the latency: the
+// hardware reciprocal refined by two Newton steps, then one multiply; within
+// about an ulp of the rounded quotient for finite nonzero d (a zero or NaN d
+// gives NaN, which the callers' pivot tests reject).
+__device__ __forceinline__ double div_pivot(double x, double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    return x * r;
+}
+
 // a double of lane `lane` (wave-uniform) to every lane of the wavefront
 __device__ __forceinline__ double readlane_f64(double x, int lane) {
     const long long b = __double_as_longlong(x);
