@@ -1145,6 +1145,7 @@ struct rcp_batch_t {
     hipEvent_t join[kBatchStreams] = {};
     std::vector<rcp_plan_t*> plans;
     std::vector<AlsArgs> h_als;           // per-problem arguments, outputs as last bound
+    std::vector<int> als_order;           // device table order: estimated ALS work, largest first
     std::vector<ExpandArgs> h_exp;
     AlsArgs* pin_als = nullptr;           // pinned staging of the argument tables
     ExpandArgs* pin_exp = nullptr;
@@ -1304,7 +1305,7 @@ rcp_status batch_bind_outputs(rcp_batch_t* b, float* const* const* A, float* con
         b->h_exp[i].lambda_out = lambda[i];
         for (int n = 0; n < b->h_exp[i].N; ++n) b->h_exp[i].A[n] = A[i][n];
     }
-    std::memcpy(b->pin_als, b->h_als.data(), b->count * sizeof(AlsArgs));
+    for (int j = 0; j < b->count; ++j) b->pin_als[j] = b->h_als[b->als_order[j]];
     std::memcpy(b->pin_exp, b->h_exp.data(), b->count * sizeof(ExpandArgs));
     RCP_TRY(hipMemcpyAsync(b->d_als, b->pin_als, b->count * sizeof(AlsArgs), hipMemcpyHostToDevice,
                            b->stream));
@@ -1624,6 +1625,23 @@ rcp_status rcp_batch_init(rcp_batch* batch, const rcp_problem* probs, int32_t co
         const float* core = core_location(pl);
         b->h_als.push_back(core_als_args(pl, core, nullptr));
         b->h_exp.push_back(core_expand_args(pl, nullptr, nullptr));
+    }
+    // The ALS launch runs one workgroup per problem, about two problems per
+    // CU: the device table lists them by estimated work (core size x R x
+    // sweeps), largest first, so the longest ones start in the first wave
+    // (longest-processing-time order).  Each entry carries its own buffers.
+    {
+        std::vector<double> work(count);
+        for (int i = 0; i < count; ++i) {
+            const AlsArgs& a = b->h_als[i];
+            double S = 1.0;
+            for (int n = 0; n < a.N; ++n) S *= a.l[n];
+            work[i] = S * a.R * a.max_iters;
+        }
+        b->als_order.resize(count);
+        for (int i = 0; i < count; ++i) b->als_order[i] = i;
+        std::stable_sort(b->als_order.begin(), b->als_order.end(),
+                         [&](int x, int y) { return work[x] > work[y]; });
     }
     // the plans' status words are cleared on the side streams: the batch
     // stream waits for that before its first use of the workspace
