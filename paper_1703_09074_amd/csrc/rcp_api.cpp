@@ -1323,7 +1323,7 @@ rcp_status batch_bind_outputs(rcp_batch_t* b, float* const* const* A, float* con
 extern "C++" {
 template <typename D>
 struct GStep {
-    struct Item { int NB, MB, prec; bool caseB, fused; size_t lds; D d; int gx, gy; };
+    struct Item { int NB, MB, prec; bool caseB, fused; size_t lds; D d; int gx, gy; double work = 0.0; };
     std::vector<Item> items;
 };
 
@@ -1337,12 +1337,22 @@ void gstep_emit(GStep<D>& st, GOp::Kind kind, std::vector<GOp>& ops, std::vector
         op.kind = kind;
         op.NB = a.NB; op.MB = a.MB; op.prec = a.prec; op.caseB = a.caseB; op.fused = a.fused;
         op.off = blob.size();
+        // the launch's descriptors by work per workgroup, largest first:
+        // workgroups dispatch in descriptor (blockIdx.z) order, so the
+        // longest start first; each problem's arithmetic is unchanged
+        std::vector<size_t> members;
         for (size_t j = i; j < st.items.size(); ++j) {
             const auto& c = st.items[j];
             if (used[j] || c.NB != a.NB || c.MB != a.MB || c.prec != a.prec || c.caseB != a.caseB ||
                 c.fused != a.fused)
                 continue;
             used[j] = true;
+            members.push_back(j);
+        }
+        std::stable_sort(members.begin(), members.end(),
+                         [&](size_t x, size_t y) { return st.items[x].work > st.items[y].work; });
+        for (size_t j : members) {
+            const auto& c = st.items[j];
             const unsigned char* src = (const unsigned char*)&c.d;
             blob.insert(blob.end(), src, src + sizeof(D));
             ++op.count;
@@ -1405,7 +1415,8 @@ void batch_build_program(rcp_batch_t* b, const float* const* X, std::vector<unsi
             d.l = m.l;
             d.P = m.P;
             d.nIB = nIB;
-            sk.items.push_back({m.NB, MBv, pl->prob.precision, m.g.caseB != 0, false, 0, d, m.P, nIB});
+            sk.items.push_back({m.NB, MBv, pl->prob.precision, m.g.caseB != 0, false, 0, d, m.P, nIB,
+                                (double)((m.g.ntiles + m.P - 1) / m.P) * (double)(64 * MBv)});
             ReduceDesc r{};
             r.part = pl->at<float>(L.part);
             r.Y = pl->at<double>(L.y64);
@@ -1433,7 +1444,8 @@ void batch_build_program(rcp_batch_t* b, const float* const* X, std::vector<unsi
             d.Qout = final_basis ? pl->at<float>(L.qb[n]) : nullptr;
             d.second_pass = final_basis ? 1 : 0;
             d.status = pl->status_word();
-            qr.items.push_back({(m.l + 15) >> 4, 0, 0, false, false, qr_group_lds(d.m, d.n), d, 1, 1});
+            qr.items.push_back({(m.l + 15) >> 4, 0, 0, false, false, qr_group_lds(d.m, d.n), d, 1, 1,
+                                (double)d.m * d.n * d.n});
         };
         for (int it = 0; it < qmax; ++it) {
             for (int i = 0; i < count; ++i) {
@@ -1448,7 +1460,8 @@ void batch_build_program(rcp_batch_t* b, const float* const* X, std::vector<unsi
                 d.out = nullptr;
                 d.P = m.P;
                 pw.items.push_back({m.NB, (int)((cur[i][n] + 63) / 64), pl->prob.precision,
-                                    m.g.caseB != 0, true, 0, d, m.P, 1});
+                                    m.g.caseB != 0, true, 0, d, m.P, 1,
+                                    (double)((m.g.ntiles + m.P - 1) / m.P) * (double)cur[i][n]});
                 ReduceDesc r{};
                 r.part = pl->at<float>(pl->L.part);
                 r.Y = pl->at<double>(pl->L.y64);
@@ -1479,7 +1492,7 @@ void batch_build_program(rcp_batch_t* b, const float* const* X, std::vector<unsi
             d.P = m.P;
             d.lout = m.l;
             pw.items.push_back({m.NB, (int)((cur[i][n] + 63) / 64), RCP_PREC_FP32, m.g.caseB != 0, false,
-                                0, d, m.P, 1});
+                                0, d, m.P, 1, (double)((m.g.ntiles + m.P - 1) / m.P) * (double)cur[i][n]});
             cur[i][n] = m.l;
             T[i] = out;
             ++comp[i];
